@@ -1,0 +1,158 @@
+/*
+ * mindist.h -- C ABI of the MI355X (gfx950) minimum-distance library.
+ *
+ * The library computes the minimum distance d of a binary linear code with
+ * the Brouwer-Zimmerman method as described by Hernando, Igual and
+ * Quintana-Orti, "Fast Algorithms for the Computation of the Minimum
+ * Distance of a Random Linear Code": Section 2 (definition of d, information
+ * sets, systematic matrices Gamma_j, Algorithm 1 with its upper bound U and
+ * lower bound L) and Section 3 (enumerating every g-subset of the rows of a
+ * Gamma_j with few row additions; Algorithm 5's left/right split with saved
+ * right sums is the scheme the GPU kernel follows).
+ *
+ * Conventions for every entry point:
+ *   - a matrix G is k rows of W = ceil(n/64) uint64 words, row-major; column
+ *     c is bit (c % 64) of word (c / 64); bits >= n must be zero;
+ *   - 1 <= k < n <= 512 (Section 2 assumes n > k);
+ *   - all pointers are host pointers unless stated; inputs are copied, the
+ *     caller keeps ownership of everything it passes;
+ *   - return value 0 on success, a negative MINDIST_E_* code otherwise; no
+ *     exception crosses the ABI; mindist_last_error() gives a per-thread
+ *     message for the last failure;
+ *   - a context is not thread-safe; separate contexts are independent.
+ */
+#ifndef MINDIST_H
+#define MINDIST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MINDIST_OK            0
+#define MINDIST_E_ARG        -1   /* null pointer, n/k out of range, nonzero padding bits */
+#define MINDIST_E_RANK       -2   /* rank(G) < k */
+#define MINDIST_E_NOMEM      -3   /* host or device allocation failed */
+#define MINDIST_E_HIP        -4   /* HIP runtime error (no device, launch failure, ...) */
+#define MINDIST_E_LIMIT      -5   /* a pair whose C(k,w) exceeds 2^63, or level > 64 */
+#define MINDIST_E_CANCELLED  -6   /* stopped by MINDIST_OPT_CANCEL_AFTER_CHUNKS */
+#define MINDIST_E_TIMEOUT    -7   /* MINDIST_OPT_DEADLINE_MS elapsed */
+#define MINDIST_E_STATE      -8   /* call out of order (e.g. results before a run) */
+
+#define MINDIST_MAX_N      512
+#define MINDIST_MAX_WORDS  8
+#define MINDIST_MAX_LEVEL  64
+
+/* ---- options (mindist_set_option keys) ------------------------------- */
+/* Termination granularity.  Algorithm 1 raises L once per level; Section 2
+ * notes it may be raised after every Gamma_j.  0 = after every Gamma_j
+ * (default), 1 = once per level (literal Algorithm 1). */
+#define MINDIST_OPT_TERM             1
+/* 1 (default) = stop a pair as soon as U <= L before that pair (only with
+ * per-pair termination); the visited pairs, d and every pair minimum are
+ * unchanged, only the executed count of the final pair shrinks. */
+#define MINDIST_OPT_MIDPAIR_EXIT     2
+/* 0 (default) = enumerate the partial (rank k_m < k) set at every level as
+ * Algorithm 1's loop over j = 1..m does; 1 = drop it and its bound term. */
+#define MINDIST_OPT_PARTIAL          3
+/* 1 = also accumulate the sum of weights of every pair (checkable against a
+ * closed form); slower.  0 (default) off. */
+#define MINDIST_OPT_VERIFY           4
+/* HIP stream (hipStream_t cast to int64) for all device work of this
+ * context; 0 = a private stream created by the library (default). */
+#define MINDIST_OPT_STREAM           5
+/* wall-clock limit of one run in ms; 0 = none.  Checked between pairs. */
+#define MINDIST_OPT_DEADLINE_MS      6
+/* kernel shape: codewords per lane-item tile (right tile length). */
+#define MINDIST_OPT_TILE_T           7
+/* kernel shape: resident workgroups per CU for the enumeration launch. */
+#define MINDIST_OPT_BLOCKS_PER_CU    8
+/* 1 = time every enumeration launch with HIP events (seconds_enum). */
+#define MINDIST_OPT_PROFILE          9
+/* testing: stop with MINDIST_E_CANCELLED once this many chunks of the run
+ * have been claimed; 0 = off. */
+#define MINDIST_OPT_CANCEL_AFTER_CHUNKS 10
+/* cap on the saved right-sum table of one (Gamma_j, size) in MiB
+ * (default 256). */
+#define MINDIST_OPT_TABLE_MIB        11
+
+typedef struct mindist_ctx mindist_ctx;
+
+typedef struct mindist_result {
+    int32_t  d;               /* minimum distance (Algorithm 1's returned U) */
+    int32_t  n, k;
+    int32_t  m_full;          /* number of disjoint full-rank information sets */
+    int32_t  k_partial;       /* rank of the partial set (0 if none) */
+    int32_t  n_gamma;         /* Gamma matrices enumerated (m_full [+1]) */
+    int32_t  w_last, j_last;  /* last visited pair (level w, set j, 0-based j) */
+    int32_t  L_final;         /* lower bound when the run stopped */
+    int32_t  U_found;         /* least weight found (n+1 if none) */
+    int32_t  pairs_visited;
+    int32_t  exited_midpair;  /* 1 if the last pair was cut short */
+    int32_t  witness_j, witness_w;   /* pair of the witness */
+    uint64_t witness[MINDIST_MAX_WORDS];       /* codeword of weight d, layout of G */
+    uint64_t witness_rows[MINDIST_MAX_WORDS];  /* bit r set = row r of Gamma_{witness_j} used */
+    uint64_t executed_total;  /* codewords evaluated on the GPU */
+    uint64_t canonical_total; /* sum of C(k,w) over visited pairs */
+    double   seconds_total;   /* wall clock of mindist_run (host preprocessing is in create) */
+    double   seconds_enum;    /* summed enumeration-kernel time (HIP events, PROFILE=1) */
+    int32_t  enum_launches;   /* enumeration kernel launches in this run */
+    int32_t  reserved;
+} mindist_result;
+
+/* one visited pair (Algorithm 1, one iteration of the inner loop) */
+typedef struct mindist_pair {
+    int32_t  j, w;            /* set index (0-based, partial set last) and level */
+    int32_t  L_before, L_after, U_after;
+    int32_t  pair_min;        /* least weight over the pair */
+    uint64_t count;           /* C(k,w): combinations the pair covers */
+    uint64_t executed;        /* combinations evaluated (< count only if cut short) */
+    uint64_t wsum;            /* sum of weights (VERIFY=1 only, else 0) */
+    double   ms;              /* kernel time of the pair (PROFILE=1 only) */
+    int32_t  dwords;          /* 32-bit words carried per codeword by the kernel */
+    int32_t  split_a;         /* rows taken per lane item (the rest come from the table) */
+} mindist_pair;
+
+/* Section 2 and Algorithm 1 preprocessing: validate and copy G, greedy
+ * disjoint information sets over the columns in ascending order, the
+ * reduced echelon Gamma_j of each set, and the device copies the
+ * enumeration needs.  Needs a HIP device.  *out is owned by the caller and
+ * released with mindist_destroy. */
+int mindist_create(const uint64_t *G, int n, int k, mindist_ctx **out);
+
+/* set an option (MINDIST_OPT_*) before mindist_run */
+int mindist_set_option(mindist_ctx *ctx, int key, int64_t value);
+
+/* partition summary of a created context */
+int mindist_info(const mindist_ctx *ctx, int *m_full, int *k_partial, int *n_gamma);
+
+/* Algorithm 1: raise the level until L >= U.  Blocking.  `out` is caller-
+ * owned.  May be called again (results are recomputed from scratch). */
+int mindist_run(mindist_ctx *ctx, mindist_result *out);
+
+/* the visited pairs of the last run, in visiting order */
+int mindist_get_pairs(const mindist_ctx *ctx, mindist_pair *out, int cap, int *n_out);
+
+/* NULL-safe */
+void mindist_destroy(mindist_ctx *ctx);
+
+const char *mindist_last_error(void);
+
+/* Host-only planning (no device needed): the greedy partition and the
+ * systematic matrices.  sets: n ints (full sets of k columns each, then the
+ * partial set); gammas: n_gamma * k * W words (full sets first, partial last;
+ * pass NULL to skip).  Returns MINDIST_OK or an error. */
+int mindist_plan(const uint64_t *G, int n, int k, int *sets, int *m_full,
+                 int *k_partial, uint64_t *gammas);
+
+/* Host-only: the lower bound after pair (j, w) under per-Gamma termination
+ * (Section 2): sum over sets i <= j of f_i(w) plus over i > j of f_i(w-1),
+ * f_full(h) = h+1, f_partial(h) = max(0, h+1-(k-k_m)). */
+int mindist_bound_after(int k, int m_full, int k_partial, int include_partial,
+                        int j, int w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MINDIST_H */

@@ -1,0 +1,214 @@
+"""Python binding of libmindist.so (the MI355X minimum-distance library).
+
+Argument marshalling only: every step of the computation runs in the C++
+host code and the HIP kernels of the library.  The binding raises if the
+library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmindist.so")
+
+E_NAMES = {0: "OK", -1: "E_ARG", -2: "E_RANK", -3: "E_NOMEM", -4: "E_HIP", -5: "E_LIMIT",
+           -6: "E_CANCELLED", -7: "E_TIMEOUT", -8: "E_STATE"}
+
+OPT = {"term": 1, "midpair_exit": 2, "partial": 3, "verify": 4, "stream": 5,
+       "deadline_ms": 6, "tile_t": 7, "blocks_per_cu": 8, "profile": 9,
+       "cancel_after_chunks": 10, "table_mib": 11}
+
+MAX_WORDS = 8
+
+
+class MindistError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{E_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Result(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n", C.c_int32), ("k", C.c_int32), ("m_full", C.c_int32),
+                ("k_partial", C.c_int32), ("n_gamma", C.c_int32), ("w_last", C.c_int32),
+                ("j_last", C.c_int32), ("L_final", C.c_int32), ("U_found", C.c_int32),
+                ("pairs_visited", C.c_int32), ("exited_midpair", C.c_int32),
+                ("witness_j", C.c_int32), ("witness_w", C.c_int32),
+                ("witness", C.c_uint64 * MAX_WORDS), ("witness_rows", C.c_uint64 * MAX_WORDS),
+                ("executed_total", C.c_uint64), ("canonical_total", C.c_uint64),
+                ("seconds_total", C.c_double), ("seconds_enum", C.c_double),
+                ("enum_launches", C.c_int32), ("reserved", C.c_int32)]
+
+    def to_dict(self):
+        W = (self.n + 63) // 64
+        return {
+            "d": self.d, "n": self.n, "k": self.k, "m_full": self.m_full,
+            "k_partial": self.k_partial, "n_gamma": self.n_gamma, "w_last": self.w_last,
+            "j_last": self.j_last, "L_final": self.L_final, "U_found": self.U_found,
+            "pairs_visited": self.pairs_visited, "exited_midpair": self.exited_midpair,
+            "witness_pair": (self.witness_j, self.witness_w),
+            "witness": np.array(self.witness[:W], dtype=np.uint64),
+            "witness_rows": [r for r in range(self.k)
+                             if (self.witness_rows[r // 64] >> (r % 64)) & 1],
+            "executed_total": self.executed_total, "canonical_total": self.canonical_total,
+            "seconds_total": self.seconds_total, "seconds_enum": self.seconds_enum,
+            "enum_launches": self.enum_launches,
+        }
+
+
+class Pair(C.Structure):
+    _fields_ = [("j", C.c_int32), ("w", C.c_int32), ("L_before", C.c_int32),
+                ("L_after", C.c_int32), ("U_after", C.c_int32), ("pair_min", C.c_int32),
+                ("count", C.c_uint64), ("executed", C.c_uint64), ("wsum", C.c_uint64),
+                ("ms", C.c_double), ("dwords", C.c_int32), ("split_a", C.c_int32)]
+
+    def to_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("tile_t", C.c_int32), ("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32),
+                ("profile", C.c_int32), ("stream", C.c_int64), ("seconds_kernel", C.c_double),
+                ("seconds_total", C.c_double), ("executed_total", C.c_uint64)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("max_active", C.c_int32), ("tile_t", C.c_int32), ("device_bytes", C.c_int64)]
+
+
+class ServerResult(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("result", Result), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmindist.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1603_06757_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        u64p, ip, vp = C.POINTER(C.c_uint64), C.POINTER(C.c_int), C.c_void_p
+        L.mindist_create.argtypes = [u64p, C.c_int, C.c_int, C.POINTER(vp)]
+        L.mindist_set_option.argtypes = [vp, C.c_int, C.c_int64]
+        L.mindist_info.argtypes = [vp, ip, ip, ip]
+        L.mindist_run.argtypes = [vp, C.POINTER(Result)]
+        L.mindist_get_pairs.argtypes = [vp, C.POINTER(Pair), C.c_int, ip]
+        L.mindist_destroy.argtypes = [vp]
+        L.mindist_destroy.restype = None
+        L.mindist_last_error.restype = C.c_char_p
+        L.mindist_plan.argtypes = [u64p, C.c_int, C.c_int, ip, ip, ip, u64p]
+        L.mindist_bound_after.argtypes = [C.c_int] * 6
+        if hasattr(L, "mindist_run_batch"):
+            L.mindist_run_batch.argtypes = [C.POINTER(u64p), ip, ip, C.c_int,
+                                            C.POINTER(Result), C.POINTER(BatchOpts)]
+        if hasattr(L, "mindist_server_create"):
+            L.mindist_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(vp)]
+            L.mindist_server_submit.argtypes = [vp, u64p, C.c_int, C.c_int, C.c_uint64]
+            L.mindist_server_poll.argtypes = [vp, C.POINTER(ServerResult), C.c_int, ip]
+            L.mindist_server_clock.argtypes = [vp]
+            L.mindist_server_clock.restype = C.c_double
+            L.mindist_server_destroy.argtypes = [vp]
+            L.mindist_server_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise MindistError(rc, lib().mindist_last_error().decode())
+    return rc
+
+
+def _mat(G, n, k):
+    G = np.ascontiguousarray(G, dtype=np.uint64)
+    if G.shape != (k, (n + 63) // 64):
+        raise ValueError(f"G must have shape ({k}, {(n + 63) // 64}), got {G.shape}")
+    return G
+
+
+def _u64(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint64))
+
+
+def plan(G, n: int, k: int):
+    """Host-only: (full sets, partial set, Gamma matrices) as the library builds them."""
+    G = _mat(G, n, k)
+    W = (n + 63) // 64
+    sets = np.zeros(n, dtype=np.int32)
+    mf, km = C.c_int(0), C.c_int(0)
+    gam = np.zeros(((n // k) + 1) * k * W, dtype=np.uint64)
+    _check(lib().mindist_plan(_u64(G), n, k, sets.ctypes.data_as(C.POINTER(C.c_int)),
+                              C.byref(mf), C.byref(km), _u64(gam)))
+    full = [sets[j * k:(j + 1) * k].tolist() for j in range(mf.value)]
+    part = sets[mf.value * k: mf.value * k + km.value].tolist()
+    ng = mf.value + (1 if km.value >= 1 else 0)
+    return full, part, gam[:ng * k * W].reshape(ng, k, W).copy()
+
+
+def bound_after(k, m_full, k_partial, include_partial, j, w) -> int:
+    return _check(lib().mindist_bound_after(k, m_full, k_partial, int(include_partial), j, w))
+
+
+class MinDist:
+    """One code: mindist_create / set_option / run / get_pairs / destroy."""
+
+    def __init__(self, G, n: int, k: int, **options):
+        self.n, self.k = n, k
+        self._G = _mat(G, n, k)
+        h = C.c_void_p()
+        _check(lib().mindist_create(_u64(self._G), n, k, C.byref(h)))
+        self._h = h
+        for key, v in options.items():
+            self.set_option(key, v)
+
+    def set_option(self, key: str, value: int):
+        _check(lib().mindist_set_option(self._h, OPT[key], int(value)))
+
+    def info(self):
+        mf, km, ng = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().mindist_info(self._h, C.byref(mf), C.byref(km), C.byref(ng)))
+        return mf.value, km.value, ng.value
+
+    def run(self) -> dict:
+        r = Result()
+        _check(lib().mindist_run(self._h, C.byref(r)))
+        out = r.to_dict()
+        out["pairs"] = self.pairs()
+        return out
+
+    def pairs(self):
+        cnt = C.c_int()
+        _check(lib().mindist_get_pairs(self._h, None, 0, C.byref(cnt)))
+        arr = (Pair * max(cnt.value, 1))()
+        _check(lib().mindist_get_pairs(self._h, arr, cnt.value, C.byref(cnt)))
+        return [arr[i].to_dict() for i in range(cnt.value)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mindist_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def min_distance(G, n: int, k: int, **options) -> dict:
+    with MinDist(G, n, k, **options) as m:
+        return m.run()

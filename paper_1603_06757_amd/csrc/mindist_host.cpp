@@ -1,0 +1,657 @@
+// mindist_host.cpp -- host side of the minimum-distance library: argument
+// checks, information sets, systematic matrices, the bound schedule and the
+// pair loop of Algorithm 1, witness reconstruction, and the C ABI.
+//
+// Readings of the paper (Section 2) implemented here:
+//   * information sets: greedy rounds over the unused columns in ascending
+//     order; a round that reaches k pivots is a full set, the first round
+//     that does not gives the partial set (rank k_m, possibly 0) and ends;
+//   * Gamma_j: the reduced row echelon form of G under the column order
+//     (set columns ascending, then all others ascending) -- unique, so the
+//     partial set's [[I, A], [0, B]] is canonical;
+//   * bounds: U starts at n-k+1, L at 1 (Algorithm 1); after pair (j, w),
+//     L = sum_{i<=j} f_i(w) + sum_{i>j} f_i(w-1) with f_full(h) = h+1 and
+//     f_partial(h) = max(0, h+1-(k-k_m)) ("one after each Gamma_j"), or the
+//     printed per-level update when MINDIST_OPT_TERM = 1.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mindist.h"
+#include "mindist_internal.h"
+
+using namespace md;
+
+// ---------------------------------------------------------------------------
+// errors
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(MINDIST_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char *mindist_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// binomials, saturating at UINT64_MAX
+namespace {
+
+struct Binom {
+    std::vector<uint64_t> t;   // kBinomX x kBinomT
+    Binom() : t((size_t)kBinomX * kBinomT, 0) {
+        for (int x = 0; x < kBinomX; ++x) {
+            t[(size_t)x * kBinomT] = 1;
+            for (int r = 1; r < kBinomT; ++r) {
+                if (r > x) { t[(size_t)x * kBinomT + r] = 0; continue; }
+                uint64_t a = t[(size_t)(x - 1) * kBinomT + r - 1];
+                uint64_t b = (r <= x - 1) ? t[(size_t)(x - 1) * kBinomT + r] : 0;
+                uint64_t s = a + b;
+                t[(size_t)x * kBinomT + r] = (s < a || a == UINT64_MAX || b == UINT64_MAX) ? UINT64_MAX : s;
+            }
+        }
+    }
+    uint64_t operator()(int x, int r) const {
+        if (x < 0 || r < 0 || r > x) return 0;
+        if (x >= kBinomX || r >= kBinomT) return UINT64_MAX;
+        return t[(size_t)x * kBinomT + r];
+    }
+};
+const Binom &BN() {
+    static Binom b;
+    return b;
+}
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+inline int bit_of(const uint64_t *row, int c) { return (int)((row[c >> 6] >> (c & 63)) & 1u); }
+
+int check_matrix(const uint64_t *G, int n, int k) {
+    if (!G) return fail(MINDIST_E_ARG, "G is NULL");
+    if (k < 1 || n <= k || n > MINDIST_MAX_N)
+        return fail(MINDIST_E_ARG, "need 1 <= k < n <= 512 (got n=" + std::to_string(n) +
+                                       ", k=" + std::to_string(k) + ")");
+    const int W = (n + 63) / 64;
+    const int rem = n - 64 * (W - 1);
+    if (rem < 64)
+        for (int r = 0; r < k; ++r)
+            if (G[(size_t)r * W + W - 1] >> rem)
+                return fail(MINDIST_E_ARG, "bits beyond column n-1 must be zero (row " +
+                                               std::to_string(r) + ")");
+    return MINDIST_OK;
+}
+
+// One Gauss-Jordan sweep: pivot the columns of `cols` in order on rows r..k-1
+// of M (k x W), eliminating every other row; stop at k pivots.  Appends the
+// pivot columns and returns the new pivot row count.
+int sweep(std::vector<uint64_t> &M, int k, int W, const std::vector<int> &cols, int r,
+          std::vector<int> *piv) {
+    for (int c : cols) {
+        if (r == k) break;
+        int p = -1;
+        for (int i = r; i < k; ++i)
+            if (bit_of(&M[(size_t)i * W], c)) { p = i; break; }
+        if (p < 0) continue;
+        if (p != r)
+            for (int t = 0; t < W; ++t) std::swap(M[(size_t)p * W + t], M[(size_t)r * W + t]);
+        for (int i = 0; i < k; ++i)
+            if (i != r && bit_of(&M[(size_t)i * W], c))
+                for (int t = 0; t < W; ++t) M[(size_t)i * W + t] ^= M[(size_t)r * W + t];
+        if (piv) piv->push_back(c);
+        ++r;
+    }
+    return r;
+}
+
+struct Plan {
+    int n = 0, k = 0, W = 0;
+    int m_full = 0, k_m = 0;
+    std::vector<std::vector<int>> sets;          // full sets, then the partial set
+    std::vector<std::vector<uint64_t>> gamma;    // k x W rows per set, original columns
+};
+
+int make_plan(const uint64_t *G, int n, int k, Plan &P) {
+    int e = check_matrix(G, n, k);
+    if (e) return e;
+    const int W = (n + 63) / 64;
+    P = Plan();
+    P.n = n; P.k = k; P.W = W;
+    std::vector<int> avail(n);
+    for (int c = 0; c < n; ++c) avail[c] = c;
+    bool first = true;
+    for (;;) {
+        std::vector<uint64_t> M(G, G + (size_t)k * W);
+        std::vector<int> piv;
+        int r = sweep(M, k, W, avail, 0, &piv);
+        if (first && r < k) return fail(MINDIST_E_RANK, "rank(G) < k");
+        first = false;
+        if (r == k) {
+            P.sets.push_back(piv);
+            P.gamma.push_back(M);
+            ++P.m_full;
+            std::vector<int> rest;
+            std::set_difference(avail.begin(), avail.end(), piv.begin(), piv.end(),
+                                std::back_inserter(rest));
+            avail.swap(rest);
+            if (avail.empty()) break;
+        } else {
+            P.k_m = r;
+            if (r >= 1) {
+                // complete the echelon form on the remaining rows over all
+                // other columns in ascending order
+                std::vector<int> others;
+                std::vector<int> s = piv;
+                std::sort(s.begin(), s.end());
+                for (int c = 0; c < n; ++c)
+                    if (!std::binary_search(s.begin(), s.end(), c)) others.push_back(c);
+                int r2 = sweep(M, k, W, others, r, nullptr);
+                if (r2 != k) return fail(MINDIST_E_RANK, "rank(G) < k");
+                P.sets.push_back(piv);
+                P.gamma.push_back(M);
+            }
+            break;
+        }
+    }
+    return MINDIST_OK;
+}
+
+int bound_f(int i, int h, int m_full, int k, int k_m) {
+    if (i < m_full) return h + 1;
+    int v = h + 1 - (k - k_m);
+    return v > 0 ? v : 0;
+}
+
+int bound_after(int k, int m_full, int k_m, int n_gamma, int j, int w) {
+    int s = 0;
+    for (int i = 0; i < n_gamma; ++i) s += bound_f(i, i <= j ? w : w - 1, m_full, k, k_m);
+    return s;
+}
+
+// colex unranking of rho into an r-subset of [0, hi) (elements ascending)
+void colex_unrank(uint64_t rho, int r, int hi, int *out) {
+    const Binom &B = BN();
+    for (int t = r; t >= 1; --t) {
+        int lo = t - 1, h = hi - 1;
+        while (lo < h) {
+            int mid = (lo + h + 1) / 2;
+            if (B(mid, t) <= rho) lo = mid; else h = mid - 1;
+        }
+        out[t - 1] = lo;
+        rho -= B(lo, t);
+        hi = lo;
+    }
+}
+
+struct GammaDev {
+    int D = 0, DP = 0;         // dwords carried / stored per row
+    bool stripped = false;     // identity columns removed (weight offset w)
+    uint32_t *rows = nullptr;  // device, k x DP
+    std::map<int, uint32_t *> tables;   // b -> device right table
+    int bcap = 0;              // largest b whose table fits the cap
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct mindist_ctx {
+    Plan P;
+    int n_gamma = 0;           // enumerated sets (partial included unless dropped)
+    std::vector<GammaDev> gd;
+    // options
+    int term_per_level = 0, midpair_exit = 1, partial_never = 0, verify = 0, profile = 0;
+    int64_t deadline_ms = 0;
+    uint64_t cancel_after = 0;
+    uint32_t tile_t = 1024;
+    int blocks_per_cu = 4;
+    uint64_t table_cap = 256ull << 20;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0, cus = 256;
+    // device buffers
+    uint64_t *d_binom = nullptr;
+    DevState *d_state = nullptr;
+    int max_pairs = 0;
+    GroupEntry *d_groups = nullptr;
+    int groups_cap = 0;
+    // pinned host staging
+    GroupEntry *h_groups = nullptr;
+    unsigned char *h_read = nullptr;    // DevState + PairStat + Slot readback
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // last run
+    std::vector<mindist_pair> trace;
+    bool have_run = false;
+};
+
+static void free_ctx(mindist_ctx *c) {
+    if (!c) return;
+    for (auto &g : c->gd) {
+        if (g.rows) (void)hipFree(g.rows);
+        for (auto &kv : g.tables) (void)hipFree(kv.second);
+    }
+    if (c->d_binom) (void)hipFree(c->d_binom);
+    if (c->d_state) (void)hipFree(c->d_state);
+    if (c->d_groups) (void)hipFree(c->d_groups);
+    if (c->h_groups) (void)hipHostFree(c->h_groups);
+    if (c->h_read) (void)hipHostFree(c->h_read);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+static int dp_of_host(int D) { return D <= 1 ? 1 : D <= 2 ? 2 : D <= 4 ? 4 : D <= 8 ? 8 : 16; }
+
+// pack the carried columns of one Gamma row into 32-bit words
+static void pack_row(const uint64_t *row, const std::vector<int> &cols, uint32_t *out, int DP) {
+    for (int d = 0; d < DP; ++d) out[d] = 0;
+    for (size_t i = 0; i < cols.size(); ++i)
+        if (bit_of(row, cols[i])) out[i >> 5] |= 1u << (i & 31);
+}
+
+static int upload_gamma(mindist_ctx *c, int j) {
+    const Plan &P = c->P;
+    GammaDev &g = c->gd[j];
+    std::vector<int> cols;
+    const bool full = j < P.m_full;
+    if (full) {
+        std::vector<int> s = P.sets[j];
+        std::sort(s.begin(), s.end());
+        for (int col = 0; col < P.n; ++col)
+            if (!std::binary_search(s.begin(), s.end(), col)) cols.push_back(col);
+    } else {
+        for (int col = 0; col < P.n; ++col) cols.push_back(col);
+    }
+    g.stripped = full;
+    g.D = (int)((cols.size() + 31) / 32);
+    g.DP = dp_of_host(g.D);
+    std::vector<uint32_t> h((size_t)P.k * g.DP);
+    for (int r = 0; r < P.k; ++r) pack_row(&P.gamma[j][(size_t)r * P.W], cols, &h[(size_t)r * g.DP], g.DP);
+    HIPCHK(hipMalloc(&g.rows, h.size() * 4));
+    HIPCHK(hipMemcpy(g.rows, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+    const Binom &B = BN();
+    g.bcap = 0;
+    for (int b = 1; b <= 16 && b <= P.k; ++b) {
+        uint64_t ent = B(P.k, b);
+        if (ent >= (1ull << 31) || ent * (uint64_t)g.DP * 4 > c->table_cap) break;
+        g.bcap = b;
+    }
+    return MINDIST_OK;
+}
+
+static int get_table(mindist_ctx *c, int j, int b, uint32_t **out) {
+    GammaDev &g = c->gd[j];
+    auto it = g.tables.find(b);
+    if (it != g.tables.end()) { *out = it->second; return MINDIST_OK; }
+    const uint64_t ent = BN()(c->P.k, b);
+    uint32_t *t = nullptr;
+    if (hipMalloc(&t, ent * g.DP * 4) != hipSuccess)
+        return fail(MINDIST_E_NOMEM, "right table allocation failed");
+    TableArgs ta{g.rows, c->d_binom, t, ent, c->P.k, b, g.DP};
+    if (launch_build_table(ta, g.D, c->stream)) {
+        (void)hipFree(t);
+        return fail(MINDIST_E_HIP, "table kernel launch failed");
+    }
+    g.tables[b] = t;
+    *out = t;
+    return MINDIST_OK;
+}
+
+extern "C" int mindist_plan(const uint64_t *G, int n, int k, int *sets, int *m_full,
+                            int *k_partial, uint64_t *gammas) {
+    Plan P;
+    int e = make_plan(G, n, k, P);
+    if (e) return e;
+    if (m_full) *m_full = P.m_full;
+    if (k_partial) *k_partial = P.k_m;
+    if (sets) {
+        int o = 0;
+        for (auto &s : P.sets) for (int c : s) sets[o++] = c;
+    }
+    if (gammas)
+        for (size_t j = 0; j < P.gamma.size(); ++j)
+            std::memcpy(gammas + j * (size_t)P.k * P.W, P.gamma[j].data(),
+                        sizeof(uint64_t) * P.k * P.W);
+    return MINDIST_OK;
+}
+
+extern "C" int mindist_bound_after(int k, int m_full, int k_partial, int include_partial,
+                                   int j, int w) {
+    const int ng = m_full + ((include_partial && k_partial >= 1) ? 1 : 0);
+    if (k < 1 || m_full < 0 || j < 0 || j >= ng || w < 1) return fail(MINDIST_E_ARG, "bad bound query");
+    return bound_after(k, m_full, k_partial, ng, j, w);
+}
+
+extern "C" int mindist_create(const uint64_t *G, int n, int k, mindist_ctx **out) {
+    if (!out) return fail(MINDIST_E_ARG, "out is NULL");
+    *out = nullptr;
+    mindist_ctx *c = new (std::nothrow) mindist_ctx();
+    if (!c) return fail(MINDIST_E_NOMEM, "context allocation failed");
+    int e = make_plan(G, n, k, c->P);
+    if (e) { free_ctx(c); return e; }
+    c->n_gamma = (int)c->P.sets.size();
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        free_ctx(c);
+        return fail(MINDIST_E_HIP, "no HIP device");
+    }
+    hipDeviceProp_t prop;
+#define CHK(expr) do { hipError_t e_ = (expr); if (e_ != hipSuccess) { free_ctx(c); \
+        return fail(MINDIST_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); } } while (0)
+    CHK(hipGetDevice(&c->device));
+    CHK(hipGetDeviceProperties(&prop, c->device));
+    c->cus = prop.multiProcessorCount;
+    CHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+    CHK(hipMalloc(&c->d_binom, sizeof(uint64_t) * kBinomX * kBinomT));
+    CHK(hipMemcpy(c->d_binom, BN().t.data(), sizeof(uint64_t) * kBinomX * kBinomT,
+                  hipMemcpyHostToDevice));
+    c->max_pairs = c->n_gamma * std::min(k, MINDIST_MAX_LEVEL) + 1;
+    CHK(hipMalloc(&c->d_state, state_bytes(c->max_pairs)));
+    c->groups_cap = k + 2;
+    CHK(hipMalloc(&c->d_groups, sizeof(GroupEntry) * c->groups_cap));
+    CHK(hipHostMalloc((void **)&c->h_groups, sizeof(GroupEntry) * c->groups_cap, hipHostMallocDefault));
+    CHK(hipHostMalloc((void **)&c->h_read, 4096, hipHostMallocDefault));
+    CHK(hipEventCreate(&c->ev0));
+    CHK(hipEventCreate(&c->ev1));
+#undef CHK
+    c->gd.resize(c->n_gamma);
+    for (int j = 0; j < c->n_gamma; ++j) {
+        e = upload_gamma(c, j);
+        if (e) { std::string m = g_err; free_ctx(c); return fail(e, m); }
+    }
+    *out = c;
+    return MINDIST_OK;
+}
+
+extern "C" void mindist_destroy(mindist_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_ctx(c);
+}
+
+extern "C" int mindist_set_option(mindist_ctx *c, int key, int64_t v) {
+    if (!c) return fail(MINDIST_E_ARG, "ctx is NULL");
+    switch (key) {
+        case MINDIST_OPT_TERM: c->term_per_level = v ? 1 : 0; break;
+        case MINDIST_OPT_MIDPAIR_EXIT: c->midpair_exit = v ? 1 : 0; break;
+        case MINDIST_OPT_PARTIAL: c->partial_never = v ? 1 : 0; break;
+        case MINDIST_OPT_VERIFY: c->verify = v ? 1 : 0; break;
+        case MINDIST_OPT_STREAM:
+            if (c->own_stream && c->stream) {
+                (void)hipStreamSynchronize(c->stream);
+                (void)hipStreamDestroy(c->stream);
+            }
+            if (v) { c->stream = (hipStream_t)v; c->own_stream = false; }
+            else {
+                HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+                c->own_stream = true;
+            }
+            break;
+        case MINDIST_OPT_DEADLINE_MS: c->deadline_ms = v < 0 ? 0 : v; break;
+        case MINDIST_OPT_TILE_T:
+            if (v < 1 || v > (1 << 20)) return fail(MINDIST_E_ARG, "tile_t out of range");
+            c->tile_t = (uint32_t)v; break;
+        case MINDIST_OPT_BLOCKS_PER_CU:
+            if (v < 1 || v > 64) return fail(MINDIST_E_ARG, "blocks_per_cu out of range");
+            c->blocks_per_cu = (int)v; break;
+        case MINDIST_OPT_PROFILE: c->profile = v ? 1 : 0; break;
+        case MINDIST_OPT_CANCEL_AFTER_CHUNKS: c->cancel_after = v < 0 ? 0 : (uint64_t)v; break;
+        case MINDIST_OPT_TABLE_MIB: {
+            if (v < 1 || v > (1 << 16)) return fail(MINDIST_E_ARG, "table cap out of range");
+            c->table_cap = (uint64_t)v << 20;
+            const Binom &B = BN();
+            for (auto &g : c->gd) {
+                g.bcap = 0;
+                for (int b = 1; b <= 16 && b <= c->P.k; ++b) {
+                    uint64_t ent = B(c->P.k, b);
+                    if (ent >= (1ull << 31) || ent * (uint64_t)g.DP * 4 > c->table_cap) break;
+                    g.bcap = b;
+                }
+            }
+            break;
+        }
+        default: return fail(MINDIST_E_ARG, "unknown option " + std::to_string(key));
+    }
+    return MINDIST_OK;
+}
+
+extern "C" int mindist_info(const mindist_ctx *c, int *m_full, int *k_partial, int *n_gamma) {
+    if (!c) return fail(MINDIST_E_ARG, "ctx is NULL");
+    if (m_full) *m_full = c->P.m_full;
+    if (k_partial) *k_partial = c->P.k_m;
+    if (n_gamma) *n_gamma = c->partial_never ? c->P.m_full : c->n_gamma;
+    return MINDIST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// one pair of Algorithm 1 on the device
+namespace {
+
+struct PairPlan {
+    int a = 0, b = 0;
+    uint64_t n_items = 0, total_chunks = 0;
+    int ngroups = 0;
+};
+
+PairPlan plan_pair(const mindist_ctx *c, int j, int w, GroupEntry *groups) {
+    const int k = c->P.k;
+    const Binom &B = BN();
+    PairPlan pp;
+    pp.b = std::min(w / 2, c->gd[j].bcap);
+    pp.a = w - pp.b;
+    const uint64_t TB = 64ull * 2;   // lane items per tile (kernel's B = 2)
+    pp.n_items = B(k - pp.b, pp.a);
+    const uint64_t tiles = ceil_div(pp.n_items, TB);
+    uint64_t base = 0;
+    for (int e = pp.a - 1; e <= k - 1 - pp.b; ++e) {
+        const uint64_t lo = B(e, pp.a), hi = B(e + 1, pp.a);
+        const uint64_t lt_lo = ceil_div(lo, TB), lt_hi = std::min(ceil_div(hi, TB), tiles);
+        if (lt_hi <= lt_lo) continue;
+        GroupEntry &g = groups[pp.ngroups++];
+        g.chunk_base = base;
+        g.lt_begin = lt_lo;
+        g.nr_first = (uint32_t)B(k - 1 - e, pp.b);
+        g.n_rt = ceil_div(g.nr_first, c->tile_t);
+        g.e = (uint32_t)e;
+        base += (lt_hi - lt_lo) * g.n_rt;
+    }
+    pp.total_chunks = base;
+    return pp;
+}
+
+}  // namespace
+
+extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
+    if (!c || !out) return fail(MINDIST_E_ARG, "NULL argument");
+    const auto t0 = std::chrono::steady_clock::now();
+    const Plan &P = c->P;
+    const int n = P.n, k = P.k;
+    const int ng = c->partial_never ? P.m_full : c->n_gamma;
+    const Binom &B = BN();
+    std::memset(out, 0, sizeof(*out));
+    c->trace.clear();
+    c->have_run = false;
+    if (launch_init_state(c->d_state, c->max_pairs, c->stream))
+        return fail(MINDIST_E_HIP, "init kernel launch failed");
+
+    const int singleton = n - k + 1;
+    int L = 1;
+    uint32_t U_found = kInf;
+    int pairs = 0, exited = 0, last_j = -1, last_w = 0;
+    uint64_t executed_total = 0, canonical_total = 0;
+    double enum_s = 0;
+    int launches = 0;
+    const int midpair = c->midpair_exit && !c->term_per_level;
+    int status = MINDIST_OK;
+    bool stop = false;
+    for (int w = 1; w <= k && !stop; ++w) {
+        int U = (int)std::min<uint32_t>(U_found, (uint32_t)singleton);
+        if (L >= U) break;
+        for (int j = 0; j < ng; ++j) {
+            U = (int)std::min<uint32_t>(U_found, (uint32_t)singleton);
+            if (!c->term_per_level && L >= U) { stop = true; break; }
+            if (w > MINDIST_MAX_LEVEL || B(k, w) >= (1ull << 63)) {
+                status = fail(MINDIST_E_LIMIT, "pair (" + std::to_string(j) + "," +
+                                                   std::to_string(w) + ") exceeds the rank-space limit");
+                stop = true;
+                break;
+            }
+            if (c->deadline_ms) {
+                const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                if (el * 1000.0 > (double)c->deadline_ms) {
+                    status = fail(MINDIST_E_TIMEOUT, "deadline reached");
+                    stop = true;
+                    break;
+                }
+            }
+            const GammaDev &g = c->gd[j];
+            PairPlan pp = plan_pair(c, j, w, c->h_groups);
+            uint32_t *table = nullptr;
+            int e = get_table(c, j, pp.b, &table);
+            if (e) return e;
+            HIPCHK(hipMemcpyAsync(c->d_groups, c->h_groups, sizeof(GroupEntry) * pp.ngroups,
+                                  hipMemcpyHostToDevice, c->stream));
+            PairArgs pa{};
+            pa.rows = g.rows;
+            pa.table = table;
+            pa.binom = c->d_binom;
+            pa.groups = c->d_groups;
+            pa.st = c->d_state;
+            pa.n_items = pp.n_items;
+            pa.total_chunks = pp.total_chunks;
+            pa.cancel_after = c->cancel_after;
+            pa.ngroups = pp.ngroups;
+            pa.k = k;
+            pa.a = pp.a;
+            pa.b = pp.b;
+            pa.T = c->tile_t;
+            pa.offset = g.stripped ? (uint32_t)w : 0u;
+            pa.L_prev = (uint32_t)L;
+            pa.pair = (uint32_t)pairs;
+            pa.midpair_exit = (uint32_t)midpair;
+            const uint64_t want = ceil_div(pp.total_chunks, 4);
+            const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->cus * c->blocks_per_cu));
+            if (c->profile) HIPCHK(hipEventRecord(c->ev0, c->stream));
+            if (launch_enum_pair(pa, g.D, c->verify, blocks, c->stream))
+                return fail(MINDIST_E_HIP, "enumeration kernel launch failed");
+            if (c->profile) HIPCHK(hipEventRecord(c->ev1, c->stream));
+            ++launches;
+            // read back the run state and this pair's statistics
+            HIPCHK(hipMemcpyAsync(c->h_read, c->d_state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipMemcpyAsync(c->h_read + 64, state_pairs(c->d_state) + pairs, sizeof(PairStat),
+                                  hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            float ms = 0;
+            if (c->profile) {
+                HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+                enum_s += ms * 1e-3;
+            }
+            const DevState *hs = reinterpret_cast<const DevState *>(c->h_read);
+            const PairStat *hp = reinterpret_cast<const PairStat *>(c->h_read + 64);
+            U_found = hs->U_found;
+            const int Lb = L;
+            const bool cut = hs->exit_flag != 0 && hp->executed < B(k, w);
+            if (!c->term_per_level && !cut) L = bound_after(k, P.m_full, P.k_m, ng, j, w);
+            mindist_pair rec{};
+            rec.j = j; rec.w = w; rec.L_before = Lb; rec.L_after = L;
+            rec.U_after = (int)std::min<uint32_t>(U_found, (uint32_t)singleton);
+            rec.pair_min = hp->pair_min == kInf ? -1 : (int)hp->pair_min;
+            rec.count = B(k, w);
+            rec.executed = hp->executed;
+            rec.wsum = hp->wsum;
+            rec.ms = ms;
+            rec.dwords = g.D;
+            rec.split_a = pp.a;
+            c->trace.push_back(rec);
+            executed_total += hp->executed;
+            canonical_total += rec.count;
+            ++pairs;
+            last_j = j;
+            last_w = w;
+            if (hs->cancelled) { status = fail(MINDIST_E_CANCELLED, "cancelled after the chunk budget"); stop = true; break; }
+            if (cut) { exited = 1; stop = true; break; }
+        }
+        if (c->term_per_level && !stop) {
+            int s = 0;
+            for (int i = 0; i < ng; ++i) s += bound_f(i, w, P.m_full, k, P.k_m);
+            L = s;
+        }
+    }
+    out->n = n;
+    out->k = k;
+    out->m_full = P.m_full;
+    out->k_partial = P.k_m;
+    out->n_gamma = ng;
+    out->U_found = U_found == kInf ? n + 1 : (int)U_found;
+    out->d = (int)std::min<uint32_t>(U_found, (uint32_t)singleton);
+    out->L_final = L;
+    out->pairs_visited = pairs;
+    out->exited_midpair = exited;
+    out->w_last = last_w;
+    out->j_last = last_j;
+    out->executed_total = executed_total;
+    out->canonical_total = canonical_total;
+    out->seconds_enum = enum_s;
+    out->enum_launches = launches;
+    if (status != MINDIST_OK) {
+        out->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return status;
+    }
+    // witness: slot[U_found] was written by the wave that lowered U_found to it
+    if (U_found != kInf) {
+        Slot s;
+        HIPCHK(hipMemcpyAsync(c->h_read, state_slots(c->d_state) + U_found, sizeof(Slot),
+                              hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        std::memcpy(&s, c->h_read, sizeof(Slot));
+        if (s.pair >= (uint32_t)c->trace.size())
+            return fail(MINDIST_E_HIP, "witness slot holds an invalid pair index");
+        const mindist_pair &pr = c->trace[s.pair];
+        const int a = pr.split_a, b = pr.w - a;
+        int X[MINDIST_MAX_LEVEL + 1], Z[MINDIST_MAX_LEVEL + 1];
+        colex_unrank(s.rho, a, k, X);
+        colex_unrank(s.i, b, k, Z);
+        std::vector<int> rows(X, X + a);
+        for (int t = 0; t < b; ++t) rows.push_back(k - 1 - Z[t]);
+        std::sort(rows.begin(), rows.end());
+        if (std::adjacent_find(rows.begin(), rows.end()) != rows.end() || (int)rows.size() != pr.w)
+            return fail(MINDIST_E_HIP, "witness slot decodes to an invalid combination");
+        uint64_t word[MINDIST_MAX_WORDS] = {0};
+        for (int r : rows) {
+            for (int t = 0; t < P.W; ++t) word[t] ^= P.gamma[pr.j][(size_t)r * P.W + t];
+            out->witness_rows[r >> 6] |= 1ull << (r & 63);
+        }
+        int wt = 0;
+        for (int t = 0; t < P.W; ++t) wt += __builtin_popcountll(word[t]);
+        if (wt != (int)U_found)
+            return fail(MINDIST_E_HIP, "witness weight " + std::to_string(wt) +
+                                           " differs from the found weight " + std::to_string(U_found));
+        std::memcpy(out->witness, word, sizeof(uint64_t) * P.W);
+        out->witness_j = pr.j;
+        out->witness_w = pr.w;
+    }
+    out->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    c->have_run = true;
+    return MINDIST_OK;
+}
+
+extern "C" int mindist_get_pairs(const mindist_ctx *c, mindist_pair *out, int cap, int *n_out) {
+    if (!c || (!out && cap > 0) || !n_out) return fail(MINDIST_E_ARG, "NULL argument");
+    const int n = (int)c->trace.size();
+    for (int i = 0; i < n && i < cap; ++i) out[i] = c->trace[i];
+    *n_out = n;
+    return MINDIST_OK;
+}

@@ -64,9 +64,11 @@ extern "C" {
 #define MINDIST_OPT_STREAM           5
 /* wall-clock limit of one run in ms; 0 = none.  Checked between pairs. */
 #define MINDIST_OPT_DEADLINE_MS      6
-/* kernel shape: codewords per lane-item tile (right tile length). */
+/* kernel shape: right-table entries per chunk; 0 (default) = chosen per
+ * pair (about 12 chunks per resident wave, between 256 and 1024). */
 #define MINDIST_OPT_TILE_T           7
-/* kernel shape: resident workgroups per CU for the enumeration launch. */
+/* kernel shape: resident workgroups per CU for the enumeration launch
+ * (default 4). */
 #define MINDIST_OPT_BLOCKS_PER_CU    8
 /* 1 = time every enumeration launch with HIP events (seconds_enum). */
 #define MINDIST_OPT_PROFILE          9
@@ -76,6 +78,16 @@ extern "C" {
 /* cap on the saved right-sum table of one (Gamma_j, size) in MiB
  * (default 256). */
 #define MINDIST_OPT_TABLE_MIB        11
+/* kernel shape: left subsets held per lane in one chunk (2 or 4, default 4). */
+#define MINDIST_OPT_LANE_ITEMS       12
+/* 1 (default) = read left subsets from a saved table when it fits the
+ * table cap; 0 = every lane unranks its left subsets and adds their rows. */
+#define MINDIST_OPT_LEFT_TABLES      13
+/* chunk order within a pair: 0 (default) = left-tile-major, 1 =
+ * right-tile-major (the resident waves share the same few right tiles). */
+#define MINDIST_OPT_CHUNK_ORDER      14
+/* chunk dispensers per pair: 8 (default) interleaved counters, or 1. */
+#define MINDIST_OPT_COUNTERS         15
 
 typedef struct mindist_ctx mindist_ctx;
 
@@ -138,6 +150,14 @@ int mindist_get_pairs(const mindist_ctx *ctx, mindist_pair *out, int cap, int *n
 void mindist_destroy(mindist_ctx *ctx);
 
 const char *mindist_last_error(void);
+
+/* Calibration microbenchmark: the enumeration kernel's inner loop (one
+ * 32-bit XOR + popcount per carried word and a min per codeword, right sums
+ * from scalar loads) over registers and a 64-entry table, on every CU, with
+ * no setup, tails or atomics.  Reports codewords/s for `dwords` carried
+ * words per codeword (1, 2, 3, 4, 7 or 8): the measured ceiling that the
+ * enumeration's achieved rate is compared against. */
+int mindist_calibrate(int dwords, int blocks_per_cu, double *codewords_per_s, double *seconds);
 
 /* Host-only planning (no device needed): the greedy partition and the
  * systematic matrices.  sets: n ints (full sets of k columns each, then the

@@ -19,7 +19,8 @@ E_NAMES = {0: "OK", -1: "E_ARG", -2: "E_RANK", -3: "E_NOMEM", -4: "E_HIP", -5: "
 
 OPT = {"term": 1, "midpair_exit": 2, "partial": 3, "verify": 4, "stream": 5,
        "deadline_ms": 6, "tile_t": 7, "blocks_per_cu": 8, "profile": 9,
-       "cancel_after_chunks": 10, "table_mib": 11}
+       "cancel_after_chunks": 10, "table_mib": 11, "lane_items": 12,
+       "left_tables": 13, "chunk_order": 14, "counters": 15}
 
 MAX_WORDS = 8
 
@@ -106,6 +107,8 @@ def lib():
         L.mindist_last_error.restype = C.c_char_p
         L.mindist_plan.argtypes = [u64p, C.c_int, C.c_int, ip, ip, ip, u64p]
         L.mindist_bound_after.argtypes = [C.c_int] * 6
+        L.mindist_calibrate.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
         if hasattr(L, "mindist_run_batch"):
             L.mindist_run_batch.argtypes = [C.POINTER(u64p), ip, ip, C.c_int,
                                             C.POINTER(Result), C.POINTER(BatchOpts)]
@@ -151,6 +154,13 @@ def plan(G, n: int, k: int):
     part = sets[mf.value * k: mf.value * k + km.value].tolist()
     ng = mf.value + (1 if km.value >= 1 else 0)
     return full, part, gam[:ng * k * W].reshape(ng, k, W).copy()
+
+
+def calibrate(dwords: int = 3, blocks_per_cu: int = 4):
+    """Measured ceiling of the enumeration's inner loop: (codewords/s, seconds)."""
+    r, t = C.c_double(), C.c_double()
+    _check(lib().mindist_calibrate(dwords, blocks_per_cu, C.byref(r), C.byref(t)))
+    return r.value, t.value
 
 
 def bound_after(k, m_full, k_partial, include_partial, j, w) -> int:

@@ -25,6 +25,7 @@
 
 #include "../../include/mindist.h"
 #include "mindist_internal.h"
+#include "mindist_pool.h"
 
 using namespace md;
 
@@ -200,6 +201,7 @@ struct GammaDev {
     bool stripped = false;     // identity columns removed (weight offset w)
     uint32_t *rows = nullptr;  // device, k x DP
     std::map<int, uint32_t *> tables;   // b -> device right table
+    std::map<int, uint32_t *> ltables;  // a -> device left table
     int bcap = 0;              // largest b whose table fits the cap
 };
 
@@ -214,22 +216,29 @@ struct mindist_ctx {
     int term_per_level = 0, midpair_exit = 1, partial_never = 0, verify = 0, profile = 0;
     int64_t deadline_ms = 0;
     uint64_t cancel_after = 0;
-    uint32_t tile_t = 1024;
+    uint32_t tile_t = 0;       // 0: chosen per pair
     int blocks_per_cu = 4;
+    int items = 4;             // lane items per chunk (kernel template B)
+    int order = 0;             // chunk order: 0 left-tile-major, 1 right-tile-major
+    int counters = kCounters;  // chunk dispensers (1 or kCounters)
+    int left_tables = 1;       // read left subsets from saved tables when they fit
     uint64_t table_cap = 256ull << 20;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0, cus = 256;
     // device buffers
-    uint64_t *d_binom = nullptr;
+    const uint64_t *d_binom = nullptr;   // shared per device
     DevState *d_state = nullptr;
     int max_pairs = 0;
     GroupEntry *d_groups = nullptr;
     int groups_cap = 0;
+    uint64_t *d_rprefix = nullptr, *h_rprefix = nullptr;
+    size_t rprefix_cap = 0;
     // pinned host staging
     GroupEntry *h_groups = nullptr;
     unsigned char *h_read = nullptr;    // DevState + PairStat + Slot readback
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<uint64_t> rprefix_host;
     // last run
     std::vector<mindist_pair> trace;
     bool have_run = false;
@@ -238,17 +247,19 @@ struct mindist_ctx {
 static void free_ctx(mindist_ctx *c) {
     if (!c) return;
     for (auto &g : c->gd) {
-        if (g.rows) (void)hipFree(g.rows);
-        for (auto &kv : g.tables) (void)hipFree(kv.second);
+        dev_free(g.rows);
+        for (auto &kv : g.tables) dev_free(kv.second);
+        for (auto &kv : g.ltables) dev_free(kv.second);
     }
-    if (c->d_binom) (void)hipFree(c->d_binom);
-    if (c->d_state) (void)hipFree(c->d_state);
-    if (c->d_groups) (void)hipFree(c->d_groups);
-    if (c->h_groups) (void)hipHostFree(c->h_groups);
-    if (c->h_read) (void)hipHostFree(c->h_read);
-    if (c->ev0) (void)hipEventDestroy(c->ev0);
-    if (c->ev1) (void)hipEventDestroy(c->ev1);
-    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    dev_free(c->d_state);
+    dev_free(c->d_groups);
+    dev_free(c->d_rprefix);
+    pinned_free(c->h_rprefix);
+    pinned_free(c->h_groups);
+    pinned_free(c->h_read);
+    event_put(c->ev0);
+    event_put(c->ev1);
+    if (c->own_stream && c->stream) stream_put(c->stream);
     delete c;
 }
 
@@ -279,8 +290,10 @@ static int upload_gamma(mindist_ctx *c, int j) {
     g.DP = dp_of_host(g.D);
     std::vector<uint32_t> h((size_t)P.k * g.DP);
     for (int r = 0; r < P.k; ++r) pack_row(&P.gamma[j][(size_t)r * P.W], cols, &h[(size_t)r * g.DP], g.DP);
-    HIPCHK(hipMalloc(&g.rows, h.size() * 4));
-    HIPCHK(hipMemcpy(g.rows, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+    g.rows = static_cast<uint32_t *>(dev_alloc(h.size() * 4));
+    if (!g.rows) return fail(MINDIST_E_NOMEM, "device allocation of Gamma rows failed");
+    HIPCHK(hipMemcpyAsync(g.rows, h.data(), h.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     const Binom &B = BN();
     g.bcap = 0;
     for (int b = 1; b <= 16 && b <= P.k; ++b) {
@@ -291,22 +304,30 @@ static int upload_gamma(mindist_ctx *c, int j) {
     return MINDIST_OK;
 }
 
-static int get_table(mindist_ctx *c, int j, int b, uint32_t **out) {
+// saved sums of all r-subsets of the rows of Gamma_j: the right table
+// (reflected rows) or the left table; built once and kept with the context
+static int get_table(mindist_ctx *c, int j, int r, bool right, uint32_t **out) {
     GammaDev &g = c->gd[j];
-    auto it = g.tables.find(b);
-    if (it != g.tables.end()) { *out = it->second; return MINDIST_OK; }
-    const uint64_t ent = BN()(c->P.k, b);
-    uint32_t *t = nullptr;
-    if (hipMalloc(&t, ent * g.DP * 4) != hipSuccess)
-        return fail(MINDIST_E_NOMEM, "right table allocation failed");
-    TableArgs ta{g.rows, c->d_binom, t, ent, c->P.k, b, g.DP};
+    auto &cache = right ? g.tables : g.ltables;
+    auto it = cache.find(r);
+    if (it != cache.end()) { *out = it->second; return MINDIST_OK; }
+    const uint64_t ent = BN()(c->P.k, r);
+    uint32_t *t = static_cast<uint32_t *>(dev_alloc(ent * g.DP * 4));
+    if (!t) return fail(MINDIST_E_NOMEM, "saved-sum table allocation failed");
+    TableArgs ta{g.rows, c->d_binom, t, ent, c->P.k, r, g.DP, right ? 1 : 0};
     if (launch_build_table(ta, g.D, c->stream)) {
-        (void)hipFree(t);
+        dev_free(t);
         return fail(MINDIST_E_HIP, "table kernel launch failed");
     }
-    g.tables[b] = t;
+    cache[r] = t;
     *out = t;
     return MINDIST_OK;
+}
+
+// a left table is used when it fits the same cap as the right tables
+static bool left_table_fits(const mindist_ctx *c, int j, int a) {
+    const uint64_t ent = BN()(c->P.k, a);
+    return ent < (1ull << 31) && ent * (uint64_t)c->gd[j].DP * 4 <= c->table_cap;
 }
 
 extern "C" int mindist_plan(const uint64_t *G, int n, int k, int *sets, int *m_full,
@@ -353,20 +374,23 @@ extern "C" int mindist_create(const uint64_t *G, int n, int k, mindist_ctx **out
     CHK(hipGetDevice(&c->device));
     CHK(hipGetDeviceProperties(&prop, c->device));
     c->cus = prop.multiProcessorCount;
-    CHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-    c->own_stream = true;
-    CHK(hipMalloc(&c->d_binom, sizeof(uint64_t) * kBinomX * kBinomT));
-    CHK(hipMemcpy(c->d_binom, BN().t.data(), sizeof(uint64_t) * kBinomX * kBinomT,
-                  hipMemcpyHostToDevice));
-    c->max_pairs = c->n_gamma * std::min(k, MINDIST_MAX_LEVEL) + 1;
-    CHK(hipMalloc(&c->d_state, state_bytes(c->max_pairs)));
-    c->groups_cap = k + 2;
-    CHK(hipMalloc(&c->d_groups, sizeof(GroupEntry) * c->groups_cap));
-    CHK(hipHostMalloc((void **)&c->h_groups, sizeof(GroupEntry) * c->groups_cap, hipHostMallocDefault));
-    CHK(hipHostMalloc((void **)&c->h_read, 4096, hipHostMallocDefault));
-    CHK(hipEventCreate(&c->ev0));
-    CHK(hipEventCreate(&c->ev1));
 #undef CHK
+    c->stream = stream_get();
+    c->own_stream = true;
+    c->d_binom = device_binom_from(BN().t.data());
+    c->max_pairs = c->n_gamma * std::min(k, MINDIST_MAX_LEVEL) + 1;
+    c->d_state = static_cast<DevState *>(dev_alloc(state_bytes(c->max_pairs)));
+    c->groups_cap = k + 2;
+    c->d_groups = static_cast<GroupEntry *>(dev_alloc(sizeof(GroupEntry) * c->groups_cap));
+    c->h_groups = static_cast<GroupEntry *>(pinned_alloc(sizeof(GroupEntry) * c->groups_cap));
+    c->h_read = static_cast<unsigned char *>(pinned_alloc(4096));
+    c->ev0 = event_get();
+    c->ev1 = event_get();
+    if (!c->stream || !c->d_binom || !c->d_state || !c->d_groups || !c->h_groups || !c->h_read ||
+        !c->ev0 || !c->ev1) {
+        free_ctx(c);
+        return fail(MINDIST_E_NOMEM, "device or pinned allocation failed");
+    }
     c->gd.resize(c->n_gamma);
     for (int j = 0; j < c->n_gamma; ++j) {
         e = upload_gamma(c, j);
@@ -390,24 +414,31 @@ extern "C" int mindist_set_option(mindist_ctx *c, int key, int64_t v) {
         case MINDIST_OPT_PARTIAL: c->partial_never = v ? 1 : 0; break;
         case MINDIST_OPT_VERIFY: c->verify = v ? 1 : 0; break;
         case MINDIST_OPT_STREAM:
-            if (c->own_stream && c->stream) {
-                (void)hipStreamSynchronize(c->stream);
-                (void)hipStreamDestroy(c->stream);
-            }
+            if (c->stream) (void)hipStreamSynchronize(c->stream);
+            if (c->own_stream && c->stream) stream_put(c->stream);
             if (v) { c->stream = (hipStream_t)v; c->own_stream = false; }
             else {
-                HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+                c->stream = stream_get();
                 c->own_stream = true;
+                if (!c->stream) return fail(MINDIST_E_HIP, "stream creation failed");
             }
             break;
         case MINDIST_OPT_DEADLINE_MS: c->deadline_ms = v < 0 ? 0 : v; break;
         case MINDIST_OPT_TILE_T:
-            if (v < 1 || v > (1 << 20)) return fail(MINDIST_E_ARG, "tile_t out of range");
+            if (v < 0 || v > (1 << 20)) return fail(MINDIST_E_ARG, "tile_t out of range");
             c->tile_t = (uint32_t)v; break;
+        case MINDIST_OPT_LEFT_TABLES: c->left_tables = v ? 1 : 0; break;
+        case MINDIST_OPT_CHUNK_ORDER: c->order = v ? 1 : 0; break;
+        case MINDIST_OPT_COUNTERS:
+            if (v != 1 && v != kCounters) return fail(MINDIST_E_ARG, "counters must be 1 or 8");
+            c->counters = (int)v; break;
         case MINDIST_OPT_BLOCKS_PER_CU:
             if (v < 1 || v > 64) return fail(MINDIST_E_ARG, "blocks_per_cu out of range");
             c->blocks_per_cu = (int)v; break;
         case MINDIST_OPT_PROFILE: c->profile = v ? 1 : 0; break;
+        case MINDIST_OPT_LANE_ITEMS:
+            if (v != 2 && v != 4) return fail(MINDIST_E_ARG, "lane items must be 2 or 4");
+            c->items = (int)v; break;
         case MINDIST_OPT_CANCEL_AFTER_CHUNKS: c->cancel_after = v < 0 ? 0 : (uint64_t)v; break;
         case MINDIST_OPT_TABLE_MIB: {
             if (v < 1 || v > (1 << 16)) return fail(MINDIST_E_ARG, "table cap out of range");
@@ -442,20 +473,42 @@ namespace {
 
 struct PairPlan {
     int a = 0, b = 0;
+    uint32_t T = 0;
+    uint32_t n_rt = 0;         // right tiles (right-major order)
     uint64_t n_items = 0, total_chunks = 0;
     int ngroups = 0;
 };
 
-PairPlan plan_pair(const mindist_ctx *c, int j, int w, GroupEntry *groups) {
+// Chunks of a pair.  Left tiles are runs of 64*items consecutive left
+// subsets (colex order); a left tile whose first subset has largest element
+// e pairs with C(k-1-e, b) right entries, cut into right tiles of T.
+// groups[] lists the runs of left tiles sharing e (left-major order);
+// rprefix[r] (right-major order) is the first chunk of right tile r, whose
+// left tiles are the prefix of tiles that still have entries past r*T.
+PairPlan plan_pair(const mindist_ctx *c, int j, int w, GroupEntry *groups,
+                   std::vector<uint64_t> *rprefix) {
     const int k = c->P.k;
     const Binom &B = BN();
     PairPlan pp;
     pp.b = std::min(w / 2, c->gd[j].bcap);
     pp.a = w - pp.b;
-    const uint64_t TB = 64ull * 2;   // lane items per tile (kernel's B = 2)
+    const uint64_t TB = 64ull * c->items;   // left subsets per tile
     pp.n_items = B(k - pp.b, pp.a);
+    // right tile length: the caller's, else about 12 chunks per resident
+    // wave so the last chunks of the pair leave little idle time, within
+    // [256, 1024] so the per-chunk setup stays amortised
+    if (c->tile_t) {
+        pp.T = c->tile_t;
+    } else {
+        const uint64_t waves = (uint64_t)c->cus * c->blocks_per_cu * 4;
+        const uint64_t want = B(k, w) / (TB * waves * 12);
+        uint32_t T = 256;
+        while (T < 1024 && T < want) T <<= 1;
+        pp.T = T;
+    }
     const uint64_t tiles = ceil_div(pp.n_items, TB);
     uint64_t base = 0;
+    std::vector<uint64_t> lt_end;
     for (int e = pp.a - 1; e <= k - 1 - pp.b; ++e) {
         const uint64_t lo = B(e, pp.a), hi = B(e + 1, pp.a);
         const uint64_t lt_lo = ceil_div(lo, TB), lt_hi = std::min(ceil_div(hi, TB), tiles);
@@ -464,11 +517,26 @@ PairPlan plan_pair(const mindist_ctx *c, int j, int w, GroupEntry *groups) {
         g.chunk_base = base;
         g.lt_begin = lt_lo;
         g.nr_first = (uint32_t)B(k - 1 - e, pp.b);
-        g.n_rt = ceil_div(g.nr_first, c->tile_t);
+        g.n_rt = ceil_div(g.nr_first, pp.T);
         g.e = (uint32_t)e;
         base += (lt_hi - lt_lo) * g.n_rt;
+        lt_end.push_back(lt_hi);
     }
     pp.total_chunks = base;
+    if (rprefix) {
+        // n_rt falls (weakly) from group to group, so the left tiles with
+        // more than r right tiles are those of the groups with n_rt > r
+        rprefix->clear();
+        pp.n_rt = pp.ngroups ? (uint32_t)groups[0].n_rt : 0;
+        uint64_t acc = 0;
+        int gl = pp.ngroups - 1;
+        for (uint32_t r = 0; r < pp.n_rt; ++r) {
+            while (gl >= 0 && groups[gl].n_rt <= r) --gl;
+            rprefix->push_back(acc);
+            acc += lt_end[gl];
+        }
+        rprefix->push_back(acc);
+    }
     return pp;
 }
 
@@ -518,15 +586,37 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
                 }
             }
             const GammaDev &g = c->gd[j];
-            PairPlan pp = plan_pair(c, j, w, c->h_groups);
-            uint32_t *table = nullptr;
-            int e = get_table(c, j, pp.b, &table);
+            std::vector<uint64_t> &rpre = c->rprefix_host;
+            PairPlan pp = plan_pair(c, j, w, c->h_groups, c->order ? &rpre : nullptr);
+            if (c->order) {
+                if (rpre.size() > c->rprefix_cap) {
+                    dev_free(c->d_rprefix);
+                    pinned_free(c->h_rprefix);
+                    c->rprefix_cap = std::max<size_t>(rpre.size(), 2 * c->rprefix_cap);
+                    c->d_rprefix = static_cast<uint64_t *>(dev_alloc(c->rprefix_cap * 8));
+                    c->h_rprefix = static_cast<uint64_t *>(pinned_alloc(c->rprefix_cap * 8));
+                    if (!c->d_rprefix || !c->h_rprefix) {
+                        c->rprefix_cap = 0;
+                        return fail(MINDIST_E_NOMEM, "chunk-order table allocation failed");
+                    }
+                }
+                std::memcpy(c->h_rprefix, rpre.data(), rpre.size() * 8);
+                HIPCHK(hipMemcpyAsync(c->d_rprefix, c->h_rprefix, rpre.size() * 8,
+                                      hipMemcpyHostToDevice, c->stream));
+            }
+            uint32_t *table = nullptr, *ltable = nullptr;
+            int e = get_table(c, j, pp.b, true, &table);
             if (e) return e;
+            if (c->left_tables && left_table_fits(c, j, pp.a)) {
+                e = get_table(c, j, pp.a, false, &ltable);
+                if (e) return e;
+            }
             HIPCHK(hipMemcpyAsync(c->d_groups, c->h_groups, sizeof(GroupEntry) * pp.ngroups,
                                   hipMemcpyHostToDevice, c->stream));
             PairArgs pa{};
             pa.rows = g.rows;
             pa.table = table;
+            pa.ltable = ltable;
             pa.binom = c->d_binom;
             pa.groups = c->d_groups;
             pa.st = c->d_state;
@@ -537,15 +627,20 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
             pa.k = k;
             pa.a = pp.a;
             pa.b = pp.b;
-            pa.T = c->tile_t;
+            pa.T = pp.T;
             pa.offset = g.stripped ? (uint32_t)w : 0u;
             pa.L_prev = (uint32_t)L;
             pa.pair = (uint32_t)pairs;
             pa.midpair_exit = (uint32_t)midpair;
+            pa.max_pairs = c->max_pairs;
+            pa.rprefix = c->d_rprefix;
+            pa.order = (uint32_t)c->order;
+            pa.n_rt = pp.n_rt;
+            pa.counters = (uint32_t)c->counters;
             const uint64_t want = ceil_div(pp.total_chunks, 4);
             const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->cus * c->blocks_per_cu));
             if (c->profile) HIPCHK(hipEventRecord(c->ev0, c->stream));
-            if (launch_enum_pair(pa, g.D, c->verify, blocks, c->stream))
+            if (launch_enum_pair(pa, g.D, c->items, c->verify, blocks, c->stream))
                 return fail(MINDIST_E_HIP, "enumeration kernel launch failed");
             if (c->profile) HIPCHK(hipEventRecord(c->ev1, c->stream));
             ++launches;
@@ -654,4 +749,46 @@ extern "C" int mindist_get_pairs(const mindist_ctx *c, mindist_pair *out, int ca
     for (int i = 0; i < n && i < cap; ++i) out[i] = c->trace[i];
     *n_out = n;
     return MINDIST_OK;
+}
+
+extern "C" int mindist_calibrate(int dwords, int blocks_per_cu, double *codewords_per_s,
+                                 double *seconds) {
+    if (!codewords_per_s || !(dwords == 1 || dwords == 2 || dwords == 3 || dwords == 4 ||
+                              dwords == 7 || dwords == 8) || blocks_per_cu < 1 || blocks_per_cu > 64)
+        return fail(MINDIST_E_ARG, "calibrate: dwords in {1,2,3,4,7,8}, 1 <= blocks_per_cu <= 64");
+    int dev = 0;
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    const int blocks = prop.multiProcessorCount * blocks_per_cu;
+    const int dp = dwords <= 1 ? 1 : dwords <= 2 ? 2 : dwords <= 4 ? 4 : 8;
+    std::vector<uint32_t> h(64 * dp);
+    for (size_t i = 0; i < h.size(); ++i) h[i] = (uint32_t)(i * 2654435761u) ^ 0x5bd1e995u;
+    uint32_t *tab = static_cast<uint32_t *>(dev_alloc(h.size() * 4));
+    uint32_t *out = static_cast<uint32_t *>(dev_alloc((size_t)blocks * 256 * 4));
+    hipStream_t s = stream_get();
+    hipEvent_t e0 = event_get(), e1 = event_get();
+    int rc = MINDIST_OK;
+    if (!tab || !out || !s || !e0 || !e1) rc = fail(MINDIST_E_NOMEM, "calibrate: allocation failed");
+    const uint32_t steps = 1u << 16;
+    float ms = 0;
+    if (rc == MINDIST_OK && (hipMemcpy(tab, h.data(), h.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                             launch_peak(tab, 1024, out, dwords, blocks, s) ||       // warm-up
+                             hipEventRecord(e0, s) != hipSuccess ||
+                             launch_peak(tab, steps, out, dwords, blocks, s) ||
+                             hipEventRecord(e1, s) != hipSuccess ||
+                             hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(MINDIST_E_HIP, "calibrate: kernel failed");
+    if (rc == MINDIST_OK) {
+        const double cw = (double)blocks * 256 * 4 * steps;   // 4 lane items per step
+        *codewords_per_s = cw / (ms * 1e-3);
+        if (seconds) *seconds = ms * 1e-3;
+    }
+    dev_free(tab);
+    dev_free(out);
+    stream_put(s);
+    event_put(e0);
+    event_put(e1);
+    return rc;
 }

@@ -46,7 +46,7 @@ struct PairStat {
     uint32_t pad;
     uint64_t executed;     // combinations evaluated
     uint64_t wsum;         // sum of weights (verify mode)
-    uint64_t next_chunk;   // chunk dispenser
+    uint64_t pad2;
 };
 
 struct Slot {              // witness of weight v: written once, by the wave
@@ -62,22 +62,36 @@ struct DevState {
     uint32_t pad;
     uint64_t claimed;      // chunks claimed in the run (for cancel_after)
     uint64_t pad2;
-    // followed by Slot slots[513] and PairStat pairs[max_pairs]
+    // followed by Slot slots[513], PairStat pairs[max_pairs] and the chunk
+    // dispensers: kCounters counters per pair, each on its own 128-byte line
 };
 
+constexpr int kCounters = 8;         // interleaved chunk dispensers per pair
+constexpr int kCounterStride = 16;   // uint64 words between two counters (128 B)
+
 MD_HD inline size_t state_bytes(int max_pairs) {
-    return sizeof(DevState) + sizeof(Slot) * 513 + sizeof(PairStat) * (size_t)max_pairs;
+    return sizeof(DevState) + sizeof(Slot) * 513 + sizeof(PairStat) * (size_t)max_pairs +
+           sizeof(uint64_t) * kCounters * kCounterStride * (size_t)max_pairs;
 }
 MD_HD inline Slot *state_slots(DevState *s) { return reinterpret_cast<Slot *>(s + 1); }
 MD_HD inline PairStat *state_pairs(DevState *s) {
     return reinterpret_cast<PairStat *>(reinterpret_cast<Slot *>(s + 1) + 513);
 }
+// counter q of pair p
+MD_HD inline uint64_t *state_counter(DevState *s, int max_pairs, int p, int q) {
+    uint64_t *base = reinterpret_cast<uint64_t *>(state_pairs(s) + max_pairs);
+    return base + ((size_t)p * kCounters + q) * kCounterStride;
+}
 
 struct PairArgs {
     const uint32_t *rows;      // k rows x dp words (stripped or full)
     const uint32_t *table;     // right table: C(k,b) entries x dp words
+    const uint32_t *ltable;    // left table: entry rho = rows of colex_unrank_a(rho)
+                               // (nullptr: lanes unrank and add the rows themselves)
     const uint64_t *binom;     // kBinomX x kBinomT
-    const GroupEntry *groups;
+    const GroupEntry *groups;  // left-tile-major chunk order (order = 0)
+    const uint64_t *rprefix;   // right-tile-major order (order = 1): chunk ids
+                               // of right tile r start at rprefix[r]
     DevState *st;
     uint64_t n_items;          // C(k-b, a): left subsets that have a right partner
     uint64_t total_chunks;
@@ -88,6 +102,10 @@ struct PairArgs {
     uint32_t L_prev;           // bound before the pair (exit threshold)
     uint32_t pair;             // index into the pair statistics
     uint32_t midpair_exit;
+    int32_t max_pairs;         // layout of the state block
+    uint32_t order;            // 0: chunk = (left tile, right tile) left-major, 1: right-major
+    uint32_t n_rt;             // right tiles (order = 1)
+    uint32_t counters;         // chunk dispensers in use (1 or kCounters)
     uint32_t pad;
 };
 
@@ -97,12 +115,15 @@ struct TableArgs {
     uint32_t *table;
     uint64_t entries;
     int32_t k, b, dp;
+    int32_t reflect;           // 1: right table (rows k-1-z), 0: left table (rows z)
 };
 
 // kernel launchers (mindist_kernels.hip)
 int launch_init_state(DevState *st, int max_pairs, void *stream);
 int launch_build_table(const TableArgs &ta, int D, void *stream);
-int launch_enum_pair(const PairArgs &pa, int D, int verify, int blocks, void *stream);
+// items: lane items per chunk (2 or 4)
+int launch_enum_pair(const PairArgs &pa, int D, int items, int verify, int blocks, void *stream);
 int max_dwords();
+int launch_peak(const uint32_t *tab, uint32_t steps, uint32_t *out, int D, int blocks, void *stream);
 
 }  // namespace md

@@ -36,6 +36,11 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
     for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
     return uni32(v);
 }
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+    return uni32(v);
+}
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += (uint64_t)__shfl_xor((long long)v, o);
@@ -66,37 +71,105 @@ __device__ __forceinline__ int unrank_add(const uint64_t *bt, const uint32_t *ro
     return top;
 }
 
-// ---------------------------------------------------------------------------
-// Run codewords [i0, i1) of the right table against the B lane items.
+// v_bcnt_u32_b32 with its accumulator operand: popcount(x) + acc in one
+// instruction (the compiler would otherwise sum separate popcounts with
+// v_add3, one more instruction per codeword).
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
+template <int D>
+__device__ __forceinline__ uint32_t weight_of(const uint32_t (&L)[D], const uint32_t (&s)[D]) {
+    uint32_t w = __builtin_popcount(L[0] ^ s[0]);
+#pragma unroll
+    for (int d = 1; d < D; ++d) w = bcnt_acc(L[d] ^ s[d], w);
+    return w;
+}
+
+// A right-table entry is dp_of(D) words; it is fetched whole (the padding
+// word of D = 3 included) so one scalar load brings one entry.
+template <int DP> struct Entry { uint32_t w[DP]; };
+template <> struct Entry<4> {
+    typedef uint32_t v4 __attribute__((ext_vector_type(4)));
+    v4 v;
+};
+template <int D>
+__device__ __forceinline__ void load_entry(cu32 *ct, uint32_t i, uint32_t (&s)[D]) {
+    constexpr int DP = dp_of(D);
+    if constexpr (DP == 4) {
+        typedef const __attribute__((address_space(4))) Entry<4>::v4 cv4;
+        const Entry<4>::v4 v = ((cv4 *)ct)[i];
+        s[0] = v.x;
+        if constexpr (D > 1) s[1] = v.y;
+        if constexpr (D > 2) s[2] = v.z;
+        if constexpr (D > 3) s[3] = v.w;
+    } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d) s[d] = ct[(size_t)i * DP + d];
+    }
+}
+
+// right-table entries per pipelined block (two blocks live in SGPRs)
+template <int D>
+__host__ __device__ constexpr int block_of() { return dp_of(D) <= 4 ? 4 : dp_of(D) <= 8 ? 2 : 1; }
+
+// One right-table entry against the B lane items.
 //   PRED: mask item t once i >= nr[t] (its right range ended)
-//   SUM : accumulate weights (verify mode)
-//   vm  : per item 0xFFFFFFFF if the item counts, 0 for a clamped duplicate
+//   SUM : accumulate weights (verify mode); vm[t] = 0 drops a clamped
+//         duplicate item from the sum
+template <int D, int B, bool PRED, bool SUM>
+__device__ __forceinline__ void step(const uint32_t (&s)[D], uint32_t i, const uint32_t (&L)[B][D],
+                                     const uint32_t (&nr)[B], const uint32_t (&vm)[B],
+                                     uint32_t (&m)[B], uint32_t &ws) {
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+        uint32_t w = weight_of<D>(L[t], s);
+        if (PRED) {
+            const bool on = i < nr[t];
+            if (SUM) ws += on ? (w & vm[t]) : 0u;
+            w = on ? w : kInf;
+        } else if (SUM) {
+            ws += w & vm[t];
+        }
+        m[t] = min(m[t], w);
+    }
+}
+
+// Run right-table entries [i0, i1) against the B lane items.  The uniform
+// entries come in by scalar loads; the next block is requested before the
+// current one is consumed so the load latency overlaps the VALU work.
 template <int D, int B, bool PRED, bool SUM>
 __device__ __forceinline__ void run_range(const uint32_t *tab, uint32_t i0, uint32_t i1,
                                           const uint32_t (&L)[B][D], const uint32_t (&nr)[B],
                                           const uint32_t (&vm)[B], uint32_t (&m)[B],
                                           uint32_t &ws) {
-    constexpr int DP = dp_of(D);
+    constexpr int U = block_of<D>();
     cu32 *ct = (cu32 *)tab;
-#pragma unroll 4
-    for (uint32_t i = i0; i < i1; ++i) {
-        uint32_t s[D];
+    uint32_t i = i0;
+    if (i1 - i0 >= 2 * U) {
+        uint32_t cur[U][D], nxt[U][D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) s[d] = ct[(size_t)i * DP + d];
+        for (int u = 0; u < U; ++u) load_entry<D>(ct, i + u, cur[u]);
+        for (; i + 2 * U <= i1; i += U) {
 #pragma unroll
-        for (int t = 0; t < B; ++t) {
-            uint32_t w = 0;
+            for (int u = 0; u < U; ++u) load_entry<D>(ct, i + U + u, nxt[u]);
 #pragma unroll
-            for (int d = 0; d < D; ++d) w = __builtin_popcount(L[t][d] ^ s[d]) + w;
-            if (PRED) {
-                const bool on = i < nr[t];
-                if (SUM) ws += on ? (w & vm[t]) : 0u;
-                w = on ? w : kInf;
-            } else if (SUM) {
-                ws += w & vm[t];
-            }
-            m[t] = min(m[t], w);
+            for (int u = 0; u < U; ++u) step<D, B, PRED, SUM>(cur[u], i + u, L, nr, vm, m, ws);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int d = 0; d < D; ++d) cur[u][d] = nxt[u][d];
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) step<D, B, PRED, SUM>(cur[u], i + u, L, nr, vm, m, ws);
+        i += U;
+    }
+    for (; i < i1; ++i) {
+        uint32_t s[D];
+        load_entry<D>(ct, i, s);
+        step<D, B, PRED, SUM>(s, i, L, nr, vm, m, ws);
     }
 }
 
@@ -108,11 +181,44 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
     PairStat *ps = state_pairs(p.st) + p.pair;
     Slot *slots = state_slots(p.st);
     int gi = 0;
+    // per-lane totals over all chunks of this wave, flushed once at the end
+    // (per-chunk atomics on the pair record serialise in L2)
+    uint32_t run_min = kInf;
+    uint64_t run_cnt = 0, run_ws = 0;
+    // One chunk per claim, so the waves running at the same moment hold
+    // neighbouring chunks (and read the same few right-table tiles).  Chunk
+    // c is handed out by counter c % 8; a wave starts on counter (wave id %
+    // 8) and moves on, for good, once that counter is past the end.  Eight
+    // counters on separate lines take eight times the claim rate of one.
+    const uint32_t nq = p.counters;
+    // (readfirstlane: the wave index is uniform, and everything derived from
+    // the claimed chunk must stay in scalar registers for the table loads)
+    const uint32_t home =
+        uni32((uint32_t)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % nq));
+    // binomial columns C(x, a) and C(x, b), x <= k, for the per-lane lookups
+    __shared__ uint64_t colA[kBinomX], colB[kBinomX];
+    for (int x = threadIdx.x; x <= p.k; x += blockDim.x) {
+        colA[x] = binom(p.binom, x, p.a);
+        colB[x] = binom(p.binom, x, p.b);
+    }
+    __syncthreads();
+    uint32_t rt_cur = 0;
+    uint32_t moved = 0;
+    uint32_t U_seen = kInf;
     for (;;) {
         uint64_t c = 0;
-        if (lane == 0) c = atomicAdd((unsigned long long *)&ps->next_chunk, 1ull);
-        c = uni64((uint64_t)__shfl((long long)c, 0));
-        if (c >= p.total_chunks) break;
+        bool have = false;
+        while (moved < nq) {
+            const uint32_t q = (home + moved) % nq;
+            uint64_t idx = 0;
+            if (lane == 0)
+                idx = atomicAdd((unsigned long long *)state_counter(p.st, p.max_pairs, p.pair, q), 1ull);
+            idx = uni64((uint64_t)__shfl((long long)idx, 0));
+            c = idx * nq + q;
+            if (c < p.total_chunks) { have = true; break; }
+            ++moved;
+        }
+        if (!have) break;
         if (p.midpair_exit &&
             __hip_atomic_load(&p.st->exit_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             break;
@@ -125,75 +231,104 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
                 break;
             }
         }
-        // chunk -> (left tile, right tile); chunk ids of a wave only grow
-        while (gi + 1 < p.ngroups && p.groups[gi + 1].chunk_base <= c) ++gi;
-        const GroupEntry g = p.groups[gi];
-        const uint64_t off = c - g.chunk_base;
-        const uint64_t lt = g.lt_begin + off / g.n_rt;
-        const uint32_t rt = (uint32_t)(off % g.n_rt);
-        const uint32_t i_begin = rt * p.T;
-        const uint32_t i_end = min(i_begin + p.T, g.nr_first);
+        U_seen = uni32(__hip_atomic_load(&p.st->U_found, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT));
+        uint64_t lt;
+        uint32_t rt, i_begin, i_end;
+        uint32_t e_first = 0;
+        if (p.order == 0) {
+            // left-major: groups of left tiles by the largest element of their
+            // first item; a wave's chunk ids grow except when it changes counter
+            if (p.groups[gi].chunk_base > c) gi = 0;
+            while (gi + 1 < p.ngroups && p.groups[gi + 1].chunk_base <= c) ++gi;
+            const GroupEntry g = p.groups[gi];
+            const uint64_t off = c - g.chunk_base;
+            lt = g.lt_begin + off / g.n_rt;
+            rt = (uint32_t)(off % g.n_rt);
+            i_begin = rt * p.T;
+            i_end = min(i_begin + p.T, g.nr_first);
+            e_first = g.e;
+        } else {
+            // right-major: right tile r holds the left tiles whose first item
+            // still has entries past r*T; find r by binary search
+            uint32_t lo = (p.rprefix[rt_cur] <= c) ? rt_cur : 0u, hi = p.n_rt - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (p.rprefix[mid] <= c) lo = mid; else hi = mid - 1;
+            }
+            rt = rt_cur = lo;
+            lt = c - p.rprefix[rt];
+            i_begin = rt * p.T;
+            i_end = i_begin + p.T;     // clipped below by the first item's range
+        }
 
         // lane items: left subsets rho = lt*64B + t*64 + lane (clamped to the
         // last valid item, which then counts once)
+        // (rank and validity are recomputed where needed rather than kept
+        // live across the hot loop, which must fit 8 waves per SIMD)
         uint32_t L[B][D];
         uint32_t nr[B];
-        uint64_t rho_c[B];
-        bool valid[B];
-        uint32_t nr_lane_min = kInf;
+        uint32_t nr_lane_min = kInf, nr_lane_max = 0;
+        const uint64_t tile0 = lt * TB + lane;
 #pragma unroll
         for (int t = 0; t < B; ++t) {
-            const uint64_t rho = lt * TB + (uint64_t)t * 64 + lane;
-            valid[t] = rho < p.n_items;
-            rho_c[t] = valid[t] ? rho : p.n_items - 1;
+            const uint64_t rho = tile0 + (uint64_t)t * 64;
+            const uint64_t rc = rho < p.n_items ? rho : p.n_items - 1;
 #pragma unroll
             for (int d = 0; d < D; ++d) L[t][d] = 0;
-            const int e = unrank_add<D>(p.binom, p.rows, DP, rho_c[t], p.a, p.k, L[t], false, p.k);
-            nr[t] = (uint32_t)binom(p.binom, p.k - 1 - e, p.b);
+            int e;
+            if (p.ltable) {
+                // saved left sum; its largest element e is the largest x with
+                // C(x, a) <= rho (colex order sorts by largest element)
+#pragma unroll
+                for (int d = 0; d < D; ++d) L[t][d] = p.ltable[rc * DP + d];
+                e = max((int)e_first, p.a - 1);
+                int hi = p.k - 1 - p.b;     // the largest e with a right partner
+                while (e < hi) {
+                    const int mid = (e + hi + 1) >> 1;
+                    if (colA[mid] <= rc) e = mid; else hi = mid - 1;
+                }
+            } else {
+                e = unrank_add<D>(p.binom, p.rows, DP, rc, p.a, p.k, L[t], false, p.k);
+            }
+            nr[t] = (uint32_t)colB[p.k - 1 - e];
             nr_lane_min = min(nr_lane_min, nr[t]);
+            nr_lane_max = max(nr_lane_max, nr[t]);
         }
         const uint32_t nr_min = wave_min_u32(nr_lane_min);
+        if (p.order != 0) i_end = min(i_end, wave_max_u32(nr_lane_max));
         const uint32_t fast_end = min(i_end, max(i_begin, nr_min));
 
         uint32_t m[B], vm[B];
 #pragma unroll
         for (int t = 0; t < B; ++t) {
             m[t] = kInf;
-            vm[t] = valid[t] ? kInf : 0u;
+            vm[t] = (tile0 + (uint64_t)t * 64 < p.n_items) ? kInf : 0u;
         }
         uint32_t ws = 0;
         run_range<D, B, false, VERIFY>(p.table, i_begin, fast_end, L, nr, vm, m, ws);
         run_range<D, B, true, VERIFY>(p.table, fast_end, i_end, L, nr, vm, m, ws);
 
-        uint64_t cnt = 0;
         uint32_t lmin = kInf;
 #pragma unroll
         for (int t = 0; t < B; ++t) {
             lmin = min(lmin, m[t]);
-            if (valid[t]) {
+            if (tile0 + (uint64_t)t * 64 < p.n_items) {
                 const uint32_t hi = min(i_end, nr[t]);
-                cnt += hi > i_begin ? (uint64_t)(hi - i_begin) : 0ull;
+                run_cnt += hi > i_begin ? (uint64_t)(hi - i_begin) : 0ull;
             }
         }
+        run_min = min(run_min, lmin);
+        if (VERIFY) run_ws += ws;
+        // only a lane that beats U (as last read) takes part in the update
+        const bool better = lmin != kInf && lmin + p.offset < U_seen;
+        if (!__ballot(better)) continue;
         const uint32_t wmin = wave_min_u32(lmin);
-        const uint64_t wcnt = wave_sum_u64(cnt);
-        uint64_t wws = 0;
-        if (VERIFY) wws = wave_sum_u64((uint64_t)ws);
-        if (lane == 0) {
-            atomicAdd((unsigned long long *)&ps->executed, (unsigned long long)wcnt);
-            if (VERIFY)
-                atomicAdd((unsigned long long *)&ps->wsum,
-                          (unsigned long long)(wws + (uint64_t)p.offset * wcnt));
-            if (wmin != kInf) atomicMin(&ps->pair_min, wmin + p.offset);
-        }
-        if (wmin == kInf) continue;
         const uint32_t val = wmin + p.offset;
-        const uint32_t cur =
-            __hip_atomic_load(&p.st->U_found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (val >= cur) continue;
         uint32_t old = 0;
         if (lane == 0) old = atomicMin(&p.st->U_found, val);
         old = uni32((uint32_t)__shfl((int)old, 0));
+        U_seen = min(old, val);
         if (old > val) {
             // this wave moved U_found to val: it alone writes slot[val].
             // Find the first (item, i) of the chunk that has weight wmin.
@@ -202,13 +337,10 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
             cu32 *ct = (cu32 *)p.table;
             for (uint32_t i = i_begin; i < i_end && hit_t < 0; ++i) {
                 uint32_t s[D];
-#pragma unroll
-                for (int d = 0; d < D; ++d) s[d] = ct[(size_t)i * DP + d];
+                load_entry<D>(ct, i, s);
 #pragma unroll
                 for (int t = 0; t < B; ++t) {
-                    uint32_t w = 0;
-#pragma unroll
-                    for (int d = 0; d < D; ++d) w = __builtin_popcount(L[t][d] ^ s[d]) + w;
+                    const uint32_t w = weight_of<D>(L[t], s);
                     if (hit_t < 0 && i < nr[t] && w == wmin) { hit_t = t; hit_i = i; }
                 }
             }
@@ -217,7 +349,11 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
             if (lane == first) {
                 uint64_t rho = 0;
 #pragma unroll
-                for (int t = 0; t < B; ++t) if (t == hit_t) rho = rho_c[t];
+                for (int t = 0; t < B; ++t)
+                    if (t == hit_t) {
+                        rho = tile0 + (uint64_t)t * 64;
+                        if (rho >= p.n_items) rho = p.n_items - 1;
+                    }
                 slots[val].pair = p.pair;
                 slots[val].i = hit_i;
                 slots[val].rho = rho;
@@ -226,9 +362,62 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
         if (p.midpair_exit && val <= p.L_prev && lane == 0)
             __hip_atomic_store(&p.st->exit_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    const uint32_t wmin = wave_min_u32(run_min);
+    const uint64_t wcnt = wave_sum_u64(run_cnt);
+    const uint64_t wws = VERIFY ? wave_sum_u64(run_ws) : 0ull;
+    if (lane == 0) {
+        if (wcnt) atomicAdd((unsigned long long *)&ps->executed, (unsigned long long)wcnt);
+        if (VERIFY && wcnt)
+            atomicAdd((unsigned long long *)&ps->wsum,
+                      (unsigned long long)(wws + (uint64_t)p.offset * wcnt));
+        if (wmin != kInf) atomicMin(&ps->pair_min, wmin + p.offset);
+    }
 }
 
-// Right table: entry i = sum of the rows {k-1-z : z in colex_unrank_b(i)}.
+// Calibration: the hot loop of enum_pair_kernel with nothing around it.
+// Every lane holds B left sums, the wave walks a 64-entry right table (kept
+// in the scalar cache) for `steps` entries per pass; no unranking, no
+// tails, no atomics.  Its rate is the ceiling of the enumeration's
+// instruction mix on this device and clock.
+template <int D, int B>
+__global__ __launch_bounds__(256) void peak_xorpop_kernel(const uint32_t *tab, uint32_t steps,
+                                                          uint32_t *out) {
+    uint32_t L[B][D], nr[B], vm[B], m[B];
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) L[t][d] = gid * 0x9E3779B9u + (uint32_t)(t * 7 + d) * 0x85EBCA6Bu;
+        nr[t] = kInf;
+        vm[t] = kInf;
+        m[t] = kInf;
+    }
+    uint32_t ws = 0;
+    for (uint32_t i = 0; i < steps; i += 64)
+        run_range<D, B, false, false>(tab, 0, 64, L, nr, vm, m, ws);
+    uint32_t r = kInf;
+#pragma unroll
+    for (int t = 0; t < B; ++t) r = min(r, m[t]);
+    if (r == 0x12345678u) out[gid] = r;    // keeps the loop alive
+}
+
+int launch_peak(const uint32_t *tab, uint32_t steps, uint32_t *out, int D, int blocks, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    switch (D) {
+        case 1: hipLaunchKernelGGL((peak_xorpop_kernel<1, 4>), dim3(blocks), dim3(256), 0, s, tab, steps, out); break;
+        case 2: hipLaunchKernelGGL((peak_xorpop_kernel<2, 4>), dim3(blocks), dim3(256), 0, s, tab, steps, out); break;
+        case 3: hipLaunchKernelGGL((peak_xorpop_kernel<3, 4>), dim3(blocks), dim3(256), 0, s, tab, steps, out); break;
+        case 4: hipLaunchKernelGGL((peak_xorpop_kernel<4, 4>), dim3(blocks), dim3(256), 0, s, tab, steps, out); break;
+        case 7: hipLaunchKernelGGL((peak_xorpop_kernel<7, 4>), dim3(blocks), dim3(256), 0, s, tab, steps, out); break;
+        case 8: hipLaunchKernelGGL((peak_xorpop_kernel<8, 4>), dim3(blocks), dim3(256), 0, s, tab, steps, out); break;
+        default: return -2;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Right table (reflect = 1): entry i = sum of the rows {k-1-z : z in
+// colex_unrank_b(i)}.  Left table (reflect = 0): entry rho = sum of the rows
+// of colex_unrank_a(rho).
 template <int D>
 __global__ __launch_bounds__(256) void build_table_kernel(TableArgs ta) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -236,7 +425,7 @@ __global__ __launch_bounds__(256) void build_table_kernel(TableArgs ta) {
     uint32_t acc[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) acc[d] = 0;
-    unrank_add<D>(ta.binom, ta.rows, ta.dp, i, ta.b, ta.k, acc, true, ta.k);
+    unrank_add<D>(ta.binom, ta.rows, ta.dp, i, ta.b, ta.k, acc, ta.reflect != 0, ta.k);
 #pragma unroll
     for (int d = 0; d < D; ++d) ta.table[i * ta.dp + d] = acc[d];
     for (int d = D; d < ta.dp; ++d) ta.table[i * ta.dp + d] = 0;
@@ -244,6 +433,8 @@ __global__ __launch_bounds__(256) void build_table_kernel(TableArgs ta) {
 
 __global__ void init_state_kernel(DevState *st, int max_pairs) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int q = tid; q < max_pairs * kCounters; q += gridDim.x * blockDim.x)
+        *state_counter(st, max_pairs, q / kCounters, q % kCounters) = 0;
     if (tid == 0) {
         st->U_found = kInf;
         st->exit_flag = 0;
@@ -255,13 +446,10 @@ __global__ void init_state_kernel(DevState *st, int max_pairs) {
         ps[p].pair_min = kInf;
         ps[p].executed = 0;
         ps[p].wsum = 0;
-        ps[p].next_chunk = 0;
     }
 }
 
 // ---------------------------------------------------------------------------
-constexpr int kB = 2;   // lane items per chunk
-
 int max_dwords() { return 16; }
 
 static int check(hipError_t e) { return e == hipSuccess ? 0 : -1; }
@@ -291,18 +479,24 @@ int launch_build_table(const TableArgs &ta, int D, void *stream) {
     return check(hipGetLastError());
 }
 
-template <int D>
-static void enum_launch(const PairArgs &pa, int verify, int blocks, hipStream_t s) {
+template <int D, int B>
+static void enum_launch_b(const PairArgs &pa, int verify, int blocks, hipStream_t s) {
     if (verify)
-        hipLaunchKernelGGL((enum_pair_kernel<D, kB, true>), dim3(blocks), dim3(256), 0, s, pa);
+        hipLaunchKernelGGL((enum_pair_kernel<D, B, true>), dim3(blocks), dim3(256), 0, s, pa);
     else
-        hipLaunchKernelGGL((enum_pair_kernel<D, kB, false>), dim3(blocks), dim3(256), 0, s, pa);
+        hipLaunchKernelGGL((enum_pair_kernel<D, B, false>), dim3(blocks), dim3(256), 0, s, pa);
 }
 
-int launch_enum_pair(const PairArgs &pa, int D, int verify, int blocks, void *stream) {
+template <int D>
+static void enum_launch(const PairArgs &pa, int items, int verify, int blocks, hipStream_t s) {
+    if (items == 4) enum_launch_b<D, 4>(pa, verify, blocks, s);
+    else enum_launch_b<D, 2>(pa, verify, blocks, s);
+}
+
+int launch_enum_pair(const PairArgs &pa, int D, int items, int verify, int blocks, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     switch (D) {
-#define MD_CASE(X) case X: enum_launch<X>(pa, verify, blocks, s); break;
+#define MD_CASE(X) case X: enum_launch<X>(pa, items, verify, blocks, s); break;
         MD_CASE(1) MD_CASE(2) MD_CASE(3) MD_CASE(4) MD_CASE(5) MD_CASE(6) MD_CASE(7) MD_CASE(8)
         MD_CASE(9) MD_CASE(10) MD_CASE(11) MD_CASE(12) MD_CASE(13) MD_CASE(14) MD_CASE(15)
         MD_CASE(16)

@@ -1,0 +1,193 @@
+// mindist_pool.cpp -- caches of device/pinned memory, streams and events.
+#include "mindist_pool.h"
+
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "mindist_internal.h"
+
+namespace md {
+namespace {
+
+std::mutex g_mu;
+
+// sizes are rounded so repeated requests of nearby sizes share blocks
+size_t round_size(size_t b) {
+    if (b < 4096) return 4096;
+    if (b <= (1u << 20)) {
+        size_t r = 4096;
+        while (r < b) r <<= 1;
+        return r;
+    }
+    const size_t q = 1u << 20;
+    return (b + q - 1) / q * q;
+}
+
+struct Block { int dev; size_t size; bool pinned; };
+std::unordered_map<void *, Block> g_live;
+std::map<std::pair<int, size_t>, std::vector<void *>> g_dev_free;   // (device, size)
+std::map<size_t, std::vector<void *>> g_pin_free;
+size_t g_dev_cached = 0;
+std::vector<hipStream_t> g_streams[64];
+std::vector<hipEvent_t> g_events[64];
+const uint64_t *g_binom[64] = {nullptr};
+
+int cur_dev() {
+    int d = 0;
+    (void)hipGetDevice(&d);
+    return d < 0 ? 0 : (d > 63 ? 63 : d);
+}
+
+void release_cached_device(int dev) {
+    for (auto it = g_dev_free.begin(); it != g_dev_free.end();) {
+        if (it->first.first == dev) {
+            for (void *p : it->second) {
+                (void)hipFree(p);
+                g_dev_cached -= it->first.second;
+            }
+            it = g_dev_free.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+}  // namespace
+
+void *dev_alloc(size_t bytes) {
+    const size_t sz = round_size(bytes);
+    const int dev = cur_dev();
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_dev_free.find({dev, sz});
+    if (it != g_dev_free.end() && !it->second.empty()) {
+        void *p = it->second.back();
+        it->second.pop_back();
+        g_dev_cached -= sz;
+        g_live[p] = {dev, sz, false};
+        return p;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        release_cached_device(dev);
+        if (hipMalloc(&p, sz) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    g_live[p] = {dev, sz, false};
+    return p;
+}
+
+void dev_free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) return;
+    g_dev_free[{it->second.dev, it->second.size}].push_back(p);
+    g_dev_cached += it->second.size;
+    g_live.erase(it);
+}
+
+void *pinned_alloc(size_t bytes) {
+    const size_t sz = round_size(bytes);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_pin_free.find(sz);
+    if (it != g_pin_free.end() && !it->second.empty()) {
+        void *p = it->second.back();
+        it->second.pop_back();
+        g_live[p] = {-1, sz, true};
+        return p;
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    g_live[p] = {-1, sz, true};
+    return p;
+}
+
+void pinned_free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) return;
+    g_pin_free[it->second.size].push_back(p);
+    g_live.erase(it);
+}
+
+hipStream_t stream_get() {
+    const int dev = cur_dev();
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_streams[dev].empty()) {
+            hipStream_t s = g_streams[dev].back();
+            g_streams[dev].pop_back();
+            return s;
+        }
+    }
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    return s;
+}
+
+void stream_put(hipStream_t s) {
+    if (!s) return;
+    const int dev = cur_dev();
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_streams[dev].push_back(s);
+}
+
+hipEvent_t event_get() {
+    const int dev = cur_dev();
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_events[dev].empty()) {
+            hipEvent_t e = g_events[dev].back();
+            g_events[dev].pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void event_put(hipEvent_t e) {
+    if (!e) return;
+    const int dev = cur_dev();
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_events[dev].push_back(e);
+}
+
+const uint64_t *device_binom_from(const uint64_t *host_table) {
+    const int dev = cur_dev();
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (g_binom[dev]) return g_binom[dev];
+    }
+    const size_t bytes = sizeof(uint64_t) * kBinomX * kBinomT;
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    if (hipMemcpy(p, host_table, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_binom[dev]) {          // another thread won the race
+        (void)hipFree(p);
+        return g_binom[dev];
+    }
+    g_binom[dev] = static_cast<const uint64_t *>(p);
+    return g_binom[dev];
+}
+
+size_t dev_cached_bytes() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_dev_cached;
+}
+
+}  // namespace md

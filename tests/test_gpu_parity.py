@@ -236,6 +236,18 @@ def test_tile_shapes(tile_t, bpc):
         compare_with_trace(res, gold["trace"], gold["counts"], gold["pair_min"], gold["wsum"], w.k)
 
 
+@pytest.mark.parametrize("order,counters,items,left", [(0, 1, 4, 1), (0, 8, 2, 0), (1, 8, 4, 1),
+                                                       (1, 1, 2, 1), (1, 1, 4, 0)])
+def test_chunk_orders_and_dispensers(order, counters, items, left):
+    for name in ["rand48x24", "rand150x75", "rand255x40"]:
+        gold = json.load(open(os.path.join(GOLDEN, f"{name}.json")))
+        w = WORKLOADS[name]
+        say(name, "order", order, "counters", counters, "items", items, "left tables", left)
+        res = md.min_distance(w.matrix(), w.n, w.k, chunk_order=order, counters=counters,
+                              lane_items=items, left_tables=left, verify=1)
+        compare_with_trace(res, gold["trace"], gold["counts"], gold["pair_min"], gold["wsum"], w.k)
+
+
 def test_max_width_code():
     """n = 512 (8 words, 16 dwords per row), many information sets."""
     G = random_generator(512, 20, 512, 0)

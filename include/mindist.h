@@ -172,6 +172,39 @@ int mindist_plan(const uint64_t *G, int n, int k, int *sets, int *m_full,
 int mindist_bound_after(int k, int m_full, int k_partial, int include_partial,
                         int j, int w);
 
+/* ---- batches: many codes in one persistent launch ---------------------- */
+typedef struct mindist_batch_opts {
+    int32_t tile_min;         /* right-tile length bounds (0 = 256 / 2048) */
+    int32_t tile_max;
+    int32_t blocks_per_cu;    /* resident workgroups per CU (0 = 4) */
+    int32_t use_graph;        /* 1 = run as one captured hipGraph (default), 0 = plain launch */
+    int32_t table_kib;        /* cap on one saved right-sum table in KiB (0 = 8192) */
+    int32_t jobs_per_code;    /* job-arena sizing: average jobs per code (0 = 96) */
+    double  deadline_s;       /* wall-clock limit of the launch; waves leave after it and the
+                                 call returns MINDIST_E_TIMEOUT (0 = none) */
+    int64_t stream;           /* hipStream_t, 0 = private */
+    mindist_pair *pairs;      /* optional: visited pairs of every code (caller-owned) */
+    int64_t pairs_cap;        /* capacity of pairs[] */
+    int64_t *pairs_index;     /* optional: B+1 offsets into pairs[] (caller-owned) */
+    double  seconds_kernel;   /* out: device time of the launch (HIP events) */
+    double  seconds_total;    /* out: wall clock of the call */
+    double  seconds_prep;     /* out: host preprocessing (information sets, packing) */
+    uint64_t executed_total;  /* out: codewords evaluated */
+} mindist_batch_opts;
+
+/* Solve B codes in one persistent launch: a device-side scheduler hands out
+ * chunks of each code's current pair (Algorithm 1's inner minimum) and, when a
+ * pair completes, applies Algorithm 1's bound and termination test for that
+ * code and opens its next pair (one raise of L per Gamma_j, midpair exit).
+ * G[i] points at code i's matrix (layout as above; n <= 256, at most 32
+ * information sets); out has B caller-owned entries.  Results equal
+ * mindist_run's with default options (d, visited pairs, counts, pair minima);
+ * witnesses may differ but have weight d.  Per-code failures (rank, limits)
+ * are reported as out[i].d = negative error code; the call returns
+ * MINDIST_OK unless the whole batch failed. */
+int mindist_run_batch(const uint64_t *const *G, const int *n, const int *k, int B,
+                      mindist_result *out, mindist_batch_opts *opts);
+
 #ifdef __cplusplus
 }
 #endif

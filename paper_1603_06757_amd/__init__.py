@@ -70,9 +70,12 @@ class Pair(C.Structure):
 
 
 class BatchOpts(C.Structure):
-    _fields_ = [("tile_t", C.c_int32), ("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32),
-                ("profile", C.c_int32), ("stream", C.c_int64), ("seconds_kernel", C.c_double),
-                ("seconds_total", C.c_double), ("executed_total", C.c_uint64)]
+    _fields_ = [("tile_min", C.c_int32), ("tile_max", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("use_graph", C.c_int32), ("table_kib", C.c_int32), ("jobs_per_code", C.c_int32),
+                ("deadline_s", C.c_double), ("stream", C.c_int64), ("pairs", C.c_void_p), ("pairs_cap", C.c_int64),
+                ("pairs_index", C.c_void_p), ("seconds_kernel", C.c_double),
+                ("seconds_total", C.c_double), ("seconds_prep", C.c_double),
+                ("executed_total", C.c_uint64)]
 
 
 class ServerOpts(C.Structure):
@@ -217,6 +220,51 @@ class MinDist:
 
     def __exit__(self, *a):
         self.close()
+
+
+BATCH_MAX_PAIRS = 256
+
+
+def run_batch(codes, tile_min: int = 0, tile_max: int = 0, blocks_per_cu: int = 0,
+              use_graph: int = 1, table_kib: int = 0, jobs_per_code: int = 0,
+              pairs: bool = True, deadline_s: float = 60.0):
+    """Solve many codes in one persistent launch.
+
+    codes: iterable of (n, k, G).  Returns (results, info): results[i] is the
+    dict of mindist_run for code i (with "pairs" when requested) or
+    {"error": code}; info holds the timings and the executed codeword count.
+    """
+    codes = list(codes)
+    B = len(codes)
+    mats = [_mat(G, n, k) for n, k, G in codes]
+    ptrs = (C.POINTER(C.c_uint64) * B)(*[_u64(m) for m in mats])
+    ns = (C.c_int * B)(*[n for n, _, _ in codes])
+    ks = (C.c_int * B)(*[k for _, k, _ in codes])
+    out = (Result * B)()
+    o = BatchOpts()
+    o.tile_min, o.tile_max, o.blocks_per_cu = tile_min, tile_max, blocks_per_cu
+    o.use_graph, o.table_kib, o.jobs_per_code = use_graph, table_kib, jobs_per_code
+    o.deadline_s = deadline_s
+    if pairs:
+        cap = B * BATCH_MAX_PAIRS
+        parr = (Pair * cap)()
+        idx = (C.c_int64 * (B + 1))()
+        o.pairs = C.cast(parr, C.c_void_p)
+        o.pairs_cap = cap
+        o.pairs_index = C.cast(idx, C.c_void_p)
+    _check(lib().mindist_run_batch(ptrs, ns, ks, B, out, C.byref(o)))
+    results = []
+    for i in range(B):
+        if out[i].d < 0:
+            results.append({"error": out[i].d, "n": codes[i][0], "k": codes[i][1]})
+            continue
+        r = out[i].to_dict()
+        if pairs:
+            r["pairs"] = [parr[t].to_dict() for t in range(idx[i], idx[i + 1])]
+        results.append(r)
+    info = {"seconds_kernel": o.seconds_kernel, "seconds_total": o.seconds_total,
+            "seconds_prep": o.seconds_prep, "executed_total": o.executed_total}
+    return results, info
 
 
 def min_distance(G, n: int, k: int, **options) -> dict:

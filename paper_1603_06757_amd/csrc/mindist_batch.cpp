@@ -1,0 +1,456 @@
+// mindist_batch.cpp -- host side of the persistent multi-code path:
+// preprocessing of many codes (a thread pool runs the information-set
+// partition and packing), the device layout of code slots, the launch (as
+// one captured hipGraph: uploads + persistent kernel), and decoding of the
+// per-code results.  The server reuses the engine with slots that are
+// refilled between launches.
+#include "mindist_batch_engine.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstring>
+#include <thread>
+
+#include "../../include/mindist.h"
+#include "mindist_plan.h"
+#include "mindist_pool.h"
+
+namespace md {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t job_bytes(int k) {
+    const size_t b = sizeof(BatchJob) + sizeof(GroupEntry) * (size_t)(k + 2);
+    return (b + 127) / 128 * 128;
+}
+
+int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &hc) {
+    hc = HostCode();
+    hc.n = n;
+    hc.k = k;
+    int e = make_plan(G, n, k, hc.P);
+    if (e) return e;
+    hc.n_gamma = (int)hc.P.sets.size();
+    if (hc.n_gamma > kBatchMaxSets) return fail(MINDIST_E_LIMIT, "more than 32 information sets");
+    const Binom &B = BN();
+    hc.D.resize(hc.n_gamma);
+    hc.dp.resize(hc.n_gamma);
+    hc.bcap.resize(hc.n_gamma);
+    hc.rows.resize(hc.n_gamma);
+    for (int j = 0; j < hc.n_gamma; ++j) {
+        const std::vector<int> cols = carried_columns(hc.P, j);
+        hc.D[j] = (int)((cols.size() + 31) / 32);
+        if (hc.D[j] > kBatchMaxD) return fail(MINDIST_E_LIMIT, "rows wider than 256 bits");
+        hc.dp[j] = dp_of_host(hc.D[j]);
+        hc.rows[j].assign((size_t)k * hc.dp[j], 0u);
+        for (int r = 0; r < k; ++r)
+            pack_row(&hc.P.gamma[j][(size_t)r * hc.P.W], cols, &hc.rows[j][(size_t)r * hc.dp[j]], hc.dp[j]);
+        int bc = 0;
+        for (int b = 1; b <= kBatchMaxB && b <= k; ++b) {
+            if (B(k, b) * (uint64_t)hc.dp[j] * 4 > table_cap) break;
+            bc = b;
+        }
+        hc.bcap[j] = bc;
+    }
+    // device footprint in three regions: rows (uploaded), right tables (built
+    // on the device), witness slots (read back); 256-byte pieces so no cache
+    // line is shared between two codes' tables
+    hc.rows_bytes = hc.tab_bytes = 0;
+    for (int j = 0; j < hc.n_gamma; ++j) {
+        hc.rows_bytes += align256((size_t)k * hc.dp[j] * 4);
+        for (int b = 0; b <= hc.bcap[j]; ++b) hc.tab_bytes += align256(B(k, b) * hc.dp[j] * 4);
+    }
+    hc.slot_bytes = align256(sizeof(Slot) * (size_t)(n + 1));
+    return MINDIST_OK;
+}
+
+void fill_slot(const HostCode &hc, const SlotPlace &pl, unsigned char *rows_stage,
+               uint32_t tile_cap, uint64_t seq, BatchCode &bc) {
+    std::memset(&bc, 0, sizeof(bc));
+    const Binom &B = BN();
+    bc.n = hc.n;
+    bc.k = hc.k;
+    bc.m_full = hc.P.m_full;
+    bc.k_m = hc.P.k_m;
+    bc.n_gamma = hc.n_gamma;
+    bc.W = hc.P.W;
+    bc.status = kSlotPending;
+    bc.njobs = 0;
+    bc.U_found = kInf;
+    bc.tile_cap = tile_cap;
+    bc.seq = seq;
+    uint64_t acc = 0;
+    for (int t = 0; t < kBatchTabs; ++t) {
+        bc.tab_off[t] = acc;
+        const int j = t / (kBatchMaxB + 1), b = t % (kBatchMaxB + 1);
+        if (j < hc.n_gamma && b <= hc.bcap[j]) acc += B(hc.k, b);
+    }
+    bc.tab_off[kBatchTabs] = acc;
+    size_t ro = 0, to = 0;
+    for (int j = 0; j < hc.n_gamma; ++j) {
+        BatchSet &s = bc.sets[j];
+        s.D = hc.D[j];
+        s.dp = hc.dp[j];
+        s.stripped = j < hc.P.m_full ? 1 : 0;
+        s.bcap = hc.bcap[j];
+        const size_t rb = (size_t)hc.k * hc.dp[j] * 4;
+        std::memcpy(rows_stage + ro, hc.rows[j].data(), rb);
+        s.rows = reinterpret_cast<const uint32_t *>(pl.rows + ro);
+        ro += align256(rb);
+        for (int b = 0; b <= hc.bcap[j]; ++b) {
+            s.rtab[b] = reinterpret_cast<uint32_t *>(pl.tabs + to);
+            to += align256(B(hc.k, b) * hc.dp[j] * 4);
+        }
+    }
+    bc.slots = reinterpret_cast<Slot *>(pl.slots);
+}
+
+int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *arena,
+                const Slot *slots, mindist_result &out, std::vector<mindist_pair> &trace) {
+    std::memset(&out, 0, sizeof(out));
+    trace.clear();
+    const int n = hc.n, k = hc.k;
+    out.n = n;
+    out.k = k;
+    out.m_full = hc.P.m_full;
+    out.k_partial = hc.P.k_m;
+    out.n_gamma = hc.n_gamma;
+    if (bc.status != kSlotDone) {
+        out.d = bc.status < 0 ? bc.status : MINDIST_E_STATE;
+        return out.d;
+    }
+    const Binom &B = BN();
+    const uint32_t singleton = (uint32_t)(n - k + 1);
+    uint64_t executed = 0, canonical = 0;
+    for (int p = 1; p < bc.njobs; ++p) {
+        const BatchJob *jb = reinterpret_cast<const BatchJob *>(arena + (size_t)bc.job[p] * 128);
+        mindist_pair r{};
+        r.j = jb->j;
+        r.w = jb->w;
+        r.L_before = (int)jb->L_before;
+        r.L_after = (int)jb->L_after;
+        r.U_after = (int)jb->U_after;
+        r.pair_min = jb->pair_min == kInf ? -1 : (int)jb->pair_min;
+        r.count = jb->count;
+        r.executed = jb->executed;
+        r.dwords = hc.D[jb->j];
+        r.split_a = jb->a;
+        trace.push_back(r);
+        executed += r.executed;
+        canonical += r.count;
+        out.exited_midpair = (jb->exit_flag && jb->executed < jb->count) ? 1 : 0;
+    }
+    out.pairs_visited = (int)trace.size();
+    if (!trace.empty()) {
+        out.j_last = trace.back().j;
+        out.w_last = trace.back().w;
+    }
+    out.L_final = (int)bc.L_final;
+    out.U_found = bc.U_found == kInf ? n + 1 : (int)bc.U_found;
+    out.d = (int)std::min<uint32_t>(bc.U_found, singleton);
+    out.executed_total = executed;
+    out.canonical_total = canonical;
+    if (bc.U_found != kInf) {
+        const Slot s = slots[bc.U_found];
+        if (s.pair < 1 || s.pair >= (uint32_t)bc.njobs)
+            return fail(MINDIST_E_HIP, "batch witness slot holds an invalid job index");
+        const BatchJob *jb = reinterpret_cast<const BatchJob *>(arena + (size_t)bc.job[s.pair] * 128);
+        const int a = jb->a, b = jb->b, j = jb->j;
+        int X[MINDIST_MAX_LEVEL + 1], Z[MINDIST_MAX_LEVEL + 1];
+        colex_unrank(s.rho, a, k, X);
+        colex_unrank(s.i, b, k, Z);
+        std::vector<int> rows(X, X + a);
+        for (int t = 0; t < b; ++t) rows.push_back(k - 1 - Z[t]);
+        std::sort(rows.begin(), rows.end());
+        if (std::adjacent_find(rows.begin(), rows.end()) != rows.end() || (int)rows.size() != jb->w)
+            return fail(MINDIST_E_HIP, "batch witness decodes to an invalid combination");
+        uint64_t word[MINDIST_MAX_WORDS] = {0};
+        for (int r : rows) {
+            for (int t = 0; t < hc.P.W; ++t) word[t] ^= hc.P.gamma[j][(size_t)r * hc.P.W + t];
+            out.witness_rows[r >> 6] |= 1ull << (r & 63);
+        }
+        int wt = 0;
+        for (int t = 0; t < hc.P.W; ++t) wt += __builtin_popcountll(word[t]);
+        if (wt != (int)bc.U_found)
+            return fail(MINDIST_E_HIP, "batch witness weight differs from the found weight");
+        std::memcpy(out.witness, word, sizeof(uint64_t) * hc.P.W);
+        out.witness_j = j;
+        out.witness_w = jb->w;
+    }
+    (void)B;
+    return MINDIST_OK;
+}
+
+// run fn(i) for i in [0, count) on up to `threads` host threads
+void parallel_for(int count, int threads, const std::function<void(int)> &fn) {
+    threads = std::max(1, std::min(threads, count));
+    if (threads == 1) {
+        for (int i = 0; i < count; ++i) fn(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::thread> pool;
+    for (int t = 0; t < threads; ++t)
+        pool.emplace_back([&]() {
+            for (int i; (i = next.fetch_add(1)) < count;) fn(i);
+        });
+    for (auto &th : pool) th.join();
+}
+
+int host_threads() {
+    const unsigned hw = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(hw ? hw : 1u, 16u));
+}
+
+}  // namespace md
+
+using namespace md;
+
+extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const int *k, int B,
+                                 mindist_result *out, mindist_batch_opts *opts) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!G || !n || !k || !out || B < 1) return fail(MINDIST_E_ARG, "bad batch arguments");
+    mindist_batch_opts dflt{};
+    mindist_batch_opts &o = opts ? *opts : dflt;
+    const uint32_t tile_min = o.tile_min > 0 ? (uint32_t)o.tile_min : 256u;
+    const uint32_t tile_max = o.tile_max > 0 ? (uint32_t)o.tile_max : 2048u;
+    const int bpc = o.blocks_per_cu > 0 ? o.blocks_per_cu : 4;
+    const uint64_t table_cap = (uint64_t)(o.table_kib > 0 ? o.table_kib : 8192) << 10;
+    const int jobs_per_code = o.jobs_per_code > 0 ? o.jobs_per_code : 96;
+    const bool use_graph = o.use_graph != 0 || opts == nullptr;
+
+    // host preprocessing
+    std::vector<HostCode> hc(B);
+    std::vector<int> status(B, 0);
+    std::vector<std::string> errs(B);
+    parallel_for(B, host_threads(), [&](int i) {
+        status[i] = prepare_code(G[i], n[i], k[i], table_cap, hc[i]);
+    });
+    const auto t_prep = std::chrono::steady_clock::now();
+    std::vector<int> live;
+    for (int i = 0; i < B; ++i)
+        if (status[i] == MINDIST_OK) live.push_back(i);
+    for (int i = 0; i < B; ++i)
+        if (status[i] != MINDIST_OK) {
+            std::memset(&out[i], 0, sizeof(out[i]));
+            out[i].d = status[i];
+            out[i].n = n[i];
+            out[i].k = k[i];
+        }
+    if (live.empty()) return fail(MINDIST_E_ARG, "no valid code in the batch");
+    const int L = (int)live.size();
+
+    // device layout: three regions, each code's pieces at running offsets
+    size_t rows_total = 0, tab_total = 0, slot_total = 0;
+    std::vector<size_t> ro(L), to(L), so(L);
+    int kmax = 1;
+    for (int s = 0; s < L; ++s) {
+        const HostCode &h = hc[live[s]];
+        ro[s] = rows_total;
+        to[s] = tab_total;
+        so[s] = slot_total;
+        rows_total += h.rows_bytes;
+        tab_total += h.tab_bytes;
+        slot_total += h.slot_bytes;
+        kmax = std::max(kmax, h.k);
+    }
+    const uint64_t arena_units = (uint64_t)L * jobs_per_code * job_bytes(kmax) / 128;
+    Engine eng;
+    int e = eng.init(L, rows_total, tab_total, slot_total, arena_units, o.stream);
+    if (e) return e;
+    parallel_for(L, host_threads(), [&](int s) {
+        SlotPlace pl{eng.d_rows + ro[s], eng.d_tabs + to[s], eng.d_slots + so[s]};
+        fill_slot(hc[live[s]], pl, eng.h_rows + ro[s], tile_max, (uint64_t)s + 1, eng.h_codes[s]);
+    });
+    e = eng.run(bpc, tile_min, tile_max, use_graph, o.deadline_s > 0 ? o.deadline_s : 0);
+    if (e) return e;
+    e = eng.fetch_all();
+    if (e) return e;
+    bool timed_out = false;
+    for (int s = 0; s < L; ++s)
+        if (eng.h_codes[s].status != kSlotDone && eng.h_codes[s].status >= 0) timed_out = true;
+    uint64_t executed = 0;
+    std::vector<std::vector<mindist_pair>> traces(L);
+    std::vector<int> drc(L, 0);
+    std::vector<std::string> derr(L);
+    parallel_for(L, host_threads(), [&](int s) {
+        const int i = live[s];
+        const Slot *slots = reinterpret_cast<const Slot *>(eng.h_slots + so[s]);
+        drc[s] = decode_code(hc[i], eng.h_codes[s], eng.h_arena, slots, out[i], traces[s]);
+        if (drc[s]) derr[s] = last_error_text();
+    });
+    for (int s = 0; s < L; ++s) {
+        executed += out[live[s]].executed_total;
+        if (drc[s] == MINDIST_E_HIP) return fail(MINDIST_E_HIP, derr[s]);
+    }
+    if (o.pairs_index) {
+        int64_t pos = 0;
+        std::vector<const std::vector<mindist_pair> *> by_code(B, nullptr);
+        for (int s = 0; s < L; ++s) by_code[live[s]] = &traces[s];
+        for (int i = 0; i < B; ++i) {
+            o.pairs_index[i] = pos;
+            if (by_code[i])
+                for (const auto &r : *by_code[i]) {
+                    if (o.pairs && pos < o.pairs_cap) o.pairs[pos] = r;
+                    ++pos;
+                }
+        }
+        o.pairs_index[B] = pos;
+    }
+    if (timed_out) return fail(MINDIST_E_TIMEOUT, "batch deadline reached before every code finished");
+    o.seconds_kernel = eng.kernel_seconds;
+    o.seconds_prep = std::chrono::duration<double>(t_prep - t0).count();
+    o.executed_total = executed;
+    o.seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return MINDIST_OK;
+}
+
+// ---------------------------------------------------------------------------
+namespace md {
+
+int Engine::init(int slots_, size_t rb, size_t tb, size_t sb, uint64_t au, int64_t user_stream,
+                 bool serving) {
+    slots = slots_;
+    rows_bytes = std::max<size_t>(rb, 256);
+    tab_bytes = std::max<size_t>(tb, 256);
+    slot_bytes = std::max<size_t>(sb, 256);
+    arena_units = std::max<uint64_t>(au, 64);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(MINDIST_E_HIP, "no HIP device");
+    cus = prop.multiProcessorCount;
+    d_codes = static_cast<BatchCode *>(dev_alloc(sizeof(BatchCode) * (size_t)slots));
+    d_g = static_cast<BatchGlobal *>(dev_alloc(sizeof(BatchGlobal)));
+    d_arena = static_cast<unsigned char *>(dev_alloc(arena_units * 128));
+    d_rows = static_cast<unsigned char *>(dev_alloc(rows_bytes));
+    d_tabs = static_cast<unsigned char *>(dev_alloc(tab_bytes));
+    d_slots = static_cast<unsigned char *>(dev_alloc(slot_bytes));
+    h_codes = static_cast<BatchCode *>(pinned_alloc(sizeof(BatchCode) * (size_t)slots));
+    h_g = static_cast<BatchGlobal *>(pinned_alloc(sizeof(BatchGlobal)));
+    h_rows = static_cast<unsigned char *>(pinned_alloc(rows_bytes));
+    h_slots = static_cast<unsigned char *>(pinned_alloc(slot_bytes));
+    if (!d_codes || !d_g || !d_arena || !d_rows || !d_tabs || !d_slots || !h_codes || !h_g ||
+        !h_rows || !h_slots)
+        return fail(MINDIST_E_NOMEM, "batch: device or pinned allocation failed");
+    if (serving) {
+        if (hipHostMalloc((void **)&h_done, sizeof(uint32_t) * (size_t)slots,
+                          hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+            hipHostMalloc((void **)&h_stop, 256, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
+            return fail(MINDIST_E_NOMEM, "server: pinned flag allocation failed");
+        std::memset(h_done, 0, sizeof(uint32_t) * (size_t)slots);
+        *h_stop = 0;
+    }
+    if (user_stream) {
+        stream = (hipStream_t)user_stream;
+        own_stream = false;
+    } else {
+        stream = stream_get();
+        own_stream = true;
+    }
+    e0 = event_get();
+    e1 = event_get();
+    if (!stream || !e0 || !e1) return fail(MINDIST_E_HIP, "batch: stream or event creation failed");
+    return MINDIST_OK;
+}
+
+int Engine::run(int blocks_per_cu, uint32_t tile_min, uint32_t tile_max, bool graph,
+                double deadline_s) {
+    std::memset(h_g, 0, sizeof(BatchGlobal));
+    h_g->arena_cap = arena_units;
+    BatchArgs a{};
+    a.codes = d_codes;
+    a.g = d_g;
+    a.arena = d_arena;
+    a.binom = device_binom_from(BN().t.data());
+    a.n_codes = slots;
+    a.serving = 0;
+    a.tile_min = tile_min;
+    a.tile_max = tile_max;
+    if (deadline_s > 0) {
+        int khz = 0;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+            khz = 100000;
+        a.deadline_ticks = (uint64_t)(deadline_s * khz * 1000.0);
+    }
+    if (!a.binom) return fail(MINDIST_E_NOMEM, "binomial table upload failed");
+    const int blocks = cus * blocks_per_cu;
+    auto enqueue = [&]() -> int {
+        if (hipMemcpyAsync(d_codes, h_codes, sizeof(BatchCode) * (size_t)slots, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(d_g, h_g, sizeof(BatchGlobal), hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(d_rows, h_rows, rows_bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+            return fail(MINDIST_E_HIP, "batch: upload failed");
+        if (launch_persistent(a, blocks, stream)) return fail(MINDIST_E_HIP, "batch: launch failed");
+        return MINDIST_OK;
+    };
+    if (graph) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(MINDIST_E_HIP, "batch: graph capture failed to start");
+        int e = enqueue();
+        const hipError_t ec = hipStreamEndCapture(stream, &g);
+        if (e) { if (g) (void)hipGraphDestroy(g); return e; }
+        if (ec != hipSuccess || hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(MINDIST_E_HIP, "batch: graph capture failed");
+        }
+        const bool ok = hipEventRecord(e0, stream) == hipSuccess &&
+                        hipGraphLaunch(ge, stream) == hipSuccess &&
+                        hipEventRecord(e1, stream) == hipSuccess &&
+                        hipStreamSynchronize(stream) == hipSuccess;
+        (void)hipGraphExecDestroy(ge);
+        (void)hipGraphDestroy(g);
+        if (!ok) return fail(MINDIST_E_HIP, std::string("batch: graph launch failed: ") +
+                                                hipGetErrorString(hipGetLastError()));
+    } else {
+        if (hipEventRecord(e0, stream) != hipSuccess) return fail(MINDIST_E_HIP, "event record failed");
+        int e = enqueue();
+        if (e) return e;
+        if (hipEventRecord(e1, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
+            return fail(MINDIST_E_HIP, std::string("batch: kernel failed: ") +
+                                           hipGetErrorString(hipGetLastError()));
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    kernel_seconds = ms * 1e-3;
+    return MINDIST_OK;
+}
+
+int Engine::fetch_all() {
+    if (hipMemcpyAsync(h_codes, d_codes, sizeof(BatchCode) * (size_t)slots, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(h_g, d_g, sizeof(BatchGlobal), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(h_slots, d_slots, slot_bytes, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return fail(MINDIST_E_HIP, "batch: readback failed");
+    const uint64_t used = std::min<uint64_t>(h_g->arena_next, arena_units) * 128;
+    arena_host.resize(std::max<uint64_t>(used, 128));
+    if (used && hipMemcpy(arena_host.data(), d_arena, used, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(MINDIST_E_HIP, "batch: job readback failed");
+    h_arena = arena_host.data();
+    return MINDIST_OK;
+}
+
+Engine::~Engine() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    dev_free(d_codes);
+    dev_free(d_g);
+    dev_free(d_arena);
+    dev_free(d_rows);
+    dev_free(d_tabs);
+    dev_free(d_slots);
+    pinned_free(h_codes);
+    pinned_free(h_g);
+    pinned_free(h_rows);
+    pinned_free(h_slots);
+    if (h_done) (void)hipHostFree(h_done);
+    if (h_stop) (void)hipHostFree(h_stop);
+    event_put(e0);
+    event_put(e1);
+    if (own_stream) stream_put(stream);
+}
+
+}  // namespace md

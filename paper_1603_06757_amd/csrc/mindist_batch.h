@@ -1,0 +1,100 @@
+// mindist_batch.h -- the device-side scheduler shared by mindist_run_batch and
+// the server: many codes in one persistent launch.
+//
+// Every code slot goes through
+//   PENDING -> (a wave opens the table job) -> TABLES -> pair 1 -> pair 2 ... -> DONE
+// on the device.  A "job" is a record with a chunk dispenser (claim), a
+// completion counter (done) and the number of chunks that will complete
+// (expected).  Waves pick a code, claim a chunk of its open job, run it, and
+// the wave that completes a job's last chunk opens the code's next job: the
+// next pair of Algorithm 1 in canonical order (w ascending, j ascending,
+// partial set last), or DONE once L >= U.  The job records live in an arena
+// and are never reused within a launch, so a wave that claims on a job that
+// has closed simply gets an index past its end.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include "mindist_internal.h"
+
+namespace md {
+
+constexpr int kBatchMaxSets = 32;     // information sets per code
+constexpr int kBatchMaxB = 4;         // right tables b = 0..4 per set
+constexpr int kBatchMaxPairs = 256;   // jobs per code (table job + pairs)
+constexpr int kBatchMaxD = 8;         // 32-bit words carried per row (n <= 256)
+constexpr int kBatchItems = 2;        // left subsets per lane
+constexpr int kTableChunk = 4096;     // table entries per table-job chunk
+constexpr int kBatchTabs = kBatchMaxSets * (kBatchMaxB + 1);
+
+enum : int32_t {
+    kSlotActive = 0,
+    kSlotDone = 1,
+    kSlotPending = 2,
+    kSlotOpening = 3,
+    kSlotEmpty = 4,
+    // negative values: MINDIST_E_* errors
+};
+
+struct BatchSet {
+    const uint32_t *rows;                  // k x dp
+    uint32_t *rtab[kBatchMaxB + 1];        // right tables b = 0..bcap (built on device)
+    int32_t D, dp, stripped, bcap;
+};
+
+// one job of a code; GroupEntry groups[ngroups] follow the struct
+struct alignas(128) BatchJob {
+    int32_t kind;                 // 0 = table job, 1 = enumeration pair
+    int32_t j, w, a, b;
+    uint32_t T, L_before, offset, ngroups;
+    uint32_t pad_a;
+    uint64_t n_items, total_chunks, count;
+    uint32_t pair_min, exit_flag, L_after, U_after;
+    uint64_t executed;
+    uint64_t expected;            // chunks that complete before the job closes
+    uint64_t pad_b[5];
+    alignas(128) uint64_t claim;  // chunk dispenser
+    uint64_t pad_c[15];
+    alignas(128) uint64_t done;   // completed chunks
+    uint64_t pad_d[15];
+};
+
+struct BatchCode {
+    int32_t n, k, m_full, k_m, n_gamma, W;
+    int32_t status;               // kSlot* or a negative error
+    int32_t njobs;                // jobs opened (the open one is njobs-1)
+    uint32_t U_found;             // least weight found (kInf = none)
+    uint32_t tile_cap;            // largest right tile for this code
+    uint32_t L_final, U_final;
+    uint64_t seq;                 // submission sequence number (server)
+    uint32_t job[kBatchMaxPairs]; // arena offsets (128-byte units) of the jobs
+    Slot *slots;                  // n+1 witness slots
+    uint64_t tab_off[kBatchTabs + 1];   // table entries before table t (t = j*(B+1)+b)
+    BatchSet sets[kBatchMaxSets];
+};
+
+struct BatchGlobal {
+    uint32_t codes_done;          // batch: codes finished (done or error)
+    uint32_t pad0;
+    uint64_t arena_next;          // 128-byte units handed out
+    uint64_t arena_cap;
+    uint64_t pad1[13];
+};
+
+struct BatchArgs {
+    BatchCode *codes;
+    BatchGlobal *g;
+    unsigned char *arena;
+    const uint64_t *binom;
+    uint32_t *host_done;          // serving: per slot completion word in pinned host memory
+    const uint32_t *host_stop;    // serving: set by the host to end the launch
+    int32_t n_codes;              // code slots
+    int32_t serving;              // 0: end when every code is done; 1: end on host_stop
+    uint32_t tile_min;            // right tile length bounds
+    uint32_t tile_max;
+    uint64_t deadline_ticks;      // wall-clock ticks after which every wave leaves (0 = none)
+};
+
+int launch_persistent(const BatchArgs &a, int blocks, void *stream);
+
+}  // namespace md

@@ -1,0 +1,454 @@
+// mindist_batch.hip -- the persistent multi-code kernel (see mindist_batch.h).
+//
+// Waves walk the code slots, claim one chunk at a time from a code's open
+// job and stay on that code while it has chunks.  Jobs:
+//   * table job: the code's saved right sums (Section 3.4), 4096 entries per
+//     chunk;
+//   * pair (Gamma_j, w): the same left/right enumeration as the single-code
+//     kernel (two left subsets per lane, left subsets unranked per lane).
+// The wave that completes a job's last chunk applies Algorithm 1's control
+// for that code: L after the pair (one raise per Gamma_j), the test L >= U,
+// and opens the next pair or marks the code done.
+#include <hip/hip_runtime.h>
+
+#include "mindist_batch.h"
+#include "mindist_device.h"
+
+namespace md {
+namespace {
+
+__device__ __forceinline__ uint32_t ld_acq(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_acq(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_acq(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_rlx(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(int32_t *p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// lane 0 does the atomic, every lane gets the (uniform) result
+__device__ __forceinline__ uint64_t wave_fetch_add(uint64_t *p, uint64_t v) {
+    uint64_t r = 0;
+    if ((threadIdx.x & 63) == 0) r = atomicAdd((unsigned long long *)p, (unsigned long long)v);
+    return uni64((uint64_t)__shfl((long long)r, 0));
+}
+
+__device__ __forceinline__ GroupEntry *job_groups(BatchJob *jb) {
+    return reinterpret_cast<GroupEntry *>(jb + 1);
+}
+__device__ __forceinline__ BatchJob *job_at(const BatchArgs &A, uint32_t off) {
+    return reinterpret_cast<BatchJob *>(A.arena + (size_t)off * 128);
+}
+
+__device__ int bound_f_dev(int i, int h, int m_full, int k, int k_m) {
+    if (i < m_full) return h + 1;
+    const int v = h + 1 - (k - k_m);
+    return v > 0 ? v : 0;
+}
+// L after pair (j, w): one raise per Gamma_j (Section 2)
+__device__ int bound_after_dev(int k, int m_full, int k_m, int ng, int j, int w) {
+    int s = 0;
+    for (int i = 0; i < ng; ++i) s += bound_f_dev(i, i <= j ? w : w - 1, m_full, k, k_m);
+    return s;
+}
+
+// Allocate a job record with room for `ngroups_cap` group entries; returns
+// its arena offset or 0xFFFFFFFF when the arena is full.
+__device__ uint32_t alloc_job(const BatchArgs &A, int ngroups_cap) {
+    const uint64_t bytes = sizeof(BatchJob) + sizeof(GroupEntry) * (uint64_t)ngroups_cap;
+    const uint64_t units = (bytes + 127) / 128;
+    const uint64_t off = wave_fetch_add(&A.g->arena_next, units);
+    if (off + units > A.g->arena_cap || off + units > 0xFFFFFFFFull) return 0xFFFFFFFFu;
+    return (uint32_t)off;
+}
+
+__device__ void finish_code(const BatchArgs &A, int c, int32_t status, uint32_t L, uint32_t U) {
+    BatchCode *cs = &A.codes[c];
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) {
+        cs->L_final = L;
+        cs->U_final = U;
+    }
+    __threadfence();
+    if (lane == 0) {
+        st_rel(&cs->status, status);
+        atomicAdd(&A.g->codes_done, 1u);
+        if (A.host_done) {
+            __threadfence_system();
+            __hip_atomic_store(&A.host_done[c], (uint32_t)cs->seq, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+}
+
+// Open pair (j, w) as job p of code c (whole wave).  Mirrors the host's
+// plan: b = min(w/2, bcap_j), a = w - b, left tiles of 64*kBatchItems
+// subsets grouped by the largest element e of their first subset.
+__device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32_t L_before) {
+    BatchCode *cs = &A.codes[c];
+    const int lane = threadIdx.x & 63;
+    const int k = cs->k;
+    const BatchSet &set = cs->sets[j];
+    const int b = min(w / 2, set.bcap), a = w - b;
+    const uint64_t TB = 64ull * kBatchItems;
+    const uint64_t n_items = binom(A.binom, k - b, a);
+    const uint64_t tiles = (n_items + TB - 1) / TB;
+    // right tile: about 4 chunks per resident wave for this pair alone,
+    // between the configured bounds (pairs of many codes run side by side)
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t want = binom(A.binom, k, w) / (TB * waves * 4 + 1);
+    uint32_t T = A.tile_min;
+    while (T < A.tile_max && T < cs->tile_cap && T < want) T <<= 1;
+    const uint32_t off = alloc_job(A, k + 2);
+    if (off == 0xFFFFFFFFu) {
+        finish_code(A, c, -5 /* MINDIST_E_LIMIT */, L_before, min(cs->U_found, (uint32_t)(cs->n - k + 1)));
+        return;
+    }
+    BatchJob *jb = job_at(A, off);
+    GroupEntry *gr = job_groups(jb);
+    // groups: one lane per candidate e, compacted with wave prefix sums
+    const int e_lo = a - 1, e_hi = k - 1 - b;
+    uint64_t chunk_base = 0;
+    uint32_t ng = 0;
+    for (int e0 = e_lo; e0 <= e_hi; e0 += 64) {
+        const int e = e0 + lane;
+        uint64_t chunks = 0, lt_lo = 0;
+        uint32_t nr_first = 0;
+        uint64_t n_rt = 0;
+        if (e <= e_hi) {
+            const uint64_t lo = binom(A.binom, e, a), hi = binom(A.binom, e + 1, a);
+            lt_lo = (lo + TB - 1) / TB;
+            uint64_t lt_hi = (hi + TB - 1) / TB;
+            if (lt_hi > tiles) lt_hi = tiles;
+            if (lt_hi > lt_lo) {
+                nr_first = (uint32_t)binom(A.binom, k - 1 - e, b);
+                n_rt = (nr_first + T - 1) / T;
+                chunks = (lt_hi - lt_lo) * n_rt;
+            }
+        }
+        const bool has = chunks > 0;
+        // exclusive prefix over lanes of (has) and (chunks)
+        uint64_t inc_c = chunks;
+        uint32_t inc_n = has ? 1u : 0u;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t yc = (uint64_t)__shfl_up((long long)inc_c, o);
+            const uint32_t yn = (uint32_t)__shfl_up((int)inc_n, o);
+            if (lane >= o) { inc_c += yc; inc_n += yn; }
+        }
+        if (has) {
+            GroupEntry &ge = gr[ng + inc_n - 1];
+            ge.chunk_base = chunk_base + inc_c - chunks;
+            ge.lt_begin = lt_lo;
+            ge.n_rt = n_rt;
+            ge.nr_first = nr_first;
+            ge.e = (uint32_t)e;
+        }
+        chunk_base += uni64((uint64_t)__shfl((long long)inc_c, 63));
+        ng += uni32((uint32_t)__shfl((int)inc_n, 63));
+    }
+    if (chunk_base == 0) {        // cannot happen for w <= k; never leave a job nobody can close
+        finish_code(A, c, -4 /* MINDIST_E_HIP */, L_before, min(cs->U_found, (uint32_t)(cs->n - k + 1)));
+        return;
+    }
+    if (lane == 0) {
+        jb->kind = 1;
+        jb->j = j;
+        jb->w = w;
+        jb->a = a;
+        jb->b = b;
+        jb->T = T;
+        jb->L_before = L_before;
+        jb->offset = set.stripped ? (uint32_t)w : 0u;
+        jb->ngroups = ng;
+        jb->n_items = n_items;
+        jb->total_chunks = chunk_base;
+        jb->count = binom(A.binom, k, w);
+        jb->pair_min = kInf;
+        jb->exit_flag = 0;
+        jb->L_after = 0;
+        jb->U_after = 0;
+        jb->executed = 0;
+        jb->expected = chunk_base;
+        jb->claim = 0;
+        jb->done = 0;
+        cs->job[p] = off;
+    }
+    __threadfence();     // the group entries of every lane, then the record
+    if (lane == 0) st_rel(&cs->njobs, p + 1);
+}
+
+// The table job (job 0): every right table of every set of the code.
+__device__ void open_tables(const BatchArgs &A, int c) {
+    BatchCode *cs = &A.codes[c];
+    const uint32_t off = alloc_job(A, 0);
+    if (off == 0xFFFFFFFFu) {
+        finish_code(A, c, -5, 1, (uint32_t)(cs->n - cs->k + 1));
+        return;
+    }
+    BatchJob *jb = job_at(A, off);
+    if ((threadIdx.x & 63) == 0) {
+        const uint64_t E = cs->tab_off[kBatchTabs];
+        jb->kind = 0;
+        jb->j = -1;
+        jb->total_chunks = (E + kTableChunk - 1) / kTableChunk;
+        jb->expected = jb->total_chunks;
+        jb->claim = 0;
+        jb->done = 0;
+        jb->executed = 0;
+        jb->pair_min = kInf;
+        cs->job[0] = off;
+    }
+    __threadfence();
+    if ((threadIdx.x & 63) == 0) {
+        st_rel(&cs->njobs, 1);
+        st_rel(&cs->status, (int32_t)kSlotActive);
+    }
+}
+
+// Chunk ch of the table job: entries [ch*4096, ...) of the flattened list.
+__device__ void table_chunk(const BatchArgs &A, BatchCode *cs, uint64_t ch) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t E = cs->tab_off[kBatchTabs];
+    const int k = cs->k;
+    for (int r = 0; r < kTableChunk / 64; ++r) {
+        const uint64_t idx = ch * kTableChunk + (uint64_t)r * 64 + lane;
+        if (idx >= E) break;
+        int lo = 0, hi = kBatchTabs - 1;   // last t with tab_off[t] <= idx
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cs->tab_off[mid] <= idx) lo = mid; else hi = mid - 1;
+        }
+        const int j = lo / (kBatchMaxB + 1), b = lo % (kBatchMaxB + 1);
+        const BatchSet &set = cs->sets[j];
+        uint64_t i = idx - cs->tab_off[lo];
+        uint32_t acc[kBatchMaxD];
+        for (int d = 0; d < kBatchMaxD; ++d) acc[d] = 0;
+        // entry i = rows {k-1-z : z in colex_unrank_b(i)}
+        int top = k;
+        for (int t = b; t >= 1; --t) {
+            int l = t - 1, h = top - 1;
+            while (l < h) {
+                const int mid = (l + h + 1) >> 1;
+                if (binom(A.binom, mid, t) <= i) l = mid; else h = mid - 1;
+            }
+            i -= binom(A.binom, l, t);
+            top = l;
+            const uint32_t *row = set.rows + (size_t)(k - 1 - l) * set.dp;
+            for (int d = 0; d < set.D; ++d) acc[d] ^= row[d];
+        }
+        uint32_t *out = set.rtab[b] + (size_t)(idx - cs->tab_off[lo]) * set.dp;
+        for (int d = 0; d < set.dp; ++d) out[d] = d < set.D ? acc[d] : 0u;
+    }
+}
+
+// One chunk of pair job p of code c.
+template <int D>
+__device__ void pair_chunk(const BatchArgs &A, int c, int p, BatchJob *jb, uint64_t ch) {
+    BatchCode *cs = &A.codes[c];
+    const int lane = threadIdx.x & 63;
+    const int j = (int)uni32((uint32_t)jb->j);
+    const int a = (int)uni32((uint32_t)jb->a), b = (int)uni32((uint32_t)jb->b);
+    const int k = (int)uni32((uint32_t)cs->k);
+    const BatchSet &set = cs->sets[j];
+    const uint32_t *rows = (const uint32_t *)uni64((uint64_t)set.rows);
+    const uint32_t *tab = (const uint32_t *)uni64((uint64_t)set.rtab[b]);
+    const uint64_t n_items = uni64(jb->n_items);
+    const uint32_t T = uni32(jb->T), offset = uni32(jb->offset), Lb = uni32(jb->L_before);
+    const int ngroups = (int)uni32(jb->ngroups);
+    const GroupEntry *gr = job_groups(jb);
+    // group of chunk ch: last group whose chunk_base <= ch
+    int lo = 0, hi = ngroups - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (uni64(gr[mid].chunk_base) <= ch) lo = mid; else hi = mid - 1;
+    }
+    const uint64_t base = uni64(gr[lo].chunk_base), n_rt = uni64(gr[lo].n_rt);
+    const uint64_t offc = ch - base;
+    ChunkGeo g;
+    g.lt = uni64(gr[lo].lt_begin) + offc / n_rt;
+    g.i_begin = (uint32_t)(offc % n_rt) * T;
+    g.i_end = min(g.i_begin + T, uni32(gr[lo].nr_first));
+    g.e_first = uni32(gr[lo].e);
+    g.clip = false;
+    const ItemSrc src{rows, tab, nullptr, A.binom, A.binom + a, A.binom + b, kBinomT, kBinomT,
+                      n_items, k, a, b};
+    uint32_t L[kBatchItems][D], nr[kBatchItems], lmin, ws;
+    uint64_t cnt;
+    run_chunk<D, kBatchItems, false>(src, g, L, nr, lmin, cnt, ws);
+    const uint32_t wmin = wave_min_u32(lmin);
+    const uint64_t wcnt = wave_sum_u64(cnt);
+    if (lane == 0) {
+        atomicAdd((unsigned long long *)&jb->executed, (unsigned long long)wcnt);
+        if (wmin != kInf) atomicMin(&jb->pair_min, wmin + offset);
+    }
+    if (wmin == kInf) return;
+    const uint32_t val = wmin + offset;
+    if (val >= uni32(ld_rlx(&cs->U_found))) return;
+    uint32_t old = 0;
+    if (lane == 0) old = atomicMin(&cs->U_found, val);
+    old = uni32((uint32_t)__shfl((int)old, 0));
+    if (old > val) {
+        uint32_t hit_i;
+        uint64_t hit_rho;
+        const int first = find_witness<D, kBatchItems>(src, g, L, nr, wmin, hit_i, hit_rho);
+        if (lane == first) {
+            cs->slots[val].pair = (uint32_t)p;
+            cs->slots[val].i = hit_i;
+            cs->slots[val].rho = hit_rho;
+        }
+    }
+    if (val <= Lb && lane == 0) {
+        // U reached the bound before this pair: stop handing out its chunks;
+        // the pair closes once the chunks already claimed are done
+        if (atomicExch(&jb->exit_flag, 1u) == 0u) {
+            const uint64_t claimed = atomicExch((unsigned long long *)&jb->claim, 1ull << 62);
+            const uint64_t total = jb->total_chunks;
+            st_rel(&jb->expected, claimed < total ? claimed : total);
+        }
+    }
+}
+
+// Job p of code c has completed: Algorithm 1's control for that code.
+__device__ void advance(const BatchArgs &A, int c, int p, BatchJob *jb) {
+    BatchCode *cs = &A.codes[c];
+    __threadfence();
+    const int k = cs->k, n = cs->n, ng = cs->n_gamma;
+    const uint32_t singleton = (uint32_t)(n - k + 1);
+    if (jb->kind == 0) {           // tables built: first pair, L = 1 (Algorithm 1)
+        open_pair(A, c, p + 1, 0, 1, 1u);
+        return;
+    }
+    const int j = jb->j, w = jb->w;
+    const uint32_t Uf = ld_acq(&cs->U_found);
+    const uint64_t executed = ld_acq(&jb->executed);
+    const bool cut = ld_acq(&jb->exit_flag) && executed < jb->count;
+    const uint32_t L = cut ? jb->L_before
+                           : (uint32_t)bound_after_dev(k, cs->m_full, cs->k_m, ng, j, w);
+    const uint32_t U = min(Uf, singleton);
+    if ((threadIdx.x & 63) == 0) {
+        jb->L_after = L;
+        jb->U_after = U;
+    }
+    if (cut) { finish_code(A, c, kSlotDone, L, U); return; }
+    int j2 = j + 1, w2 = w;
+    if (j2 >= ng) { j2 = 0; w2 = w + 1; }
+    if (w2 > k || L >= U) { finish_code(A, c, kSlotDone, L, U); return; }
+    if (p + 1 >= kBatchMaxPairs || w2 > 64 || binom(A.binom, k, w2) >= (1ull << 63)) {
+        finish_code(A, c, -5 /* MINDIST_E_LIMIT */, L, U);
+        return;
+    }
+    open_pair(A, c, p + 1, j2, w2, L);
+}
+
+__device__ void complete_chunk(const BatchArgs &A, int c, int p, BatchJob *jb) {
+    __threadfence();
+    uint64_t prev = 0, expected = 0;
+    if ((threadIdx.x & 63) == 0) {
+        prev = atomicAdd((unsigned long long *)&jb->done, 1ull);
+        __threadfence();
+        expected = ld_acq(&jb->expected);
+    }
+    prev = uni64((uint64_t)__shfl((long long)prev, 0));
+    expected = uni64((uint64_t)__shfl((long long)expected, 0));
+    if (prev + 1 == expected) advance(A, c, p, jb);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void persistent_batch_kernel(BatchArgs A) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = uni32(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const int nc = A.n_codes;
+    int cur = (int)(wave % (uint32_t)nc);
+    const uint64_t t_start = wall_clock64();
+    for (;;) {
+        if (A.deadline_ticks && wall_clock64() - t_start > A.deadline_ticks) break;
+        if (A.serving) {
+            const uint32_t stop = A.host_stop ? __hip_atomic_load(A.host_stop, __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_SYSTEM)
+                                              : 1u;
+            if (uni32(stop)) break;
+        } else if (uni32(ld_rlx(&A.g->codes_done)) >= (uint32_t)nc) {
+            break;
+        }
+        // find a code with an open job: look at 64 slots at once from cur
+        bool found = false;
+        int c = cur;
+        int32_t st = 0;
+        {
+            const int probe = (cur + lane) % nc;
+            const int32_t s = ld_acq(&A.codes[probe].status);
+            const bool live = s == kSlotActive || s == kSlotPending;
+            const unsigned long long ball = __ballot(live);
+            if (ball) {
+                // start from this wave's own rotation among the live ones
+                const int pick = __builtin_ctzll(ball);
+                c = (cur + pick) % nc;
+                st = (int32_t)uni32((uint32_t)__shfl(s, pick));
+                found = true;
+            }
+        }
+        if (!found) {
+            cur = (cur + 64) % nc;
+            __builtin_amdgcn_s_sleep(4);
+            continue;
+        }
+        BatchCode *cs = &A.codes[c];
+        if (st == kSlotPending) {
+            // first wave to see the slot opens its table job
+            int32_t won = 0;
+            if (lane == 0)
+                won = atomicCAS(&cs->status, (int32_t)kSlotPending, (int32_t)kSlotOpening) == kSlotPending;
+            if (uni32((uint32_t)__shfl(won, 0))) open_tables(A, c);
+            continue;
+        }
+        const int nj = (int)uni32((uint32_t)ld_acq(&cs->njobs));
+        if (nj <= 0) { cur = (c + 1) % nc; continue; }
+        const int p = nj - 1;
+        BatchJob *jb = job_at(A, uni32(ld_acq(&cs->job[p])));
+        const uint64_t ch = wave_fetch_add(&jb->claim, 1ull);
+        if (ch >= uni64(jb->total_chunks)) {   // nothing left to claim: look elsewhere
+            cur = (c + 1) % nc;
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        cur = c;                               // stay while the code has chunks
+        if (jb->kind == 0) {
+            table_chunk(A, cs, ch);
+        } else {
+            const int D = cs->sets[uni32((uint32_t)jb->j)].D;
+            switch (uni32((uint32_t)D)) {
+                case 1: pair_chunk<1>(A, c, p, jb, ch); break;
+                case 2: pair_chunk<2>(A, c, p, jb, ch); break;
+                case 3: pair_chunk<3>(A, c, p, jb, ch); break;
+                case 4: pair_chunk<4>(A, c, p, jb, ch); break;
+                case 5: pair_chunk<5>(A, c, p, jb, ch); break;
+                case 6: pair_chunk<6>(A, c, p, jb, ch); break;
+                case 7: pair_chunk<7>(A, c, p, jb, ch); break;
+                default: pair_chunk<8>(A, c, p, jb, ch); break;
+            }
+        }
+        complete_chunk(A, c, p, jb);
+    }
+}
+
+int launch_persistent(const BatchArgs &a, int blocks, void *stream) {
+    hipLaunchKernelGGL(persistent_batch_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace md

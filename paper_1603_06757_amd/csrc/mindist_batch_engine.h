@@ -1,0 +1,72 @@
+// mindist_batch_engine.h -- host-side pieces of the persistent multi-code
+// path, shared by mindist_run_batch and the server.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/mindist.h"
+#include "mindist_batch.h"
+#include "mindist_plan.h"
+
+namespace md {
+
+const char *last_error_text();
+
+// one code prepared on the host
+struct HostCode {
+    int n = 0, k = 0, n_gamma = 0;
+    Plan P;
+    std::vector<int> D, dp, bcap;               // per set
+    std::vector<std::vector<uint32_t>> rows;    // per set, k x dp packed words
+    size_t rows_bytes = 0, tab_bytes = 0, slot_bytes = 0;
+};
+
+// where a slot's pieces live on the device
+struct SlotPlace {
+    unsigned char *rows, *tabs, *slots;
+};
+
+int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &hc);
+void fill_slot(const HostCode &hc, const SlotPlace &pl, unsigned char *rows_stage,
+               uint32_t tile_cap, uint64_t seq, BatchCode &bc);
+int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *arena,
+                const Slot *slots, mindist_result &out, std::vector<mindist_pair> &trace);
+size_t job_bytes(int k);
+void parallel_for(int count, int threads, const std::function<void(int)> &fn);
+int host_threads();
+
+// device buffers and launch of the persistent kernel over `slots` codes
+struct Engine {
+    int slots = 0;
+    int cus = 256;
+    BatchCode *d_codes = nullptr;
+    BatchGlobal *d_g = nullptr;
+    unsigned char *d_arena = nullptr, *d_rows = nullptr, *d_tabs = nullptr, *d_slots = nullptr;
+    size_t rows_bytes = 0, tab_bytes = 0, slot_bytes = 0;
+    uint64_t arena_units = 0;
+    BatchCode *h_codes = nullptr;       // pinned mirrors
+    BatchGlobal *h_g = nullptr;
+    unsigned char *h_rows = nullptr, *h_slots = nullptr, *h_arena = nullptr;
+    uint32_t *h_done = nullptr, *h_stop = nullptr;   // serving: host-visible flags
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double kernel_seconds = 0;
+    std::vector<unsigned char> arena_host;
+
+    int init(int slots, size_t rows_bytes, size_t tab_bytes, size_t slot_bytes,
+             uint64_t arena_units, int64_t user_stream, bool serving = false);
+    // upload every slot descriptor, the rows and the global state; launch the
+    // persistent kernel (inside one captured hipGraph when graph is set) and
+    // wait for it
+    int run(int blocks_per_cu, uint32_t tile_min, uint32_t tile_max, bool graph,
+            double deadline_s = 0);
+    // read back the descriptors, the used part of the job arena and the slots
+    int fetch_all();
+    ~Engine();
+};
+
+}  // namespace md

@@ -1,0 +1,296 @@
+// mindist_device.h -- device helpers shared by the enumeration kernels: the
+// per-chunk work of one pair (left subsets per lane, right sums by scalar
+// loads, one XOR + popcount per carried word) and the witness search.
+//
+// Per codeword the hot loop issues D x v_xor_b32 (lane row sum ^ scalar
+// right sum), D x v_bcnt_u32_b32 (accumulating popcount) and one v_min_u32.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mindist_internal.h"
+
+namespace md {
+
+typedef const __attribute__((address_space(4))) uint32_t cu32;
+
+__host__ __device__ constexpr int dp_of(int D) {
+    return D <= 1 ? 1 : D <= 2 ? 2 : D <= 4 ? 4 : D <= 8 ? 8 : 16;
+}
+
+__device__ __forceinline__ uint64_t binom(const uint64_t *bt, int x, int t) {
+    return (x < 0 || t < 0 || t > x) ? 0ull : bt[x * kBinomT + t];
+}
+
+__device__ __forceinline__ uint32_t uni32(uint32_t v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+    return uni32(v);
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+    return uni32(v);
+}
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += (uint64_t)__shfl_xor((long long)v, o);
+    return uni64(v);
+}
+
+// Colex unranking: the a-subset {x_1 < ... < x_a} of [0, hi) with
+// sum_t C(x_t, t) = rho.  Adds the rows of the subset into acc and returns
+// the largest element.
+template <int D>
+__device__ __forceinline__ int unrank_add(const uint64_t *bt, const uint32_t *rows, int dp,
+                                          uint64_t rho, int a, int hi, uint32_t (&acc)[D],
+                                          bool reflect, int k) {
+    int top = -1;
+    for (int t = a; t >= 1; --t) {
+        int lo = t - 1, h = hi - 1;
+        while (lo < h) {
+            int mid = (lo + h + 1) >> 1;
+            if (binom(bt, mid, t) <= rho) lo = mid; else h = mid - 1;
+        }
+        rho -= binom(bt, lo, t);
+        hi = lo;
+        if (top < 0) top = lo;
+        const int r = reflect ? (k - 1 - lo) : lo;
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc[d] ^= rows[(size_t)r * dp + d];
+    }
+    return top;
+}
+
+// v_bcnt_u32_b32 with its accumulator operand: popcount(x) + acc in one
+// instruction (the compiler would otherwise sum separate popcounts with
+// v_add3, one more instruction per codeword).
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
+template <int D>
+__device__ __forceinline__ uint32_t weight_of(const uint32_t (&L)[D], const uint32_t (&s)[D]) {
+    uint32_t w = __builtin_popcount(L[0] ^ s[0]);
+#pragma unroll
+    for (int d = 1; d < D; ++d) w = bcnt_acc(L[d] ^ s[d], w);
+    return w;
+}
+
+// A right-table entry is dp_of(D) words; it is fetched whole (the padding
+// word of D = 3 included) so one scalar load brings one entry.
+template <int DP> struct Entry { uint32_t w[DP]; };
+template <> struct Entry<4> {
+    typedef uint32_t v4 __attribute__((ext_vector_type(4)));
+    v4 v;
+};
+template <int D>
+__device__ __forceinline__ void load_entry(cu32 *ct, uint32_t i, uint32_t (&s)[D]) {
+    constexpr int DP = dp_of(D);
+    if constexpr (DP == 4) {
+        typedef const __attribute__((address_space(4))) Entry<4>::v4 cv4;
+        const Entry<4>::v4 v = ((cv4 *)ct)[i];
+        s[0] = v.x;
+        if constexpr (D > 1) s[1] = v.y;
+        if constexpr (D > 2) s[2] = v.z;
+        if constexpr (D > 3) s[3] = v.w;
+    } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d) s[d] = ct[(size_t)i * DP + d];
+    }
+}
+
+// right-table entries per pipelined block (two blocks live in SGPRs)
+template <int D>
+__host__ __device__ constexpr int block_of() { return dp_of(D) <= 4 ? 4 : dp_of(D) <= 8 ? 2 : 1; }
+
+// One right-table entry against the B lane items.
+//   PRED: mask item t once i >= nr[t] (its right range ended)
+//   SUM : accumulate weights (verify mode); vm[t] = 0 drops a clamped
+//         duplicate item from the sum
+template <int D, int B, bool PRED, bool SUM>
+__device__ __forceinline__ void step(const uint32_t (&s)[D], uint32_t i, const uint32_t (&L)[B][D],
+                                     const uint32_t (&nr)[B], const uint32_t (&vm)[B],
+                                     uint32_t (&m)[B], uint32_t &ws) {
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+        uint32_t w = weight_of<D>(L[t], s);
+        if (PRED) {
+            const bool on = i < nr[t];
+            if (SUM) ws += on ? (w & vm[t]) : 0u;
+            w = on ? w : kInf;
+        } else if (SUM) {
+            ws += w & vm[t];
+        }
+        m[t] = min(m[t], w);
+    }
+}
+
+// Run right-table entries [i0, i1) against the B lane items.  The uniform
+// entries come in by scalar loads; the next block is requested before the
+// current one is consumed so the load latency overlaps the VALU work.
+template <int D, int B, bool PRED, bool SUM>
+__device__ __forceinline__ void run_range(const uint32_t *tab, uint32_t i0, uint32_t i1,
+                                          const uint32_t (&L)[B][D], const uint32_t (&nr)[B],
+                                          const uint32_t (&vm)[B], uint32_t (&m)[B],
+                                          uint32_t &ws) {
+    constexpr int U = block_of<D>();
+    cu32 *ct = (cu32 *)tab;
+    uint32_t i = i0;
+    if (i1 - i0 >= 2 * U) {
+        uint32_t cur[U][D], nxt[U][D];
+#pragma unroll
+        for (int u = 0; u < U; ++u) load_entry<D>(ct, i + u, cur[u]);
+        for (; i + 2 * U <= i1; i += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) load_entry<D>(ct, i + U + u, nxt[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) step<D, B, PRED, SUM>(cur[u], i + u, L, nr, vm, m, ws);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int d = 0; d < D; ++d) cur[u][d] = nxt[u][d];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) step<D, B, PRED, SUM>(cur[u], i + u, L, nr, vm, m, ws);
+        i += U;
+    }
+    for (; i < i1; ++i) {
+        uint32_t s[D];
+        load_entry<D>(ct, i, s);
+        step<D, B, PRED, SUM>(s, i, L, nr, vm, m, ws);
+    }
+}
+
+
+// Where the left and right sums of one pair come from.
+struct ItemSrc {
+    const uint32_t *rows;      // k x DP
+    const uint32_t *table;     // right table
+    const uint32_t *ltable;    // left table or nullptr (lanes unrank)
+    const uint64_t *binom;     // full binomial table (unranking)
+    const uint64_t *colA;      // C(x, a) = colA[x * sA]
+    const uint64_t *colB;      // C(x, b) = colB[x * sB]
+    int sA, sB;
+    uint64_t n_items;          // C(k-b, a)
+    int k, a, b;
+};
+
+// The part of the pair one chunk covers: left tile lt, right entries
+// [i_begin, i_end) (i_end is clipped to the tile's first item's range when
+// clip is set), e_first a lower bound on the largest element of the tile.
+struct ChunkGeo {
+    uint64_t lt;
+    uint32_t i_begin, i_end;
+    uint32_t e_first;
+    bool clip;
+};
+
+// One chunk: B left subsets per lane (ranks lt*64B + t*64 + lane, clamped to
+// the last valid one) against right entries [i_begin, i_end).  Returns the
+// lane's least weight (without the identity offset), the number of
+// combinations it evaluated and (VERIFY) their weight sum; L and nr stay
+// valid for a witness search.
+template <int D, int B, bool VERIFY>
+__device__ __forceinline__ void run_chunk(const ItemSrc &s, ChunkGeo &g, uint32_t (&L)[B][D],
+                                          uint32_t (&nr)[B], uint32_t &lmin, uint64_t &cnt,
+                                          uint32_t &ws) {
+    constexpr int DP = dp_of(D);
+    const int lane = threadIdx.x & 63;
+    const uint64_t tile0 = g.lt * (64ull * B) + lane;
+    uint32_t nr_lane_min = kInf, nr_lane_max = 0;
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+        const uint64_t rho = tile0 + (uint64_t)t * 64;
+        const uint64_t rc = rho < s.n_items ? rho : s.n_items - 1;
+#pragma unroll
+        for (int d = 0; d < D; ++d) L[t][d] = 0;
+        int e;
+        if (s.ltable) {
+            // saved left sum; its largest element e is the largest x with
+            // C(x, a) <= rho (colex order sorts by largest element)
+#pragma unroll
+            for (int d = 0; d < D; ++d) L[t][d] = s.ltable[rc * DP + d];
+            e = max((int)g.e_first, s.a - 1);
+            int hi = s.k - 1 - s.b;     // the largest e with a right partner
+            while (e < hi) {
+                const int mid = (e + hi + 1) >> 1;
+                if (s.colA[(size_t)mid * s.sA] <= rc) e = mid; else hi = mid - 1;
+            }
+        } else {
+            e = unrank_add<D>(s.binom, s.rows, DP, rc, s.a, s.k, L[t], false, s.k);
+        }
+        nr[t] = (uint32_t)s.colB[(size_t)(s.k - 1 - e) * s.sB];
+        nr_lane_min = min(nr_lane_min, nr[t]);
+        nr_lane_max = max(nr_lane_max, nr[t]);
+    }
+    const uint32_t nr_min = wave_min_u32(nr_lane_min);
+    if (g.clip) g.i_end = min(g.i_end, wave_max_u32(nr_lane_max));
+    const uint32_t fast_end = min(g.i_end, max(g.i_begin, nr_min));
+
+    uint32_t m[B], vm[B];
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+        m[t] = kInf;
+        vm[t] = (tile0 + (uint64_t)t * 64 < s.n_items) ? kInf : 0u;
+    }
+    ws = 0;
+    run_range<D, B, false, VERIFY>(s.table, g.i_begin, fast_end, L, nr, vm, m, ws);
+    run_range<D, B, true, VERIFY>(s.table, fast_end, g.i_end, L, nr, vm, m, ws);
+    lmin = kInf;
+    cnt = 0;
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+        lmin = min(lmin, m[t]);
+        if (tile0 + (uint64_t)t * 64 < s.n_items) {
+            const uint32_t hi = min(g.i_end, nr[t]);
+            cnt += hi > g.i_begin ? (uint64_t)(hi - g.i_begin) : 0ull;
+        }
+    }
+}
+
+// The first (item, entry) of the chunk whose weight is wmin: returns the lane
+// that holds it (or -1), with its right index and left rank.
+template <int D, int B>
+__device__ __forceinline__ int find_witness(const ItemSrc &s, const ChunkGeo &g,
+                                            const uint32_t (&L)[B][D], const uint32_t (&nr)[B],
+                                            uint32_t wmin, uint32_t &hit_i, uint64_t &hit_rho) {
+    const int lane = threadIdx.x & 63;
+    hit_i = kInf;
+    int hit_t = -1;
+    cu32 *ct = (cu32 *)s.table;
+    for (uint32_t i = g.i_begin; i < g.i_end && hit_t < 0; ++i) {
+        uint32_t e[D];
+        load_entry<D>(ct, i, e);
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            const uint32_t w = weight_of<D>(L[t], e);
+            if (hit_t < 0 && i < nr[t] && w == wmin) { hit_t = t; hit_i = i; }
+        }
+    }
+    const unsigned long long ball = __ballot(hit_t >= 0);
+    const int first = ball ? __builtin_ctzll(ball) : -1;
+    hit_rho = 0;
+    if (lane == first) {
+        const uint64_t tile0 = g.lt * (64ull * B) + lane;
+#pragma unroll
+        for (int t = 0; t < B; ++t)
+            if (t == hit_t) {
+                hit_rho = tile0 + (uint64_t)t * 64;
+                if (hit_rho >= s.n_items) hit_rho = s.n_items - 1;
+            }
+    }
+    return first;
+}
+
+}  // namespace md

@@ -1,183 +1,18 @@
-// mindist_kernels.hip -- gfx950 kernels of the minimum-distance enumeration.
+// mindist_kernels.hip -- gfx950 kernels of the single-code path.
 //
 // enum_pair_kernel computes, for one pair (Gamma_j, w) of Algorithm 1, the
 // least weight of c*Gamma_j over all c with wt(c) = w (the inner minimum of
 // Algorithm 1), with the left/right split described in mindist_internal.h.
-// The hot loop per codeword is: D x v_xor_b32 (lane row sum ^ scalar right
-// sum), D x v_bcnt_u32_b32 (accumulating popcount), one v_min_u32.  Rows and
-// tables are a few KB to a few MB; nothing per codeword touches HBM.
+// Rows and tables are a few KB to a few MB; nothing per codeword touches HBM.
 #include <hip/hip_runtime.h>
 
-#include "mindist_internal.h"
+#include "mindist_device.h"
 
 namespace md {
 
-typedef const __attribute__((address_space(4))) uint32_t cu32;
-
-__host__ __device__ constexpr int dp_of(int D) {
-    return D <= 1 ? 1 : D <= 2 ? 2 : D <= 4 ? 4 : D <= 8 ? 8 : 16;
-}
-
-__device__ __forceinline__ uint64_t binom(const uint64_t *bt, int x, int t) {
-    return (x < 0 || t < 0 || t > x) ? 0ull : bt[x * kBinomT + t];
-}
-
-__device__ __forceinline__ uint32_t uni32(uint32_t v) {
-    return __builtin_amdgcn_readfirstlane(v);
-}
-__device__ __forceinline__ uint64_t uni64(uint64_t v) {
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
-    return uni32(v);
-}
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
-    return uni32(v);
-}
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += (uint64_t)__shfl_xor((long long)v, o);
-    return uni64(v);
-}
-
-// Colex unranking: the a-subset {x_1 < ... < x_a} of [0, hi) with
-// sum_t C(x_t, t) = rho.  Adds the rows of the subset into acc and returns
-// the largest element.
-template <int D>
-__device__ __forceinline__ int unrank_add(const uint64_t *bt, const uint32_t *rows, int dp,
-                                          uint64_t rho, int a, int hi, uint32_t (&acc)[D],
-                                          bool reflect, int k) {
-    int top = -1;
-    for (int t = a; t >= 1; --t) {
-        int lo = t - 1, h = hi - 1;
-        while (lo < h) {
-            int mid = (lo + h + 1) >> 1;
-            if (binom(bt, mid, t) <= rho) lo = mid; else h = mid - 1;
-        }
-        rho -= binom(bt, lo, t);
-        hi = lo;
-        if (top < 0) top = lo;
-        const int r = reflect ? (k - 1 - lo) : lo;
-#pragma unroll
-        for (int d = 0; d < D; ++d) acc[d] ^= rows[(size_t)r * dp + d];
-    }
-    return top;
-}
-
-// v_bcnt_u32_b32 with its accumulator operand: popcount(x) + acc in one
-// instruction (the compiler would otherwise sum separate popcounts with
-// v_add3, one more instruction per codeword).
-__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
-    uint32_t r;
-    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
-    return r;
-}
-
-template <int D>
-__device__ __forceinline__ uint32_t weight_of(const uint32_t (&L)[D], const uint32_t (&s)[D]) {
-    uint32_t w = __builtin_popcount(L[0] ^ s[0]);
-#pragma unroll
-    for (int d = 1; d < D; ++d) w = bcnt_acc(L[d] ^ s[d], w);
-    return w;
-}
-
-// A right-table entry is dp_of(D) words; it is fetched whole (the padding
-// word of D = 3 included) so one scalar load brings one entry.
-template <int DP> struct Entry { uint32_t w[DP]; };
-template <> struct Entry<4> {
-    typedef uint32_t v4 __attribute__((ext_vector_type(4)));
-    v4 v;
-};
-template <int D>
-__device__ __forceinline__ void load_entry(cu32 *ct, uint32_t i, uint32_t (&s)[D]) {
-    constexpr int DP = dp_of(D);
-    if constexpr (DP == 4) {
-        typedef const __attribute__((address_space(4))) Entry<4>::v4 cv4;
-        const Entry<4>::v4 v = ((cv4 *)ct)[i];
-        s[0] = v.x;
-        if constexpr (D > 1) s[1] = v.y;
-        if constexpr (D > 2) s[2] = v.z;
-        if constexpr (D > 3) s[3] = v.w;
-    } else {
-#pragma unroll
-        for (int d = 0; d < D; ++d) s[d] = ct[(size_t)i * DP + d];
-    }
-}
-
-// right-table entries per pipelined block (two blocks live in SGPRs)
-template <int D>
-__host__ __device__ constexpr int block_of() { return dp_of(D) <= 4 ? 4 : dp_of(D) <= 8 ? 2 : 1; }
-
-// One right-table entry against the B lane items.
-//   PRED: mask item t once i >= nr[t] (its right range ended)
-//   SUM : accumulate weights (verify mode); vm[t] = 0 drops a clamped
-//         duplicate item from the sum
-template <int D, int B, bool PRED, bool SUM>
-__device__ __forceinline__ void step(const uint32_t (&s)[D], uint32_t i, const uint32_t (&L)[B][D],
-                                     const uint32_t (&nr)[B], const uint32_t (&vm)[B],
-                                     uint32_t (&m)[B], uint32_t &ws) {
-#pragma unroll
-    for (int t = 0; t < B; ++t) {
-        uint32_t w = weight_of<D>(L[t], s);
-        if (PRED) {
-            const bool on = i < nr[t];
-            if (SUM) ws += on ? (w & vm[t]) : 0u;
-            w = on ? w : kInf;
-        } else if (SUM) {
-            ws += w & vm[t];
-        }
-        m[t] = min(m[t], w);
-    }
-}
-
-// Run right-table entries [i0, i1) against the B lane items.  The uniform
-// entries come in by scalar loads; the next block is requested before the
-// current one is consumed so the load latency overlaps the VALU work.
-template <int D, int B, bool PRED, bool SUM>
-__device__ __forceinline__ void run_range(const uint32_t *tab, uint32_t i0, uint32_t i1,
-                                          const uint32_t (&L)[B][D], const uint32_t (&nr)[B],
-                                          const uint32_t (&vm)[B], uint32_t (&m)[B],
-                                          uint32_t &ws) {
-    constexpr int U = block_of<D>();
-    cu32 *ct = (cu32 *)tab;
-    uint32_t i = i0;
-    if (i1 - i0 >= 2 * U) {
-        uint32_t cur[U][D], nxt[U][D];
-#pragma unroll
-        for (int u = 0; u < U; ++u) load_entry<D>(ct, i + u, cur[u]);
-        for (; i + 2 * U <= i1; i += U) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) load_entry<D>(ct, i + U + u, nxt[u]);
-#pragma unroll
-            for (int u = 0; u < U; ++u) step<D, B, PRED, SUM>(cur[u], i + u, L, nr, vm, m, ws);
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int d = 0; d < D; ++d) cur[u][d] = nxt[u][d];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) step<D, B, PRED, SUM>(cur[u], i + u, L, nr, vm, m, ws);
-        i += U;
-    }
-    for (; i < i1; ++i) {
-        uint32_t s[D];
-        load_entry<D>(ct, i, s);
-        step<D, B, PRED, SUM>(s, i, L, nr, vm, m, ws);
-    }
-}
-
 template <int D, int B, bool VERIFY>
 __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
-    constexpr int DP = dp_of(D);
     const int lane = threadIdx.x & 63;
-    const uint64_t TB = 64ull * B;
     PairStat *ps = state_pairs(p.st) + p.pair;
     Slot *slots = state_slots(p.st);
     int gi = 0;
@@ -186,10 +21,10 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
     uint32_t run_min = kInf;
     uint64_t run_cnt = 0, run_ws = 0;
     // One chunk per claim, so the waves running at the same moment hold
-    // neighbouring chunks (and read the same few right-table tiles).  Chunk
-    // c is handed out by counter c % 8; a wave starts on counter (wave id %
-    // 8) and moves on, for good, once that counter is past the end.  Eight
-    // counters on separate lines take eight times the claim rate of one.
+    // neighbouring chunks.  Chunk c is handed out by counter c % nq; a wave
+    // starts on counter (wave id % nq) and moves on, for good, once that
+    // counter is past the end.  Counters on separate lines take nq times
+    // the claim rate of one.
     const uint32_t nq = p.counters;
     // (readfirstlane: the wave index is uniform, and everything derived from
     // the claimed chunk must stay in scalar registers for the table loads)
@@ -202,6 +37,8 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
         colB[x] = binom(p.binom, x, p.b);
     }
     __syncthreads();
+    const ItemSrc src{p.rows, p.table, p.ltable, p.binom, colA, colB, 1, 1,
+                      p.n_items, p.k, p.a, p.b};
     uint32_t rt_cur = 0;
     uint32_t moved = 0;
     uint32_t U_seen = kInf;
@@ -233,21 +70,20 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
         }
         U_seen = uni32(__hip_atomic_load(&p.st->U_found, __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT));
-        uint64_t lt;
-        uint32_t rt, i_begin, i_end;
-        uint32_t e_first = 0;
+        ChunkGeo g;
         if (p.order == 0) {
             // left-major: groups of left tiles by the largest element of their
             // first item; a wave's chunk ids grow except when it changes counter
             if (p.groups[gi].chunk_base > c) gi = 0;
             while (gi + 1 < p.ngroups && p.groups[gi + 1].chunk_base <= c) ++gi;
-            const GroupEntry g = p.groups[gi];
-            const uint64_t off = c - g.chunk_base;
-            lt = g.lt_begin + off / g.n_rt;
-            rt = (uint32_t)(off % g.n_rt);
-            i_begin = rt * p.T;
-            i_end = min(i_begin + p.T, g.nr_first);
-            e_first = g.e;
+            const GroupEntry ge = p.groups[gi];
+            const uint64_t off = c - ge.chunk_base;
+            g.lt = ge.lt_begin + off / ge.n_rt;
+            const uint32_t rt = (uint32_t)(off % ge.n_rt);
+            g.i_begin = rt * p.T;
+            g.i_end = min(g.i_begin + p.T, ge.nr_first);
+            g.e_first = ge.e;
+            g.clip = false;
         } else {
             // right-major: right tile r holds the left tiles whose first item
             // still has entries past r*T; find r by binary search
@@ -256,69 +92,18 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
                 const uint32_t mid = (lo + hi + 1) >> 1;
                 if (p.rprefix[mid] <= c) lo = mid; else hi = mid - 1;
             }
-            rt = rt_cur = lo;
-            lt = c - p.rprefix[rt];
-            i_begin = rt * p.T;
-            i_end = i_begin + p.T;     // clipped below by the first item's range
+            rt_cur = lo;
+            g.lt = c - p.rprefix[lo];
+            g.i_begin = lo * p.T;
+            g.i_end = g.i_begin + p.T;
+            g.e_first = 0;
+            g.clip = true;
         }
-
-        // lane items: left subsets rho = lt*64B + t*64 + lane (clamped to the
-        // last valid item, which then counts once)
-        // (rank and validity are recomputed where needed rather than kept
-        // live across the hot loop, which must fit 8 waves per SIMD)
-        uint32_t L[B][D];
-        uint32_t nr[B];
-        uint32_t nr_lane_min = kInf, nr_lane_max = 0;
-        const uint64_t tile0 = lt * TB + lane;
-#pragma unroll
-        for (int t = 0; t < B; ++t) {
-            const uint64_t rho = tile0 + (uint64_t)t * 64;
-            const uint64_t rc = rho < p.n_items ? rho : p.n_items - 1;
-#pragma unroll
-            for (int d = 0; d < D; ++d) L[t][d] = 0;
-            int e;
-            if (p.ltable) {
-                // saved left sum; its largest element e is the largest x with
-                // C(x, a) <= rho (colex order sorts by largest element)
-#pragma unroll
-                for (int d = 0; d < D; ++d) L[t][d] = p.ltable[rc * DP + d];
-                e = max((int)e_first, p.a - 1);
-                int hi = p.k - 1 - p.b;     // the largest e with a right partner
-                while (e < hi) {
-                    const int mid = (e + hi + 1) >> 1;
-                    if (colA[mid] <= rc) e = mid; else hi = mid - 1;
-                }
-            } else {
-                e = unrank_add<D>(p.binom, p.rows, DP, rc, p.a, p.k, L[t], false, p.k);
-            }
-            nr[t] = (uint32_t)colB[p.k - 1 - e];
-            nr_lane_min = min(nr_lane_min, nr[t]);
-            nr_lane_max = max(nr_lane_max, nr[t]);
-        }
-        const uint32_t nr_min = wave_min_u32(nr_lane_min);
-        if (p.order != 0) i_end = min(i_end, wave_max_u32(nr_lane_max));
-        const uint32_t fast_end = min(i_end, max(i_begin, nr_min));
-
-        uint32_t m[B], vm[B];
-#pragma unroll
-        for (int t = 0; t < B; ++t) {
-            m[t] = kInf;
-            vm[t] = (tile0 + (uint64_t)t * 64 < p.n_items) ? kInf : 0u;
-        }
-        uint32_t ws = 0;
-        run_range<D, B, false, VERIFY>(p.table, i_begin, fast_end, L, nr, vm, m, ws);
-        run_range<D, B, true, VERIFY>(p.table, fast_end, i_end, L, nr, vm, m, ws);
-
-        uint32_t lmin = kInf;
-#pragma unroll
-        for (int t = 0; t < B; ++t) {
-            lmin = min(lmin, m[t]);
-            if (tile0 + (uint64_t)t * 64 < p.n_items) {
-                const uint32_t hi = min(i_end, nr[t]);
-                run_cnt += hi > i_begin ? (uint64_t)(hi - i_begin) : 0ull;
-            }
-        }
+        uint32_t L[B][D], nr[B], lmin, ws;
+        uint64_t cnt;
+        run_chunk<D, B, VERIFY>(src, g, L, nr, lmin, cnt, ws);
         run_min = min(run_min, lmin);
+        run_cnt += cnt;
         if (VERIFY) run_ws += ws;
         // only a lane that beats U (as last read) takes part in the update
         const bool better = lmin != kInf && lmin + p.offset < U_seen;
@@ -330,33 +115,14 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
         old = uni32((uint32_t)__shfl((int)old, 0));
         U_seen = min(old, val);
         if (old > val) {
-            // this wave moved U_found to val: it alone writes slot[val].
-            // Find the first (item, i) of the chunk that has weight wmin.
-            uint32_t hit_i = kInf;
-            int hit_t = -1;
-            cu32 *ct = (cu32 *)p.table;
-            for (uint32_t i = i_begin; i < i_end && hit_t < 0; ++i) {
-                uint32_t s[D];
-                load_entry<D>(ct, i, s);
-#pragma unroll
-                for (int t = 0; t < B; ++t) {
-                    const uint32_t w = weight_of<D>(L[t], s);
-                    if (hit_t < 0 && i < nr[t] && w == wmin) { hit_t = t; hit_i = i; }
-                }
-            }
-            const unsigned long long ball = __ballot(hit_t >= 0);
-            const int first = ball ? __builtin_ctzll(ball) : -1;
+            // this wave moved U_found to val: it alone writes slot[val]
+            uint32_t hit_i;
+            uint64_t hit_rho;
+            const int first = find_witness<D, B>(src, g, L, nr, wmin, hit_i, hit_rho);
             if (lane == first) {
-                uint64_t rho = 0;
-#pragma unroll
-                for (int t = 0; t < B; ++t)
-                    if (t == hit_t) {
-                        rho = tile0 + (uint64_t)t * 64;
-                        if (rho >= p.n_items) rho = p.n_items - 1;
-                    }
                 slots[val].pair = p.pair;
                 slots[val].i = hit_i;
-                slots[val].rho = rho;
+                slots[val].rho = hit_rho;
             }
         }
         if (p.midpair_exit && val <= p.L_prev && lane == 0)

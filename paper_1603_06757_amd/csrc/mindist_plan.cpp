@@ -1,0 +1,177 @@
+// mindist_plan.cpp -- host-side mathematics shared by all paths (see
+// mindist_plan.h for the readings of the paper it implements).
+#include "mindist_plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <iterator>
+#include <string>
+
+#include "../../include/mindist.h"
+#include "mindist_internal.h"
+
+namespace md {
+
+static thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+const char *last_error_text() { return g_err.c_str(); }
+
+
+Binom::Binom() : t((size_t)kBinomX * kBinomT, 0) {
+        for (int x = 0; x < kBinomX; ++x) {
+            t[(size_t)x * kBinomT] = 1;
+            for (int r = 1; r < kBinomT; ++r) {
+                if (r > x) { t[(size_t)x * kBinomT + r] = 0; continue; }
+                uint64_t a = t[(size_t)(x - 1) * kBinomT + r - 1];
+                uint64_t b = (r <= x - 1) ? t[(size_t)(x - 1) * kBinomT + r] : 0;
+                uint64_t s = a + b;
+                t[(size_t)x * kBinomT + r] = (s < a || a == UINT64_MAX || b == UINT64_MAX) ? UINT64_MAX : s;
+            }
+        }
+}
+
+uint64_t Binom::operator()(int x, int r) const {
+    if (x < 0 || r < 0 || r > x) return 0;
+    if (x >= kBinomX || r >= kBinomT) return UINT64_MAX;
+    return t[(size_t)x * kBinomT + r];
+}
+const Binom &BN() {
+    static Binom b;
+    return b;
+}
+
+int check_matrix(const uint64_t *G, int n, int k) {
+    if (!G) return fail(MINDIST_E_ARG, "G is NULL");
+    if (k < 1 || n <= k || n > MINDIST_MAX_N)
+        return fail(MINDIST_E_ARG, "need 1 <= k < n <= 512 (got n=" + std::to_string(n) +
+                                       ", k=" + std::to_string(k) + ")");
+    const int W = (n + 63) / 64;
+    const int rem = n - 64 * (W - 1);
+    if (rem < 64)
+        for (int r = 0; r < k; ++r)
+            if (G[(size_t)r * W + W - 1] >> rem)
+                return fail(MINDIST_E_ARG, "bits beyond column n-1 must be zero (row " +
+                                               std::to_string(r) + ")");
+    return MINDIST_OK;
+}
+
+// One Gauss-Jordan sweep: pivot the columns of `cols` in order on rows r..k-1
+// of M (k x W), eliminating every other row; stop at k pivots.  Appends the
+// pivot columns and returns the new pivot row count.
+static int sweep(std::vector<uint64_t> &M, int k, int W, const std::vector<int> &cols, int r,
+          std::vector<int> *piv) {
+    for (int c : cols) {
+        if (r == k) break;
+        int p = -1;
+        for (int i = r; i < k; ++i)
+            if (bit_of(&M[(size_t)i * W], c)) { p = i; break; }
+        if (p < 0) continue;
+        if (p != r)
+            for (int t = 0; t < W; ++t) std::swap(M[(size_t)p * W + t], M[(size_t)r * W + t]);
+        for (int i = 0; i < k; ++i)
+            if (i != r && bit_of(&M[(size_t)i * W], c))
+                for (int t = 0; t < W; ++t) M[(size_t)i * W + t] ^= M[(size_t)r * W + t];
+        if (piv) piv->push_back(c);
+        ++r;
+    }
+    return r;
+}
+
+int make_plan(const uint64_t *G, int n, int k, Plan &P) {
+    int e = check_matrix(G, n, k);
+    if (e) return e;
+    const int W = (n + 63) / 64;
+    P = Plan();
+    P.n = n; P.k = k; P.W = W;
+    std::vector<int> avail(n);
+    for (int c = 0; c < n; ++c) avail[c] = c;
+    bool first = true;
+    for (;;) {
+        std::vector<uint64_t> M(G, G + (size_t)k * W);
+        std::vector<int> piv;
+        int r = sweep(M, k, W, avail, 0, &piv);
+        if (first && r < k) return fail(MINDIST_E_RANK, "rank(G) < k");
+        first = false;
+        if (r == k) {
+            P.sets.push_back(piv);
+            P.gamma.push_back(M);
+            ++P.m_full;
+            std::vector<int> rest;
+            std::set_difference(avail.begin(), avail.end(), piv.begin(), piv.end(),
+                                std::back_inserter(rest));
+            avail.swap(rest);
+            if (avail.empty()) break;
+        } else {
+            P.k_m = r;
+            if (r >= 1) {
+                // complete the echelon form on the remaining rows over all
+                // other columns in ascending order
+                std::vector<int> others;
+                std::vector<int> s = piv;
+                std::sort(s.begin(), s.end());
+                for (int c = 0; c < n; ++c)
+                    if (!std::binary_search(s.begin(), s.end(), c)) others.push_back(c);
+                int r2 = sweep(M, k, W, others, r, nullptr);
+                if (r2 != k) return fail(MINDIST_E_RANK, "rank(G) < k");
+                P.sets.push_back(piv);
+                P.gamma.push_back(M);
+            }
+            break;
+        }
+    }
+    return MINDIST_OK;
+}
+
+int bound_f(int i, int h, int m_full, int k, int k_m) {
+    if (i < m_full) return h + 1;
+    int v = h + 1 - (k - k_m);
+    return v > 0 ? v : 0;
+}
+
+int bound_after(int k, int m_full, int k_m, int n_gamma, int j, int w) {
+    int s = 0;
+    for (int i = 0; i < n_gamma; ++i) s += bound_f(i, i <= j ? w : w - 1, m_full, k, k_m);
+    return s;
+}
+
+// colex unranking of rho into an r-subset of [0, hi) (elements ascending)
+void colex_unrank(uint64_t rho, int r, int hi, int *out) {
+    const Binom &B = BN();
+    for (int t = r; t >= 1; --t) {
+        int lo = t - 1, h = hi - 1;
+        while (lo < h) {
+            int mid = (lo + h + 1) / 2;
+            if (B(mid, t) <= rho) lo = mid; else h = mid - 1;
+        }
+        out[t - 1] = lo;
+        rho -= B(lo, t);
+        hi = lo;
+    }
+}
+
+
+std::vector<int> carried_columns(const Plan &P, int j) {
+    std::vector<int> cols;
+    if (j < P.m_full) {
+        std::vector<int> s = P.sets[j];
+        std::sort(s.begin(), s.end());
+        for (int col = 0; col < P.n; ++col)
+            if (!std::binary_search(s.begin(), s.end(), col)) cols.push_back(col);
+    } else {
+        for (int col = 0; col < P.n; ++col) cols.push_back(col);
+    }
+    return cols;
+}
+
+void pack_row(const uint64_t *row, const std::vector<int> &cols, uint32_t *out, int DP) {
+    for (int d = 0; d < DP; ++d) out[d] = 0;
+    for (size_t i = 0; i < cols.size(); ++i)
+        if (bit_of(row, cols[i])) out[i >> 5] |= 1u << (i & 31);
+}
+
+}  // namespace md

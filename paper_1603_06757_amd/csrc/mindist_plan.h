@@ -1,0 +1,61 @@
+// mindist_plan.h -- host-side mathematics shared by the single-code,
+// batch and serving paths: binomials, argument checks, information sets and
+// systematic matrices (Section 2), the lower-bound schedule (Section 2 and
+// Algorithm 1), colex unranking and row packing.
+//
+// Readings of the paper implemented here:
+//   * information sets: greedy rounds over the unused columns in ascending
+//     order; a round that reaches k pivots is a full set, the first round
+//     that does not gives the partial set (rank k_m, possibly 0) and ends;
+//   * Gamma_j: the reduced row echelon form of G under the column order
+//     (set columns ascending, then all others ascending) -- unique, so the
+//     partial set's [[I, A], [0, B]] is canonical;
+//   * bounds: U starts at n-k+1, L at 1 (Algorithm 1); after pair (j, w),
+//     L = sum_{i<=j} f_i(w) + sum_{i>j} f_i(w-1) with f_full(h) = h+1 and
+//     f_partial(h) = max(0, h+1-(k-k_m)) ("one after each Gamma_j").
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace md {
+
+// records msg as the calling thread's last error and returns code
+int fail(int code, const std::string &msg);
+
+struct Binom {
+    std::vector<uint64_t> t;   // kBinomX x kBinomT, saturating at UINT64_MAX
+    Binom();
+    uint64_t operator()(int x, int r) const;
+};
+const Binom &BN();
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline int bit_of(const uint64_t *row, int c) { return (int)((row[c >> 6] >> (c & 63)) & 1u); }
+inline int dp_of_host(int D) { return D <= 1 ? 1 : D <= 2 ? 2 : D <= 4 ? 4 : D <= 8 ? 8 : 16; }
+
+int check_matrix(const uint64_t *G, int n, int k);
+
+struct Plan {
+    int n = 0, k = 0, W = 0;
+    int m_full = 0, k_m = 0;
+    std::vector<std::vector<int>> sets;          // full sets, then the partial set
+    std::vector<std::vector<uint64_t>> gamma;    // k x W rows per set, original columns
+};
+int make_plan(const uint64_t *G, int n, int k, Plan &P);
+
+// the columns a set's rows carry on the device: the non-set columns for a
+// full set (its identity part is implied by the level), all columns for the
+// partial set
+std::vector<int> carried_columns(const Plan &P, int j);
+// pack the carried columns of one Gamma row into 32-bit words
+void pack_row(const uint64_t *row, const std::vector<int> &cols, uint32_t *out, int DP);
+
+int bound_f(int i, int h, int m_full, int k, int k_m);
+int bound_after(int k, int m_full, int k_m, int n_gamma, int j, int w);
+
+// colex unranking of rho into an r-subset of [0, hi) (elements ascending)
+void colex_unrank(uint64_t rho, int r, int hi, int *out);
+
+}  // namespace md

@@ -123,7 +123,9 @@ typedef struct mindist_pair {
     uint64_t wsum;            /* sum of weights (VERIFY=1 only, else 0) */
     double   ms;              /* kernel time of the pair (PROFILE=1 only) */
     int32_t  dwords;          /* 32-bit words carried per codeword by the kernel */
-    int32_t  split_a;         /* rows taken per lane item (the rest come from the table) */
+    int32_t  split_a;         /* rows per lane subset */
+    int32_t  split_b;         /* rows from the (outer) right table */
+    int32_t  split_b2;        /* rows from the inner table (0: two-level split) */
 } mindist_pair;
 
 /* Section 2 and Algorithm 1 preprocessing: validate and copy G, greedy

@@ -63,7 +63,8 @@ class Pair(C.Structure):
     _fields_ = [("j", C.c_int32), ("w", C.c_int32), ("L_before", C.c_int32),
                 ("L_after", C.c_int32), ("U_after", C.c_int32), ("pair_min", C.c_int32),
                 ("count", C.c_uint64), ("executed", C.c_uint64), ("wsum", C.c_uint64),
-                ("ms", C.c_double), ("dwords", C.c_int32), ("split_a", C.c_int32)]
+                ("ms", C.c_double), ("dwords", C.c_int32), ("split_a", C.c_int32),
+                ("split_b", C.c_int32), ("split_b2", C.c_int32)]
 
     def to_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -60,6 +60,10 @@ int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &
     for (int j = 0; j < hc.n_gamma; ++j) {
         hc.rows_bytes += align256((size_t)k * hc.dp[j] * 4);
         for (int b = 0; b <= hc.bcap[j]; ++b) hc.tab_bytes += align256(B(k, b) * hc.dp[j] * 4);
+        for (int b1 = 1; b1 <= hc.bcap[j]; ++b1) {
+            const uint64_t ent = B(k - hc.bcap[j], b1);
+            hc.tab_bytes += align256(ent * hc.dp[j] * 4) + align256(ent * 4);
+        }
     }
     hc.slot_bytes = align256(sizeof(Slot) * (size_t)(n + 1));
     return MINDIST_OK;
@@ -83,8 +87,14 @@ void fill_slot(const HostCode &hc, const SlotPlace &pl, unsigned char *rows_stag
     uint64_t acc = 0;
     for (int t = 0; t < kBatchTabs; ++t) {
         bc.tab_off[t] = acc;
-        const int j = t / (kBatchMaxB + 1), b = t % (kBatchMaxB + 1);
-        if (j < hc.n_gamma && b <= hc.bcap[j]) acc += B(hc.k, b);
+        const int j = t / kTabsPerSet, r = t % kTabsPerSet;
+        if (j >= hc.n_gamma) continue;
+        if (r <= kBatchMaxB) {
+            if (r <= hc.bcap[j]) acc += B(hc.k, r);
+        } else {
+            const int b1 = r - (kBatchMaxB + 1);
+            if (b1 >= 1 && b1 <= hc.bcap[j]) acc += B(hc.k - hc.bcap[j], b1);
+        }
     }
     bc.tab_off[kBatchTabs] = acc;
     size_t ro = 0, to = 0;
@@ -101,6 +111,13 @@ void fill_slot(const HostCode &hc, const SlotPlace &pl, unsigned char *rows_stag
         for (int b = 0; b <= hc.bcap[j]; ++b) {
             s.rtab[b] = reinterpret_cast<uint32_t *>(pl.tabs + to);
             to += align256(B(hc.k, b) * hc.dp[j] * 4);
+        }
+        for (int b1 = 1; b1 <= hc.bcap[j]; ++b1) {
+            const uint64_t ent = B(hc.k - hc.bcap[j], b1);
+            s.otab[b1] = reinterpret_cast<uint32_t *>(pl.tabs + to);
+            to += align256(ent * hc.dp[j] * 4);
+            s.ocnt[b1] = reinterpret_cast<uint32_t *>(pl.tabs + to);
+            to += align256(ent * 4);
         }
     }
     bc.slots = reinterpret_cast<Slot *>(pl.slots);
@@ -136,6 +153,8 @@ int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *ar
         r.executed = jb->executed;
         r.dwords = hc.D[jb->j];
         r.split_a = jb->a;
+        r.split_b = jb->b;
+        r.split_b2 = jb->b2;
         trace.push_back(r);
         executed += r.executed;
         canonical += r.count;
@@ -156,14 +175,9 @@ int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *ar
         if (s.pair < 1 || s.pair >= (uint32_t)bc.njobs)
             return fail(MINDIST_E_HIP, "batch witness slot holds an invalid job index");
         const BatchJob *jb = reinterpret_cast<const BatchJob *>(arena + (size_t)bc.job[s.pair] * 128);
-        const int a = jb->a, b = jb->b, j = jb->j;
-        int X[MINDIST_MAX_LEVEL + 1], Z[MINDIST_MAX_LEVEL + 1];
-        colex_unrank(s.rho, a, k, X);
-        colex_unrank(s.i, b, k, Z);
-        std::vector<int> rows(X, X + a);
-        for (int t = 0; t < b; ++t) rows.push_back(k - 1 - Z[t]);
-        std::sort(rows.begin(), rows.end());
-        if (std::adjacent_find(rows.begin(), rows.end()) != rows.end() || (int)rows.size() != jb->w)
+        const int j = jb->j;
+        const std::vector<int> rows = witness_rows(k, jb->a, jb->b, jb->b2, s);
+        if ((int)rows.size() != jb->w)
             return fail(MINDIST_E_HIP, "batch witness decodes to an invalid combination");
         uint64_t word[MINDIST_MAX_WORDS] = {0};
         for (int r : rows) {

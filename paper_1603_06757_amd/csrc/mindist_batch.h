@@ -25,7 +25,11 @@ constexpr int kBatchMaxPairs = 256;   // jobs per code (table job + pairs)
 constexpr int kBatchMaxD = 8;         // 32-bit words carried per row (n <= 256)
 constexpr int kBatchItems = 2;        // left subsets per lane
 constexpr int kTableChunk = 4096;     // table entries per table-job chunk
-constexpr int kBatchTabs = kBatchMaxSets * (kBatchMaxB + 1);
+// tables of set j: right tables b = 0..bcap (shift 0) at t = j*kTabsPerSet + b,
+// outer tables b1 = 1..bcap over rows [0, k-bcap) (shift bcap, with inner
+// counts) at t = j*kTabsPerSet + (kBatchMaxB+1) + b1
+constexpr int kTabsPerSet = 2 * (kBatchMaxB + 1);
+constexpr int kBatchTabs = kBatchMaxSets * kTabsPerSet;
 
 enum : int32_t {
     kSlotActive = 0,
@@ -39,6 +43,8 @@ enum : int32_t {
 struct BatchSet {
     const uint32_t *rows;                  // k x dp
     uint32_t *rtab[kBatchMaxB + 1];        // right tables b = 0..bcap (built on device)
+    uint32_t *otab[kBatchMaxB + 1];        // outer tables b1 = 1..bcap, shift bcap
+    uint32_t *ocnt[kBatchMaxB + 1];        // their inner counts
     int32_t D, dp, stripped, bcap;
 };
 
@@ -47,7 +53,7 @@ struct alignas(128) BatchJob {
     int32_t kind;                 // 0 = table job, 1 = enumeration pair
     int32_t j, w, a, b;
     uint32_t T, L_before, offset, ngroups;
-    uint32_t pad_a;
+    int32_t b2;                   // inner subset size (0: two-level split)
     uint64_t n_items, total_chunks, count;
     uint32_t pair_min, exit_flag, L_after, U_after;
     uint64_t executed;

@@ -102,16 +102,31 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
     const int lane = threadIdx.x & 63;
     const int k = cs->k;
     const BatchSet &set = cs->sets[j];
-    const int b = min(w / 2, set.bcap), a = w - b;
+    // split: the rule of the host planner, with the inner size fixed to
+    // bcap, the shift the outer tables were built with
+    int a, b, b2;
+    split_rows(k, w, set.bcap, true, [&](int x, int r) { return binom(A.binom, x, r); }, a, b, b2);
     const uint64_t TB = 64ull * kBatchItems;
-    const uint64_t n_items = binom(A.binom, k - b, a);
+    const uint64_t n_items = binom(A.binom, k - b - b2, a);
     const uint64_t tiles = (n_items + TB - 1) / TB;
-    // right tile: about 4 chunks per resident wave for this pair alone,
-    // between the configured bounds (pairs of many codes run side by side)
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    const uint64_t want = binom(A.binom, k, w) / (TB * waves * 4 + 1);
-    uint32_t T = A.tile_min;
-    while (T < A.tile_max && T < cs->tile_cap && T < want) T <<= 1;
+    uint32_t T;
+    if (b2 == 0) {
+        // right tile: about 4 chunks per resident wave for this pair alone,
+        // between the configured bounds (pairs of many codes run side by side)
+        const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+        const uint64_t want = binom(A.binom, k, w) / (TB * waves * 4 + 1);
+        T = A.tile_min;
+        while (T < A.tile_max && T < cs->tile_cap && T < want) T <<= 1;
+    } else {
+        // outer tile: about 256K codewords per chunk
+        const int e = (k - b - b2) * a / (a + 1);
+        const uint64_t outer = binom(A.binom, k - 1 - b2 - e, b);
+        const uint64_t both = binom(A.binom, k - 1 - e, b + b2);
+        const double n2 = outer ? (double)both / (double)outer : 1.0;
+        const double want = 262144.0 / ((double)TB * (n2 > 1 ? n2 : 1));
+        T = 1;
+        while (T < 1024 && T * 2 <= want) T <<= 1;
+    }
     const uint32_t off = alloc_job(A, k + 2);
     if (off == 0xFFFFFFFFu) {
         finish_code(A, c, -5 /* MINDIST_E_LIMIT */, L_before, min(cs->U_found, (uint32_t)(cs->n - k + 1)));
@@ -120,7 +135,7 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
     BatchJob *jb = job_at(A, off);
     GroupEntry *gr = job_groups(jb);
     // groups: one lane per candidate e, compacted with wave prefix sums
-    const int e_lo = a - 1, e_hi = k - 1 - b;
+    const int e_lo = a - 1, e_hi = k - 1 - b - b2;
     uint64_t chunk_base = 0;
     uint32_t ng = 0;
     for (int e0 = e_lo; e0 <= e_hi; e0 += 64) {
@@ -134,7 +149,7 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
             uint64_t lt_hi = (hi + TB - 1) / TB;
             if (lt_hi > tiles) lt_hi = tiles;
             if (lt_hi > lt_lo) {
-                nr_first = (uint32_t)binom(A.binom, k - 1 - e, b);
+                nr_first = (uint32_t)binom(A.binom, k - 1 - b2 - e, b);
                 n_rt = (nr_first + T - 1) / T;
                 chunks = (lt_hi - lt_lo) * n_rt;
             }
@@ -170,6 +185,7 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
         jb->w = w;
         jb->a = a;
         jb->b = b;
+        jb->b2 = b2;
         jb->T = T;
         jb->L_before = L_before;
         jb->offset = set.stripped ? (uint32_t)w : 0u;
@@ -219,99 +235,169 @@ __device__ void open_tables(const BatchArgs &A, int c) {
     }
 }
 
-// Chunk ch of the table job: entries [ch*4096, ...) of the flattened list.
+// Chunk ch of the table job: entries [ch*4096, ...) of the flattened list;
+// lane l fills 64 consecutive entries, the first by unranking, the rest by
+// the colex successor (one or two row additions each).
 __device__ void table_chunk(const BatchArgs &A, BatchCode *cs, uint64_t ch) {
     const int lane = threadIdx.x & 63;
     const uint64_t E = cs->tab_off[kBatchTabs];
     const int k = cs->k;
-    for (int r = 0; r < kTableChunk / 64; ++r) {
-        const uint64_t idx = ch * kTableChunk + (uint64_t)r * 64 + lane;
-        if (idx >= E) break;
-        int lo = 0, hi = kBatchTabs - 1;   // last t with tab_off[t] <= idx
+    uint64_t idx = ch * kTableChunk + (uint64_t)lane * (kTableChunk / 64);
+    uint64_t left = kTableChunk / 64;
+    while (left > 0 && idx < E) {
+        int lo = 0, hi = kBatchTabs - 1;   // last table t with tab_off[t] <= idx
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (cs->tab_off[mid] <= idx) lo = mid; else hi = mid - 1;
         }
-        const int j = lo / (kBatchMaxB + 1), b = lo % (kBatchMaxB + 1);
+        const int j = lo / kTabsPerSet, r0 = lo % kTabsPerSet;
         const BatchSet &set = cs->sets[j];
+        const bool outer = r0 > kBatchMaxB;
+        const int b = outer ? r0 - (kBatchMaxB + 1) : r0;
+        const int shift = outer ? set.bcap : 0;   // outer: rows [0, k-bcap)
+        const int kk = k - shift;
+        const uint64_t size = cs->tab_off[lo + 1] - cs->tab_off[lo];
         uint64_t i = idx - cs->tab_off[lo];
+        // z = colex_unrank_b(i), ascending; entry = rows {kk-1-z}
+        int z[kBatchMaxB + 1];
         uint32_t acc[kBatchMaxD];
         for (int d = 0; d < kBatchMaxD; ++d) acc[d] = 0;
-        // entry i = rows {k-1-z : z in colex_unrank_b(i)}
-        int top = k;
-        for (int t = b; t >= 1; --t) {
-            int l = t - 1, h = top - 1;
-            while (l < h) {
-                const int mid = (l + h + 1) >> 1;
-                if (binom(A.binom, mid, t) <= i) l = mid; else h = mid - 1;
+        {
+            uint64_t r = i;
+            int top = kk;
+            for (int t = b; t >= 1; --t) {
+                int l = t - 1, h = top - 1;
+                while (l < h) {
+                    const int mid = (l + h + 1) >> 1;
+                    if (binom(A.binom, mid, t) <= r) l = mid; else h = mid - 1;
+                }
+                r -= binom(A.binom, l, t);
+                top = l;
+                z[t - 1] = l;
+                const uint32_t *row = set.rows + (size_t)(kk - 1 - l) * set.dp;
+                for (int d = 0; d < set.D; ++d) acc[d] ^= row[d];
             }
-            i -= binom(A.binom, l, t);
-            top = l;
-            const uint32_t *row = set.rows + (size_t)(k - 1 - l) * set.dp;
-            for (int d = 0; d < set.D; ++d) acc[d] ^= row[d];
         }
-        uint32_t *out = set.rtab[b] + (size_t)(idx - cs->tab_off[lo]) * set.dp;
-        for (int d = 0; d < set.dp; ++d) out[d] = d < set.D ? acc[d] : 0u;
+        z[b] = kk;                        // sentinel
+        uint32_t *out = outer ? set.otab[b] : set.rtab[b];
+        uint32_t *cnt = outer ? set.ocnt[b] : nullptr;
+        for (; left > 0 && i < size; --left, ++i, ++idx) {
+            uint32_t *o = out + (size_t)i * set.dp;
+            for (int d = 0; d < set.dp; ++d) o[d] = d < set.D ? acc[d] : 0u;
+            if (cnt) cnt[i] = (uint32_t)binom(A.binom, shift + z[0], shift);
+            if (i + 1 == size || b == 0) continue;
+            // colex successor: the lowest position that can move up by one
+            int t0 = 0;
+            while (z[t0] + 1 == z[t0 + 1]) ++t0;
+            for (int t = 0; t <= t0; ++t) {
+                const uint32_t *row = set.rows + (size_t)(kk - 1 - z[t]) * set.dp;
+                for (int d = 0; d < set.D; ++d) acc[d] ^= row[d];
+            }
+            z[t0] += 1;
+            for (int t = 0; t < t0; ++t) z[t] = t;
+            for (int t = 0; t <= t0; ++t) {
+                const uint32_t *row = set.rows + (size_t)(kk - 1 - z[t]) * set.dp;
+                for (int d = 0; d < set.D; ++d) acc[d] ^= row[d];
+            }
+        }
     }
 }
 
-// One chunk of pair job p of code c.
-template <int D>
-__device__ void pair_chunk(const BatchArgs &A, int c, int p, BatchJob *jb, uint64_t ch) {
+// What a wave keeps about the job it is working on (read once per job).
+struct JobView {
+    int c, p, kind;
+    BatchJob *jb;
+    uint64_t total;
+    // pair jobs
+    int j, a, b, b2, k, D, ngroups, gi;
+    uint32_t T, offset, L_before;
+    uint64_t n_items;
+    const uint32_t *rows, *tab, *tab2, *cnt2;
+    const GroupEntry *gr;
+};
+
+__device__ void load_view(const BatchArgs &A, int c, int p, BatchJob *jb, JobView &v) {
     BatchCode *cs = &A.codes[c];
-    const int lane = threadIdx.x & 63;
-    const int j = (int)uni32((uint32_t)jb->j);
-    const int a = (int)uni32((uint32_t)jb->a), b = (int)uni32((uint32_t)jb->b);
-    const int k = (int)uni32((uint32_t)cs->k);
-    const BatchSet &set = cs->sets[j];
-    const uint32_t *rows = (const uint32_t *)uni64((uint64_t)set.rows);
-    const uint32_t *tab = (const uint32_t *)uni64((uint64_t)set.rtab[b]);
-    const uint64_t n_items = uni64(jb->n_items);
-    const uint32_t T = uni32(jb->T), offset = uni32(jb->offset), Lb = uni32(jb->L_before);
-    const int ngroups = (int)uni32(jb->ngroups);
-    const GroupEntry *gr = job_groups(jb);
-    // group of chunk ch: last group whose chunk_base <= ch
-    int lo = 0, hi = ngroups - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (uni64(gr[mid].chunk_base) <= ch) lo = mid; else hi = mid - 1;
+    v.c = c;
+    v.p = p;
+    v.jb = jb;
+    v.kind = (int)uni32((uint32_t)jb->kind);
+    v.total = uni64(jb->total_chunks);
+    if (v.kind == 0) return;
+    v.j = (int)uni32((uint32_t)jb->j);
+    v.a = (int)uni32((uint32_t)jb->a);
+    v.b = (int)uni32((uint32_t)jb->b);
+    v.b2 = (int)uni32((uint32_t)jb->b2);
+    v.k = (int)uni32((uint32_t)cs->k);
+    const BatchSet &set = cs->sets[v.j];
+    v.D = (int)uni32((uint32_t)set.D);
+    v.rows = (const uint32_t *)uni64((uint64_t)set.rows);
+    if (v.b2) {
+        v.tab = (const uint32_t *)uni64((uint64_t)set.otab[v.b]);
+        v.cnt2 = (const uint32_t *)uni64((uint64_t)set.ocnt[v.b]);
+        v.tab2 = (const uint32_t *)uni64((uint64_t)set.rtab[v.b2]);
+    } else {
+        v.tab = (const uint32_t *)uni64((uint64_t)set.rtab[v.b]);
+        v.cnt2 = v.tab2 = nullptr;
     }
-    const uint64_t base = uni64(gr[lo].chunk_base), n_rt = uni64(gr[lo].n_rt);
+    v.n_items = uni64(jb->n_items);
+    v.T = uni32(jb->T);
+    v.offset = uni32(jb->offset);
+    v.L_before = uni32(jb->L_before);
+    v.ngroups = (int)uni32(jb->ngroups);
+    v.gr = job_groups(jb);
+    v.gi = 0;
+}
+
+// One chunk of pair job v.p of code v.c.
+template <int D>
+__device__ void pair_chunk(const BatchArgs &A, JobView &v, uint64_t ch) {
+    BatchCode *cs = &A.codes[v.c];
+    BatchJob *jb = v.jb;
+    const int lane = threadIdx.x & 63;
+    // group of chunk ch: a wave's claims on one job only grow
+    while (v.gi + 1 < v.ngroups && uni64(v.gr[v.gi + 1].chunk_base) <= ch) ++v.gi;
+    const GroupEntry *ge = v.gr + v.gi;
+    const uint64_t base = uni64(ge->chunk_base), n_rt = uni64(ge->n_rt);
     const uint64_t offc = ch - base;
     ChunkGeo g;
-    g.lt = uni64(gr[lo].lt_begin) + offc / n_rt;
-    g.i_begin = (uint32_t)(offc % n_rt) * T;
-    g.i_end = min(g.i_begin + T, uni32(gr[lo].nr_first));
-    g.e_first = uni32(gr[lo].e);
+    g.lt = uni64(ge->lt_begin) + offc / n_rt;
+    g.i_begin = (uint32_t)(offc % n_rt) * v.T;
+    g.i_end = min(g.i_begin + v.T, uni32(ge->nr_first));
+    g.e_first = uni32(ge->e);
     g.clip = false;
-    const ItemSrc src{rows, tab, nullptr, A.binom, A.binom + a, A.binom + b, kBinomT, kBinomT,
-                      n_items, k, a, b};
+    const ItemSrc src{v.rows, v.tab, nullptr, A.binom, A.binom + v.a, A.binom + v.b, kBinomT, kBinomT,
+                      v.n_items, v.k, v.a, v.b, v.b2, v.tab2, v.cnt2};
     uint32_t L[kBatchItems][D], nr[kBatchItems], lmin, ws;
     uint64_t cnt;
-    run_chunk<D, kBatchItems, false>(src, g, L, nr, lmin, cnt, ws);
+    if (v.b2) run_chunk3<D, kBatchItems, false>(src, g, L, nr, lmin, cnt, ws);
+    else run_chunk<D, kBatchItems, false>(src, g, L, nr, lmin, cnt, ws);
     const uint32_t wmin = wave_min_u32(lmin);
     const uint64_t wcnt = wave_sum_u64(cnt);
     if (lane == 0) {
         atomicAdd((unsigned long long *)&jb->executed, (unsigned long long)wcnt);
-        if (wmin != kInf) atomicMin(&jb->pair_min, wmin + offset);
+        if (wmin != kInf) atomicMin(&jb->pair_min, wmin + v.offset);
     }
     if (wmin == kInf) return;
-    const uint32_t val = wmin + offset;
+    const uint32_t val = wmin + v.offset;
     if (val >= uni32(ld_rlx(&cs->U_found))) return;
     uint32_t old = 0;
     if (lane == 0) old = atomicMin(&cs->U_found, val);
     old = uni32((uint32_t)__shfl((int)old, 0));
     if (old > val) {
-        uint32_t hit_i;
+        uint32_t hit_i, hit_i2 = 0;
         uint64_t hit_rho;
-        const int first = find_witness<D, kBatchItems>(src, g, L, nr, wmin, hit_i, hit_rho);
+        const int first =
+            v.b2 ? find_witness3<D, kBatchItems>(src, g, L, nr, wmin, hit_i, hit_i2, hit_rho)
+                 : find_witness<D, kBatchItems>(src, g, L, nr, wmin, hit_i, hit_rho);
         if (lane == first) {
-            cs->slots[val].pair = (uint32_t)p;
+            cs->slots[val].pair = (uint32_t)v.p;
             cs->slots[val].i = hit_i;
+            cs->slots[val].i2 = hit_i2;
             cs->slots[val].rho = hit_rho;
         }
     }
-    if (val <= Lb && lane == 0) {
+    if (val <= v.L_before && lane == 0) {
         // U reached the bound before this pair: stop handing out its chunks;
         // the pair closes once the chunks already claimed are done
         if (atomicExch(&jb->exit_flag, 1u) == 0u) {
@@ -355,16 +441,21 @@ __device__ void advance(const BatchArgs &A, int c, int p, BatchJob *jb) {
 }
 
 __device__ void complete_chunk(const BatchArgs &A, int c, int p, BatchJob *jb) {
-    __threadfence();
+    // release: this chunk's atomics are performed before it counts as done
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     uint64_t prev = 0, expected = 0;
     if ((threadIdx.x & 63) == 0) {
         prev = atomicAdd((unsigned long long *)&jb->done, 1ull);
-        __threadfence();
-        expected = ld_acq(&jb->expected);
+        // read-modify-write read: the coherent value, including an exit's
+        // lowered count stored before the exiting chunk counted as done
+        expected = atomicAdd((unsigned long long *)&jb->expected, 0ull);
     }
     prev = uni64((uint64_t)__shfl((long long)prev, 0));
     expected = uni64((uint64_t)__shfl((long long)expected, 0));
-    if (prev + 1 == expected) advance(A, c, p, jb);
+    if (prev + 1 == expected) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        advance(A, c, p, jb);
+    }
 }
 
 }  // namespace
@@ -375,6 +466,8 @@ __global__ __launch_bounds__(256) void persistent_batch_kernel(BatchArgs A) {
     const int nc = A.n_codes;
     int cur = (int)(wave % (uint32_t)nc);
     const uint64_t t_start = wall_clock64();
+    JobView v;
+    bool have = false;             // v describes an open job worth claiming on
     for (;;) {
         if (A.deadline_ticks && wall_clock64() - t_start > A.deadline_ticks) break;
         if (A.serving) {
@@ -385,28 +478,43 @@ __global__ __launch_bounds__(256) void persistent_batch_kernel(BatchArgs A) {
         } else if (uni32(ld_rlx(&A.g->codes_done)) >= (uint32_t)nc) {
             break;
         }
-        // find a code with an open job: look at 64 slots at once from cur
-        bool found = false;
-        int c = cur;
-        int32_t st = 0;
-        {
-            const int probe = (cur + lane) % nc;
-            const int32_t s = ld_acq(&A.codes[probe].status);
-            const bool live = s == kSlotActive || s == kSlotPending;
-            const unsigned long long ball = __ballot(live);
-            if (ball) {
-                // start from this wave's own rotation among the live ones
-                const int pick = __builtin_ctzll(ball);
-                c = (cur + pick) % nc;
-                st = (int32_t)uni32((uint32_t)__shfl(s, pick));
-                found = true;
+        if (have) {
+            const uint64_t ch = wave_fetch_add(&v.jb->claim, 1ull);
+            if (ch < v.total) {
+                if (v.kind == 0) {
+                    table_chunk(A, &A.codes[v.c], ch);
+                } else {
+                    switch (v.D) {
+                        case 1: pair_chunk<1>(A, v, ch); break;
+                        case 2: pair_chunk<2>(A, v, ch); break;
+                        case 3: pair_chunk<3>(A, v, ch); break;
+                        case 4: pair_chunk<4>(A, v, ch); break;
+                        case 5: pair_chunk<5>(A, v, ch); break;
+                        case 6: pair_chunk<6>(A, v, ch); break;
+                        case 7: pair_chunk<7>(A, v, ch); break;
+                        default: pair_chunk<8>(A, v, ch); break;
+                    }
+                }
+                complete_chunk(A, v.c, v.p, v.jb);
+                continue;
             }
+            // this job is fully claimed: its code may open the next pair soon
+            have = false;
+            cur = v.c;
         }
-        if (!found) {
+        // find a code with an open job: 64 slots per look, relaxed reads
+        const int probe = (cur + lane) % nc;
+        const int32_t s = (int32_t)__hip_atomic_load(&A.codes[probe].status, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long live = __ballot(s == kSlotActive || s == kSlotPending);
+        if (!live) {
             cur = (cur + 64) % nc;
             __builtin_amdgcn_s_sleep(4);
             continue;
         }
+        const int pick = __builtin_ctzll(live);
+        const int c = (cur + pick) % nc;
+        const int32_t st = (int32_t)uni32((uint32_t)__shfl(s, pick));
         BatchCode *cs = &A.codes[c];
         if (st == kSlotPending) {
             // first wave to see the slot opens its table job
@@ -416,33 +524,23 @@ __global__ __launch_bounds__(256) void persistent_batch_kernel(BatchArgs A) {
             if (uni32((uint32_t)__shfl(won, 0))) open_tables(A, c);
             continue;
         }
-        const int nj = (int)uni32((uint32_t)ld_acq(&cs->njobs));
+        const int nj = (int)uni32((uint32_t)__hip_atomic_load(&cs->njobs, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT));
         if (nj <= 0) { cur = (c + 1) % nc; continue; }
+        // acquire once per job: everything written before the job was
+        // published (record, groups, tables) is visible from here on
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int p = nj - 1;
-        BatchJob *jb = job_at(A, uni32(ld_acq(&cs->job[p])));
-        const uint64_t ch = wave_fetch_add(&jb->claim, 1ull);
-        if (ch >= uni64(jb->total_chunks)) {   // nothing left to claim: look elsewhere
+        BatchJob *jb = job_at(A, uni32(cs->job[p]));
+        if (have && v.jb == jb) { cur = (c + 1) % nc; __builtin_amdgcn_s_sleep(2); continue; }
+        load_view(A, c, p, jb, v);
+        if (uni64(jb->claim) >= v.total) {     // nothing left to claim here
             cur = (c + 1) % nc;
             __builtin_amdgcn_s_sleep(2);
             continue;
         }
-        cur = c;                               // stay while the code has chunks
-        if (jb->kind == 0) {
-            table_chunk(A, cs, ch);
-        } else {
-            const int D = cs->sets[uni32((uint32_t)jb->j)].D;
-            switch (uni32((uint32_t)D)) {
-                case 1: pair_chunk<1>(A, c, p, jb, ch); break;
-                case 2: pair_chunk<2>(A, c, p, jb, ch); break;
-                case 3: pair_chunk<3>(A, c, p, jb, ch); break;
-                case 4: pair_chunk<4>(A, c, p, jb, ch); break;
-                case 5: pair_chunk<5>(A, c, p, jb, ch); break;
-                case 6: pair_chunk<6>(A, c, p, jb, ch); break;
-                case 7: pair_chunk<7>(A, c, p, jb, ch); break;
-                default: pair_chunk<8>(A, c, p, jb, ch); break;
-            }
-        }
-        complete_chunk(A, c, p, jb);
+        have = true;
+        cur = c;
     }
 }
 

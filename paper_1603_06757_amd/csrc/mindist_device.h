@@ -173,17 +173,22 @@ __device__ __forceinline__ void run_range(const uint32_t *tab, uint32_t i0, uint
 }
 
 
-// Where the left and right sums of one pair come from.
+// Where the left and right sums of one pair come from.  b is the size of the
+// (outer) right subsets; b2 > 0 selects the three-level split with inner
+// subsets of size b2 from table2.
 struct ItemSrc {
     const uint32_t *rows;      // k x DP
-    const uint32_t *table;     // right table
+    const uint32_t *table;     // right (outer) table
     const uint32_t *ltable;    // left table or nullptr (lanes unrank)
     const uint64_t *binom;     // full binomial table (unranking)
     const uint64_t *colA;      // C(x, a) = colA[x * sA]
     const uint64_t *colB;      // C(x, b) = colB[x * sB]
     int sA, sB;
-    uint64_t n_items;          // C(k-b, a)
+    uint64_t n_items;          // C(k-b-b2, a)
     int k, a, b;
+    int b2;
+    const uint32_t *table2;    // inner table
+    const uint32_t *cnt2;      // inner entries of each outer entry
 };
 
 // The part of the pair one chunk covers: left tile lt, right entries
@@ -222,7 +227,7 @@ __device__ __forceinline__ void run_chunk(const ItemSrc &s, ChunkGeo &g, uint32_
 #pragma unroll
             for (int d = 0; d < D; ++d) L[t][d] = s.ltable[rc * DP + d];
             e = max((int)g.e_first, s.a - 1);
-            int hi = s.k - 1 - s.b;     // the largest e with a right partner
+            int hi = s.k - 1 - s.b - s.b2;   // the largest e with a right partner
             while (e < hi) {
                 const int mid = (e + hi + 1) >> 1;
                 if (s.colA[(size_t)mid * s.sA] <= rc) e = mid; else hi = mid - 1;
@@ -276,6 +281,187 @@ __device__ __forceinline__ int find_witness(const ItemSrc &s, const ChunkGeo &g,
         for (int t = 0; t < B; ++t) {
             const uint32_t w = weight_of<D>(L[t], e);
             if (hit_t < 0 && i < nr[t] && w == wmin) { hit_t = t; hit_i = i; }
+        }
+    }
+    const unsigned long long ball = __ballot(hit_t >= 0);
+    const int first = ball ? __builtin_ctzll(ball) : -1;
+    hit_rho = 0;
+    if (lane == first) {
+        const uint64_t tile0 = g.lt * (64ull * B) + lane;
+#pragma unroll
+        for (int t = 0; t < B; ++t)
+            if (t == hit_t) {
+                hit_rho = tile0 + (uint64_t)t * 64;
+                if (hit_rho >= s.n_items) hit_rho = s.n_items - 1;
+            }
+    }
+    return first;
+}
+
+// Inner loop of the three-level split: entries [0, n2) of the inner table
+// against lane sums L2 (= left sum ^ outer entry); per item minimum and
+// (SUM) weight sum.  Same pipelined scalar loads as run_range.
+template <int D, int B, bool SUM>
+__device__ __forceinline__ void run_inner(const uint32_t *tab, uint32_t n2, const uint32_t (&L2)[B][D],
+                                          uint32_t (&mi)[B], uint32_t (&wsi)[B]) {
+    constexpr int U = block_of<D>();
+    cu32 *ct = (cu32 *)tab;
+    uint32_t i = 0;
+    if (n2 >= 2 * U) {
+        uint32_t cur[U][D], nxt[U][D];
+#pragma unroll
+        for (int u = 0; u < U; ++u) load_entry<D>(ct, i + u, cur[u]);
+        for (; i + 2 * U <= n2; i += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) load_entry<D>(ct, i + U + u, nxt[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int t = 0; t < B; ++t) {
+                    const uint32_t w = weight_of<D>(L2[t], cur[u]);
+                    if (SUM) wsi[t] += w;
+                    mi[t] = min(mi[t], w);
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int d = 0; d < D; ++d) cur[u][d] = nxt[u][d];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                const uint32_t w = weight_of<D>(L2[t], cur[u]);
+                if (SUM) wsi[t] += w;
+                mi[t] = min(mi[t], w);
+            }
+        i += U;
+    }
+    for (; i < n2; ++i) {
+        uint32_t e[D];
+        load_entry<D>(ct, i, e);
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            const uint32_t w = weight_of<D>(L2[t], e);
+            if (SUM) wsi[t] += w;
+            mi[t] = min(mi[t], w);
+        }
+    }
+}
+
+// Lane items of a chunk: left sums L and outer range lengths nr; returns the
+// wave-uniform min of nr and clips g.i_end (right-major order) to the max.
+template <int D, int B>
+__device__ __forceinline__ uint32_t setup_items(const ItemSrc &s, ChunkGeo &g, uint32_t (&L)[B][D],
+                                                uint32_t (&nr)[B]) {
+    constexpr int DP = dp_of(D);
+    const int lane = threadIdx.x & 63;
+    const uint64_t tile0 = g.lt * (64ull * B) + lane;
+    uint32_t nr_lane_min = kInf, nr_lane_max = 0;
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+        const uint64_t rho = tile0 + (uint64_t)t * 64;
+        const uint64_t rc = rho < s.n_items ? rho : s.n_items - 1;
+#pragma unroll
+        for (int d = 0; d < D; ++d) L[t][d] = 0;
+        int e;
+        if (s.ltable) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) L[t][d] = s.ltable[rc * DP + d];
+            e = max((int)g.e_first, s.a - 1);
+            int hi = s.k - 1 - s.b - s.b2;
+            while (e < hi) {
+                const int mid = (e + hi + 1) >> 1;
+                if (s.colA[(size_t)mid * s.sA] <= rc) e = mid; else hi = mid - 1;
+            }
+        } else {
+            e = unrank_add<D>(s.binom, s.rows, DP, rc, s.a, s.k, L[t], false, s.k);
+        }
+        nr[t] = (uint32_t)s.colB[(size_t)(s.k - 1 - s.b2 - e) * s.sB];
+        nr_lane_min = min(nr_lane_min, nr[t]);
+        nr_lane_max = max(nr_lane_max, nr[t]);
+    }
+    if (g.clip) g.i_end = min(g.i_end, wave_max_u32(nr_lane_max));
+    return wave_min_u32(nr_lane_min);
+}
+
+// One chunk of the three-level split: outer entries [i_begin, i_end) of
+// table (b-subsets Y1), for each the inner entries [0, C(zmin, b2)) of
+// table2.  Outputs as run_chunk.
+template <int D, int B, bool VERIFY>
+__device__ __forceinline__ void run_chunk3(const ItemSrc &s, ChunkGeo &g, uint32_t (&L)[B][D],
+                                           uint32_t (&nr)[B], uint32_t &lmin, uint64_t &cnt,
+                                           uint32_t &ws) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t tile0 = g.lt * (64ull * B) + lane;
+    const uint32_t nr_min = setup_items<D, B>(s, g, L, nr);
+    const uint32_t fast_end = min(g.i_end, max(g.i_begin, nr_min));
+    cu32 *ct = (cu32 *)s.table;
+    cu32 *cn = (cu32 *)s.cnt2;
+    uint32_t m[B];
+    bool valid[B];
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+        m[t] = kInf;
+        valid[t] = tile0 + (uint64_t)t * 64 < s.n_items;
+    }
+    cnt = 0;
+    ws = 0;
+    for (uint32_t i1 = g.i_begin; i1 < g.i_end; ++i1) {
+        uint32_t s1[D];
+        load_entry<D>(ct, i1, s1);
+        const uint32_t n2 = cn[i1];
+        uint32_t L2[B][D], mi[B], wsi[B];
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            mi[t] = kInf;
+            wsi[t] = 0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) L2[t][d] = L[t][d] ^ s1[d];
+        }
+        run_inner<D, B, VERIFY>(s.table2, n2, L2, mi, wsi);
+        const bool all_on = i1 < fast_end;
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            const bool on = all_on || i1 < nr[t];
+            if (on) m[t] = min(m[t], mi[t]);
+            if (on && valid[t]) {
+                cnt += n2;
+                if (VERIFY) ws += wsi[t];
+            }
+        }
+    }
+    lmin = kInf;
+#pragma unroll
+    for (int t = 0; t < B; ++t) lmin = min(lmin, m[t]);
+}
+
+// Three-level witness search: the first (item, i1, i2) of the chunk with
+// weight wmin; returns the holding lane (or -1).
+template <int D, int B>
+__device__ __forceinline__ int find_witness3(const ItemSrc &s, const ChunkGeo &g,
+                                             const uint32_t (&L)[B][D], const uint32_t (&nr)[B],
+                                             uint32_t wmin, uint32_t &hit_i, uint32_t &hit_i2,
+                                             uint64_t &hit_rho) {
+    const int lane = threadIdx.x & 63;
+    hit_i = hit_i2 = kInf;
+    int hit_t = -1;
+    cu32 *ct = (cu32 *)s.table;
+    cu32 *c2 = (cu32 *)s.table2;
+    for (uint32_t i1 = g.i_begin; i1 < g.i_end && hit_t < 0; ++i1) {
+        uint32_t s1[D];
+        load_entry<D>(ct, i1, s1);
+        const uint32_t n2 = s.cnt2[i1];
+        for (uint32_t i2 = 0; i2 < n2 && hit_t < 0; ++i2) {
+            uint32_t e[D];
+            load_entry<D>(c2, i2, e);
+#pragma unroll
+            for (int d = 0; d < D; ++d) e[d] ^= s1[d];
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                const uint32_t w = weight_of<D>(L[t], e);
+                if (hit_t < 0 && i1 < nr[t] && w == wmin) { hit_t = t; hit_i = i1; hit_i2 = i2; }
+            }
         }
     }
     const unsigned long long ball = __ballot(hit_t >= 0);

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -39,8 +40,9 @@ struct GammaDev {
     int D = 0, DP = 0;         // dwords carried / stored per row
     bool stripped = false;     // identity columns removed (weight offset w)
     uint32_t *rows = nullptr;  // device, k x DP
-    std::map<int, uint32_t *> tables;   // b -> device right table
-    std::map<int, uint32_t *> ltables;  // a -> device left table
+    // saved-sum tables keyed by (kind, size, shift): kind 0 left, 1 right
+    // (shift 0) or outer (shift = b2, with inner counts)
+    std::map<std::tuple<int, int, int>, std::pair<uint32_t *, uint32_t *>> tabs;
     int bcap = 0;              // largest b whose table fits the cap
 };
 
@@ -87,8 +89,10 @@ static void free_ctx(mindist_ctx *c) {
     if (!c) return;
     for (auto &g : c->gd) {
         dev_free(g.rows);
-        for (auto &kv : g.tables) dev_free(kv.second);
-        for (auto &kv : g.ltables) dev_free(kv.second);
+        for (auto &kv : g.tabs) {
+            dev_free(kv.second.first);
+            dev_free(kv.second.second);
+        }
     }
     dev_free(c->d_state);
     dev_free(c->d_groups);
@@ -126,23 +130,36 @@ static int upload_gamma(mindist_ctx *c, int j) {
     return MINDIST_OK;
 }
 
-// saved sums of all r-subsets of the rows of Gamma_j: the right table
-// (reflected rows) or the left table; built once and kept with the context
-static int get_table(mindist_ctx *c, int j, int r, bool right, uint32_t **out) {
+// saved sums of r-subsets of the rows of Gamma_j (see TableArgs): built once
+// per (kind, r, shift) and kept with the context.  kind 0 = left table,
+// 1 = right table (shift 0) or outer table of a three-level split (shift b2).
+static int get_table(mindist_ctx *c, int j, int r, int kind, int shift, uint32_t **out,
+                     uint32_t **cnt_out = nullptr) {
     GammaDev &g = c->gd[j];
-    auto &cache = right ? g.tables : g.ltables;
-    auto it = cache.find(r);
-    if (it != cache.end()) { *out = it->second; return MINDIST_OK; }
-    const uint64_t ent = BN()(c->P.k, r);
+    const auto key = std::make_tuple(kind, r, shift);
+    auto it = g.tabs.find(key);
+    if (it != g.tabs.end()) {
+        *out = it->second.first;
+        if (cnt_out) *cnt_out = it->second.second;
+        return MINDIST_OK;
+    }
+    const uint64_t ent = BN()(c->P.k - shift, r);
     uint32_t *t = static_cast<uint32_t *>(dev_alloc(ent * g.DP * 4));
-    if (!t) return fail(MINDIST_E_NOMEM, "saved-sum table allocation failed");
-    TableArgs ta{g.rows, c->d_binom, t, ent, c->P.k, r, g.DP, right ? 1 : 0};
+    uint32_t *cn = shift ? static_cast<uint32_t *>(dev_alloc(ent * 4)) : nullptr;
+    if (!t || (shift && !cn)) {
+        dev_free(t);
+        dev_free(cn);
+        return fail(MINDIST_E_NOMEM, "saved-sum table allocation failed");
+    }
+    TableArgs ta{g.rows, c->d_binom, t, cn, ent, c->P.k, r, g.DP, kind ? 1 : 0, shift};
     if (launch_build_table(ta, g.D, c->stream)) {
         dev_free(t);
+        dev_free(cn);
         return fail(MINDIST_E_HIP, "table kernel launch failed");
     }
-    cache[r] = t;
+    g.tabs[key] = {t, cn};
     *out = t;
+    if (cnt_out) *cnt_out = cn;
     return MINDIST_OK;
 }
 
@@ -294,7 +311,7 @@ extern "C" int mindist_info(const mindist_ctx *c, int *m_full, int *k_partial, i
 namespace {
 
 struct PairPlan {
-    int a = 0, b = 0;
+    int a = 0, b = 0, b2 = 0;   // |X| per lane, outer |Y1| (or right |Y|), inner |Y2|
     uint32_t T = 0;
     uint32_t n_rt = 0;         // right tiles (right-major order)
     uint64_t n_items = 0, total_chunks = 0;
@@ -312,33 +329,37 @@ PairPlan plan_pair(const mindist_ctx *c, int j, int w, GroupEntry *groups,
     const int k = c->P.k;
     const Binom &B = BN();
     PairPlan pp;
-    pp.b = std::min(w / 2, c->gd[j].bcap);
-    pp.a = w - pp.b;
+    const Split sp = choose_split(k, w, c->gd[j].bcap, false);
+    pp.a = sp.a;
+    pp.b = sp.b;
+    pp.b2 = sp.b2;
     const uint64_t TB = 64ull * c->items;   // left subsets per tile
-    pp.n_items = B(k - pp.b, pp.a);
-    // right tile length: the caller's, else about 12 chunks per resident
-    // wave so the last chunks of the pair leave little idle time, within
-    // [256, 1024] so the per-chunk setup stays amortised
+    pp.n_items = B(k - pp.b - pp.b2, pp.a);
     if (c->tile_t) {
         pp.T = c->tile_t;
-    } else {
+    } else if (pp.b2 == 0) {
+        // right tile length: about 12 chunks per resident wave so the last
+        // chunks of the pair leave little idle time, within [256, 1024] so the
+        // per-chunk setup stays amortised
         const uint64_t waves = (uint64_t)c->cus * c->blocks_per_cu * 4;
         const uint64_t want = B(k, w) / (TB * waves * 12);
         uint32_t T = 256;
         while (T < 1024 && T < want) T <<= 1;
         pp.T = T;
+    } else {
+        pp.T = outer_tile(k, sp, (uint32_t)TB);
     }
     const uint64_t tiles = ceil_div(pp.n_items, TB);
     uint64_t base = 0;
     std::vector<uint64_t> lt_end;
-    for (int e = pp.a - 1; e <= k - 1 - pp.b; ++e) {
+    for (int e = pp.a - 1; e <= k - 1 - pp.b - pp.b2; ++e) {
         const uint64_t lo = B(e, pp.a), hi = B(e + 1, pp.a);
         const uint64_t lt_lo = ceil_div(lo, TB), lt_hi = std::min(ceil_div(hi, TB), tiles);
         if (lt_hi <= lt_lo) continue;
         GroupEntry &g = groups[pp.ngroups++];
         g.chunk_base = base;
         g.lt_begin = lt_lo;
-        g.nr_first = (uint32_t)B(k - 1 - e, pp.b);
+        g.nr_first = (uint32_t)B(k - 1 - pp.b2 - e, pp.b);
         g.n_rt = ceil_div(g.nr_first, pp.T);
         g.e = (uint32_t)e;
         base += (lt_hi - lt_lo) * g.n_rt;
@@ -426,11 +447,15 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
                 HIPCHK(hipMemcpyAsync(c->d_rprefix, c->h_rprefix, rpre.size() * 8,
                                       hipMemcpyHostToDevice, c->stream));
             }
-            uint32_t *table = nullptr, *ltable = nullptr;
-            int e = get_table(c, j, pp.b, true, &table);
+            uint32_t *table = nullptr, *ltable = nullptr, *table2 = nullptr, *cnt2 = nullptr;
+            int e = get_table(c, j, pp.b, 1, pp.b2, &table, &cnt2);
             if (e) return e;
+            if (pp.b2) {
+                e = get_table(c, j, pp.b2, 1, 0, &table2);
+                if (e) return e;
+            }
             if (c->left_tables && left_table_fits(c, j, pp.a)) {
-                e = get_table(c, j, pp.a, false, &ltable);
+                e = get_table(c, j, pp.a, 0, 0, &ltable);
                 if (e) return e;
             }
             HIPCHK(hipMemcpyAsync(c->d_groups, c->h_groups, sizeof(GroupEntry) * pp.ngroups,
@@ -449,6 +474,9 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
             pa.k = k;
             pa.a = pp.a;
             pa.b = pp.b;
+            pa.b2 = pp.b2;
+            pa.table2 = table2;
+            pa.cnt2 = cnt2;
             pa.T = pp.T;
             pa.offset = g.stripped ? (uint32_t)w : 0u;
             pa.L_prev = (uint32_t)L;
@@ -492,6 +520,8 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
             rec.ms = ms;
             rec.dwords = g.D;
             rec.split_a = pp.a;
+            rec.split_b = pp.b;
+            rec.split_b2 = pp.b2;
             c->trace.push_back(rec);
             executed_total += hp->executed;
             canonical_total += rec.count;
@@ -537,14 +567,8 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
         if (s.pair >= (uint32_t)c->trace.size())
             return fail(MINDIST_E_HIP, "witness slot holds an invalid pair index");
         const mindist_pair &pr = c->trace[s.pair];
-        const int a = pr.split_a, b = pr.w - a;
-        int X[MINDIST_MAX_LEVEL + 1], Z[MINDIST_MAX_LEVEL + 1];
-        colex_unrank(s.rho, a, k, X);
-        colex_unrank(s.i, b, k, Z);
-        std::vector<int> rows(X, X + a);
-        for (int t = 0; t < b; ++t) rows.push_back(k - 1 - Z[t]);
-        std::sort(rows.begin(), rows.end());
-        if (std::adjacent_find(rows.begin(), rows.end()) != rows.end() || (int)rows.size() != pr.w)
+        const std::vector<int> rows = witness_rows(k, pr.split_a, pr.split_b, pr.split_b2, s);
+        if ((int)rows.size() != pr.w)
             return fail(MINDIST_E_HIP, "witness slot decodes to an invalid combination");
         uint64_t word[MINDIST_MAX_WORDS] = {0};
         for (int r : rows) {

@@ -16,6 +16,13 @@
 // Left subsets in colex order are grouped by their maximum e, and the right
 // ranges of larger e are prefixes of those of smaller e, so a wave whose 64*B
 // items straddle several e runs one loop and masks lanes past their range.
+//
+// Three-level split (large w with small saved tables): X u Y1 u Y2 with
+// |X| = a per lane, Y1 a b1-subset of rows (max X, k-b2) from the outer
+// table (uniform loop) and Y2 a b2-subset of rows (max Y1, k) from the inner
+// table (uniform inner loop over its first C(k-1-max Y1, b2) entries).  The
+// inner loop is the two-level hot loop with the lane sums L ^ Y1 held fixed,
+// so a lane subset covers C(k-1-e, b1+b2) codewords instead of C(k-1-e, b).
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
@@ -51,8 +58,11 @@ struct PairStat {
 
 struct Slot {              // witness of weight v: written once, by the wave
     uint32_t pair;         // whose atomicMin moved U_found down to v
-    uint32_t i;            // right table index
+    uint32_t i;            // right (outer) table index
+    uint32_t i2;           // inner table index (three-level split only)
+    uint32_t pad;
     uint64_t rho;          // colex rank of the left subset
+    uint64_t pad2;
 };
 
 struct DevState {
@@ -88,6 +98,8 @@ struct PairArgs {
     const uint32_t *table;     // right table: C(k,b) entries x dp words
     const uint32_t *ltable;    // left table: entry rho = rows of colex_unrank_a(rho)
                                // (nullptr: lanes unrank and add the rows themselves)
+    const uint32_t *table2;    // three-level split: inner right table (b2-subsets)
+    const uint32_t *cnt2;      // three-level split: inner entries of each outer entry
     const uint64_t *binom;     // kBinomX x kBinomT
     const GroupEntry *groups;  // left-tile-major chunk order (order = 0)
     const uint64_t *rprefix;   // right-tile-major order (order = 1): chunk ids
@@ -97,6 +109,7 @@ struct PairArgs {
     uint64_t total_chunks;
     uint64_t cancel_after;     // 0 = off
     int32_t ngroups, k, a, b;
+    int32_t b2;                // 0: two-level split (left | right), else inner size
     uint32_t T;                // right tile length
     uint32_t offset;           // added to every weight (w for identity-stripped rows)
     uint32_t L_prev;           // bound before the pair (exit threshold)
@@ -109,13 +122,19 @@ struct PairArgs {
     uint32_t pad;
 };
 
+// Saved sums of r-subsets: entry i is the sum of the rows of colex_unrank_r(i)
+// (left table, reflect = 0) or of the rows {k-1-shift-z} (right tables,
+// reflect = 1; shift = b2 > 0 builds the outer table of a three-level split
+// over rows [0, k-b2), with cnt2[i] = C(b2 + min z, b2) inner entries).
 struct TableArgs {
     const uint32_t *rows;
     const uint64_t *binom;
     uint32_t *table;
+    uint32_t *cnt2;            // outer tables only (else nullptr)
     uint64_t entries;
     int32_t k, b, dp;
-    int32_t reflect;           // 1: right table (rows k-1-z), 0: left table (rows z)
+    int32_t reflect;
+    int32_t shift;
 };
 
 // kernel launchers (mindist_kernels.hip)
@@ -125,5 +144,45 @@ int launch_build_table(const TableArgs &ta, int D, void *stream);
 int launch_enum_pair(const PairArgs &pa, int D, int items, int verify, int blocks, void *stream);
 int max_dwords();
 int launch_peak(const uint32_t *tab, uint32_t steps, uint32_t *out, int D, int blocks, void *stream);
+
+// Split of the w rows of a pair between the levels, chosen identically by
+// the host planner and the persistent batch scheduler.  The balanced
+// two-level split (b = min(w/2, bcap)) is kept while a typical left subset
+// (maximum e at the expected position (k-b)a/(a+1)) has at least
+// kSplitShortRun right entries.  Otherwise the right side takes a second
+// table level of b2 = bcap rows (min(bcap, w-2) unless fixed_b2) and the
+// smallest left size a that still gives kSplitMinItems left subsets and no
+// more than kSplitMaxInner inner entries per outer entry on average (so one
+// outer entry never holds more than a few microseconds of work).
+constexpr uint64_t kSplitShortRun = 256;
+constexpr uint64_t kSplitMinItems = 2048;
+constexpr uint64_t kSplitMaxInner = 4096;
+
+template <class BinomFn>
+MD_HD inline void split_rows(int k, int w, int bcap, bool fixed_b2, const BinomFn &C,
+                             int &a, int &b, int &b2) {
+    b = w / 2 < bcap ? w / 2 : bcap;
+    a = w - b;
+    b2 = 0;
+    if (w < 5) return;
+    const int e_typ = (k - b) * a / (a + 1);
+    if (C(k - 1 - e_typ, b) >= kSplitShortRun) return;
+    const int s2 = fixed_b2 ? bcap : (bcap < w - 2 ? bcap : w - 2);
+    if (s2 < 1 || s2 > w - 2) return;
+    for (int aa = 1; aa <= w - 2; ++aa) {
+        const int b1 = w - aa - s2;
+        if (b1 < 1) break;
+        if (b1 > bcap) continue;
+        if (C(k - b1 - s2, aa) < kSplitMinItems) continue;
+        const int e = (k - b1 - s2) * aa / (aa + 1);
+        const uint64_t outer = C(k - 1 - s2 - e, b1);
+        const uint64_t both = C(k - 1 - e, b1 + s2);
+        if (outer == 0 || both / outer > kSplitMaxInner) continue;
+        a = aa;
+        b = b1;
+        b2 = s2;
+        return;
+    }
+}
 
 }  // namespace md

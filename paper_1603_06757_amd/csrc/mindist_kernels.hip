@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
     }
     __syncthreads();
     const ItemSrc src{p.rows, p.table, p.ltable, p.binom, colA, colB, 1, 1,
-                      p.n_items, p.k, p.a, p.b};
+                      p.n_items, p.k, p.a, p.b, p.b2, p.table2, p.cnt2};
     uint32_t rt_cur = 0;
     uint32_t moved = 0;
     uint32_t U_seen = kInf;
@@ -101,7 +101,8 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
         }
         uint32_t L[B][D], nr[B], lmin, ws;
         uint64_t cnt;
-        run_chunk<D, B, VERIFY>(src, g, L, nr, lmin, cnt, ws);
+        if (p.b2) run_chunk3<D, B, VERIFY>(src, g, L, nr, lmin, cnt, ws);
+        else run_chunk<D, B, VERIFY>(src, g, L, nr, lmin, cnt, ws);
         run_min = min(run_min, lmin);
         run_cnt += cnt;
         if (VERIFY) run_ws += ws;
@@ -116,12 +117,14 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
         U_seen = min(old, val);
         if (old > val) {
             // this wave moved U_found to val: it alone writes slot[val]
-            uint32_t hit_i;
+            uint32_t hit_i, hit_i2 = 0;
             uint64_t hit_rho;
-            const int first = find_witness<D, B>(src, g, L, nr, wmin, hit_i, hit_rho);
+            const int first = p.b2 ? find_witness3<D, B>(src, g, L, nr, wmin, hit_i, hit_i2, hit_rho)
+                                   : find_witness<D, B>(src, g, L, nr, wmin, hit_i, hit_rho);
             if (lane == first) {
                 slots[val].pair = p.pair;
                 slots[val].i = hit_i;
+                slots[val].i2 = hit_i2;
                 slots[val].rho = hit_rho;
             }
         }
@@ -181,9 +184,9 @@ int launch_peak(const uint32_t *tab, uint32_t steps, uint32_t *out, int D, int b
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Right table (reflect = 1): entry i = sum of the rows {k-1-z : z in
-// colex_unrank_b(i)}.  Left table (reflect = 0): entry rho = sum of the rows
-// of colex_unrank_a(rho).
+// Saved sums (see TableArgs): entry i = rows of colex_unrank_b(i) (left) or
+// rows {k-1-shift-z} (right / outer); outer tables also record the number of
+// inner entries C(shift + min z, shift) above each entry.
 template <int D>
 __global__ __launch_bounds__(256) void build_table_kernel(TableArgs ta) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -191,10 +194,25 @@ __global__ __launch_bounds__(256) void build_table_kernel(TableArgs ta) {
     uint32_t acc[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) acc[d] = 0;
-    unrank_add<D>(ta.binom, ta.rows, ta.dp, i, ta.b, ta.k, acc, ta.reflect != 0, ta.k);
+    uint64_t rho = i;
+    int hi = ta.k - ta.shift, zmin = 0;
+    for (int t = ta.b; t >= 1; --t) {
+        int lo = t - 1, h = hi - 1;
+        while (lo < h) {
+            const int mid = (lo + h + 1) >> 1;
+            if (binom(ta.binom, mid, t) <= rho) lo = mid; else h = mid - 1;
+        }
+        rho -= binom(ta.binom, lo, t);
+        hi = lo;
+        zmin = lo;
+        const int r = ta.reflect ? (ta.k - 1 - ta.shift - lo) : lo;
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc[d] ^= ta.rows[(size_t)r * ta.dp + d];
+    }
 #pragma unroll
     for (int d = 0; d < D; ++d) ta.table[i * ta.dp + d] = acc[d];
     for (int d = D; d < ta.dp; ++d) ta.table[i * ta.dp + d] = 0;
+    if (ta.cnt2) ta.cnt2[i] = (uint32_t)binom(ta.binom, ta.shift + zmin, ta.shift);
 }
 
 __global__ void init_state_kernel(DevState *st, int max_pairs) {

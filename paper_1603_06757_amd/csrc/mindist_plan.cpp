@@ -155,6 +155,40 @@ void colex_unrank(uint64_t rho, int r, int hi, int *out) {
 }
 
 
+Split choose_split(int k, int w, int bcap, bool fixed_b2) {
+    const Binom &B = BN();
+    Split sp{0, 0, 0};
+    split_rows(k, w, bcap, fixed_b2, [&](int x, int r) { return B(x, r); }, sp.a, sp.b, sp.b2);
+    return sp;
+}
+
+uint32_t outer_tile(int k, const Split &sp, uint32_t tile_items) {
+    const Binom &B = BN();
+    const int e = (k - sp.b - sp.b2) * sp.a / (sp.a + 1);
+    const uint64_t outer = B(k - 1 - sp.b2 - e, sp.b);
+    const uint64_t both = B(k - 1 - e, sp.b + sp.b2);
+    const double n2 = outer ? (double)both / (double)outer : 1.0;
+    const double want = 262144.0 / ((double)tile_items * (n2 > 1 ? n2 : 1));
+    uint32_t T = 1;
+    while (T < 1024 && T * 2 <= want) T <<= 1;
+    return T;
+}
+
+std::vector<int> witness_rows(int k, int a, int b, int b2, const Slot &s) {
+    int X[MINDIST_MAX_LEVEL + 1], Z[MINDIST_MAX_LEVEL + 1];
+    colex_unrank(s.rho, a, k, X);
+    colex_unrank(s.i, b, k - b2, Z);
+    std::vector<int> rows(X, X + a);
+    for (int t = 0; t < b; ++t) rows.push_back(k - 1 - b2 - Z[t]);
+    if (b2) {
+        colex_unrank(s.i2, b2, k, Z);
+        for (int t = 0; t < b2; ++t) rows.push_back(k - 1 - Z[t]);
+    }
+    std::sort(rows.begin(), rows.end());
+    if (std::adjacent_find(rows.begin(), rows.end()) != rows.end()) rows.clear();
+    return rows;
+}
+
 std::vector<int> carried_columns(const Plan &P, int j) {
     std::vector<int> cols;
     if (j < P.m_full) {

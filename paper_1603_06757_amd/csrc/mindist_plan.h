@@ -58,4 +58,19 @@ int bound_after(int k, int m_full, int k_m, int n_gamma, int j, int w);
 // colex unranking of rho into an r-subset of [0, hi) (elements ascending)
 void colex_unrank(uint64_t rho, int r, int hi, int *out);
 
+// How one pair's w-subsets are split (see mindist_internal.h): a rows per
+// lane, b rows from the (outer) right table, b2 rows from the inner table
+// (0: two-level).  The two-level split b = min(w/2, bcap) is kept unless a
+// lane subset would typically meet fewer than 1024 right entries; then the
+// three-level split with b2 = min(bcap, w-2) (fixed_b2: exactly bcap) and the
+// smallest a leaving at least 2048 lane subsets.
+struct Split { int a, b, b2; };
+Split choose_split(int k, int w, int bcap, bool fixed_b2);
+// outer-table entries per chunk of a three-level pair: about 256K codewords
+// per chunk of tile_items lane subsets
+uint32_t outer_tile(int k, const Split &sp, uint32_t tile_items);
+// rows of the witness recorded in a slot (ascending); empty if invalid
+struct Slot;
+std::vector<int> witness_rows(int k, int a, int b, int b2, const Slot &s);
+
 }  // namespace md

@@ -248,6 +248,36 @@ def test_chunk_orders_and_dispensers(order, counters, items, left):
         compare_with_trace(res, gold["trace"], gold["counts"], gold["pair_min"], gold["wsum"], w.k)
 
 
+@pytest.mark.parametrize("table_mib", [1, 4])
+def test_three_level_split_small_tables(table_mib):
+    """Small saved tables force the three-level split (lane subset, outer
+    table, inner table) on the larger levels of [255,40], whose two-level
+    right runs become short; results must not change."""
+    for name in ["rand48x24", "rand150x75", "rand255x40"]:
+        gold = json.load(open(os.path.join(GOLDEN, f"{name}.json")))
+        w = WORKLOADS[name]
+        say(name, "table_mib", table_mib)
+        res = md.min_distance(w.matrix(), w.n, w.k, table_mib=table_mib, verify=1)
+        assert any(p["split_b2"] > 0 for p in res["pairs"]) or name != "rand255x40"
+        compare_with_trace(res, gold["trace"], gold["counts"], gold["pair_min"], gold["wsum"], w.k)
+        check_witness(w.matrix(), w.n, w.k, res)
+    rng = PCG32(31337, 5)
+    done = 0
+    while done < 40:
+        n = rng.uniform_int(40, 200)
+        k = rng.uniform_int(10, min(n - 1, 60))
+        if estimated_work(n, k) > 3e7:
+            continue
+        G = draw_matrix(rng, n, k)
+        try:
+            oracle.partition(G, n, k)
+        except oracle.OracleError:
+            continue
+        say("random small tables", n, k)
+        run_and_compare(G, n, k, verify=True, table_mib=table_mib)
+        done += 1
+
+
 def test_max_width_code():
     """n = 512 (8 words, 16 dwords per row), many information sets."""
     G = random_generator(512, 20, 512, 0)

@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_DWORD_OPS = 256 * 64 * 2.4e9 / 2      # 32-bit XOR+popcount per second
+LANE_ITEMS = 4                              # left subsets per lane (library default)
 
 
 def single_code_leg(steps: int, warmup: int):
@@ -72,7 +73,7 @@ def roofline(results):
         "unit": "T 32-bit xor+popcount/s",
         "frac": achieved / PEAK_DWORD_OPS,
         "traffic": None,
-        "kernel": f"md::enum_pair_kernel<{D}, 2, false>",
+        "kernel": f"md::enum_pair_kernel<{D}, {LANE_ITEMS}, false>",
         "launches": launches,
         "avg_launch_us": sec / launches * 1e6,
         "ops_per_launch": cw * D / launches,
@@ -100,17 +101,38 @@ def cpu_baseline(w, seconds: float = 12.0):
                       f"{t_used:.1f}s, stack-based enumeration, full-width rows"}
 
 
+def copy_probe(mib: int):
+    """Plain device-to-device copies of a known size: the reference reading
+    for the FETCH_SIZE / WRITE_SIZE counters (each copy reads and writes
+    mib MiB)."""
+    import torch
+    n = mib << 20
+    x = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    print(json.dumps({"copy_probe_mib": mib, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run plain device copies of this size (counter reference) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
         print("this benchmark runs on one GPU only (single-GPU build); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if a.copy_probe_mib:
+        copy_probe(a.copy_probe_mib)
+        return
     w, results, dt = single_code_leg(a.steps, a.warmup)
     ref = results[0]
     for r in results:

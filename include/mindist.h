@@ -180,7 +180,7 @@ typedef struct mindist_batch_opts {
     int32_t tile_max;
     int32_t blocks_per_cu;    /* resident workgroups per CU (0 = 4) */
     int32_t use_graph;        /* 1 = run as one captured hipGraph (default), 0 = plain launch */
-    int32_t table_kib;        /* cap on one saved right-sum table in KiB (0 = 8192) */
+    int32_t table_kib;        /* cap on one saved right-sum table in KiB (0 = 65536) */
     int32_t jobs_per_code;    /* job-arena sizing: average jobs per code (0 = 96) */
     double  deadline_s;       /* wall-clock limit of the launch; waves leave after it and the
                                  call returns MINDIST_E_TIMEOUT (0 = none) */
@@ -192,6 +192,16 @@ typedef struct mindist_batch_opts {
     double  seconds_total;    /* out: wall clock of the call */
     double  seconds_prep;     /* out: host preprocessing (information sets, packing) */
     uint64_t executed_total;  /* out: codewords evaluated */
+    /* out: profile of the launch, summed over its waves: seconds spent in
+     * table chunks, in enumeration chunks and in job completion (flushes and
+     * the opening of the next job); the rest of waves * seconds_kernel is
+     * spent looking for work */
+    double  wave_s_table, wave_s_pair, wave_s_flush;
+    int64_t waves;            /* out: waves of the launch */
+    uint64_t chunks_table, chunks_pair;   /* out: chunks run of each kind */
+    double  *done_s;          /* optional, caller-owned, B entries: seconds from the first
+                                 code's start on the device to code i's completion (-1 if
+                                 it did not run) */
 } mindist_batch_opts;
 
 /* Solve B codes in one persistent launch: a device-side scheduler hands out

@@ -76,7 +76,9 @@ class BatchOpts(C.Structure):
                 ("deadline_s", C.c_double), ("stream", C.c_int64), ("pairs", C.c_void_p), ("pairs_cap", C.c_int64),
                 ("pairs_index", C.c_void_p), ("seconds_kernel", C.c_double),
                 ("seconds_total", C.c_double), ("seconds_prep", C.c_double),
-                ("executed_total", C.c_uint64)]
+                ("executed_total", C.c_uint64), ("wave_s_table", C.c_double),
+                ("wave_s_pair", C.c_double), ("wave_s_flush", C.c_double), ("waves", C.c_int64),
+                ("chunks_table", C.c_uint64), ("chunks_pair", C.c_uint64), ("done_s", C.c_void_p)]
 
 
 class ServerOpts(C.Structure):
@@ -246,6 +248,8 @@ def run_batch(codes, tile_min: int = 0, tile_max: int = 0, blocks_per_cu: int = 
     o.tile_min, o.tile_max, o.blocks_per_cu = tile_min, tile_max, blocks_per_cu
     o.use_graph, o.table_kib, o.jobs_per_code = use_graph, table_kib, jobs_per_code
     o.deadline_s = deadline_s
+    done = (C.c_double * B)()
+    o.done_s = C.cast(done, C.c_void_p)
     if pairs:
         cap = B * BATCH_MAX_PAIRS
         parr = (Pair * cap)()
@@ -264,7 +268,11 @@ def run_batch(codes, tile_min: int = 0, tile_max: int = 0, blocks_per_cu: int = 
             r["pairs"] = [parr[t].to_dict() for t in range(idx[i], idx[i + 1])]
         results.append(r)
     info = {"seconds_kernel": o.seconds_kernel, "seconds_total": o.seconds_total,
-            "seconds_prep": o.seconds_prep, "executed_total": o.executed_total}
+            "seconds_prep": o.seconds_prep, "executed_total": o.executed_total,
+            "wave_s_table": o.wave_s_table, "wave_s_pair": o.wave_s_pair,
+            "wave_s_flush": o.wave_s_flush, "waves": o.waves,
+            "chunks_table": o.chunks_table, "chunks_pair": o.chunks_pair,
+            "done_s": list(done)}
     return results, info
 
 

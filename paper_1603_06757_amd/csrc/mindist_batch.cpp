@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <thread>
 
@@ -23,6 +24,34 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t job_bytes(int k) {
     const size_t b = sizeof(BatchJob) + sizeof(GroupEntry) * (size_t)(k + 2);
     return (b + 127) / 128 * 128;
+}
+
+// Largest level w Algorithm 1 is expected to reach on a random [n,k] code:
+// the pair sequence's lower bound against the Gilbert-Varshamov distance
+// (smallest d with sum_{i<=d} C(n,i) >= 2^(n-k)) plus a margin of two.
+// It only sizes the saved tables: pairs beyond it still run, with the
+// tables that exist.
+static int expected_top_level(const HostCode &hc) {
+    const int n = hc.n, k = hc.k;
+    auto log2c = [](int a, int b) {
+        return (std::lgamma(a + 1.0) - std::lgamma(b + 1.0) - std::lgamma(a - b + 1.0)) / std::log(2.0);
+    };
+    double acc = -1e300;          // log2 of the partial sum
+    int d = n - k + 1;
+    for (int i = 0; i <= n; ++i) {
+        const double t = log2c(n, i);
+        acc = acc > t ? acc + std::log2(1.0 + std::exp2(t - acc)) : t + std::log2(1.0 + std::exp2(acc - t));
+        if (acc >= n - k) { d = i; break; }
+    }
+    d = std::min(d + 2, n - k + 1);
+    int top = 1, L = 1;
+    for (int w = 1; w <= k; ++w)
+        for (int j = 0; j < hc.n_gamma; ++j) {
+            if (L >= d) return top;
+            top = w;
+            L = bound_after(k, hc.P.m_full, hc.P.k_m, hc.n_gamma, j, w);
+        }
+    return top;
 }
 
 int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &hc) {
@@ -53,9 +82,19 @@ int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &
         }
         hc.bcap[j] = bc;
     }
+    // the balanced split of the expected top level needs b = top/2
+    const int want = std::max(1, expected_top_level(hc) / 2);
+    for (int &b : hc.bcap) b = std::min(b, want);
+    size_tables(hc);
+    return MINDIST_OK;
+}
+
+void size_tables(HostCode &hc) {
     // device footprint in three regions: rows (uploaded), right tables (built
     // on the device), witness slots (read back); 256-byte pieces so no cache
     // line is shared between two codes' tables
+    const Binom &B = BN();
+    const int k = hc.k;
     hc.rows_bytes = hc.tab_bytes = 0;
     for (int j = 0; j < hc.n_gamma; ++j) {
         hc.rows_bytes += align256((size_t)k * hc.dp[j] * 4);
@@ -65,8 +104,27 @@ int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &
             hc.tab_bytes += align256(ent * hc.dp[j] * 4) + align256(ent * 4);
         }
     }
-    hc.slot_bytes = align256(sizeof(Slot) * (size_t)(n + 1));
-    return MINDIST_OK;
+    hc.slot_bytes = align256(sizeof(Slot) * (size_t)(hc.n + 1));
+}
+
+void fit_tables(std::vector<HostCode *> &codes, uint64_t budget) {
+    uint64_t sum = 0;
+    for (HostCode *h : codes) sum += h->tab_bytes;
+    while (sum > budget) {
+        // the code with the largest tables gives up one level on every set
+        HostCode *big = nullptr;
+        for (HostCode *h : codes) {
+            bool can = false;
+            for (int b : h->bcap) can = can || b > 1;
+            if (can && (!big || h->tab_bytes > big->tab_bytes)) big = h;
+        }
+        if (!big) return;
+        const uint64_t before = big->tab_bytes;
+        for (int &b : big->bcap)
+            if (b > 1) --b;
+        size_tables(*big);
+        sum -= before - big->tab_bytes;
+    }
 }
 
 void fill_slot(const HostCode &hc, const SlotPlace &pl, unsigned char *rows_stage,
@@ -230,7 +288,7 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
     const uint32_t tile_min = o.tile_min > 0 ? (uint32_t)o.tile_min : 256u;
     const uint32_t tile_max = o.tile_max > 0 ? (uint32_t)o.tile_max : 2048u;
     const int bpc = o.blocks_per_cu > 0 ? o.blocks_per_cu : 4;
-    const uint64_t table_cap = (uint64_t)(o.table_kib > 0 ? o.table_kib : 8192) << 10;
+    const uint64_t table_cap = (uint64_t)(o.table_kib > 0 ? o.table_kib : 65536) << 10;
     const int jobs_per_code = o.jobs_per_code > 0 ? o.jobs_per_code : 96;
     const bool use_graph = o.use_graph != 0 || opts == nullptr;
 
@@ -254,6 +312,15 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
         }
     if (live.empty()) return fail(MINDIST_E_ARG, "no valid code in the batch");
     const int L = (int)live.size();
+    {
+        // all saved tables of the batch within half of the free device memory
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+            std::vector<HostCode *> ptrs;
+            for (int i : live) ptrs.push_back(&hc[i]);
+            fit_tables(ptrs, free_b / 2);
+        }
+    }
 
     // device layout: three regions, each code's pieces at running offsets
     size_t rows_total = 0, tab_total = 0, slot_total = 0;
@@ -314,6 +381,22 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
     }
     if (timed_out) return fail(MINDIST_E_TIMEOUT, "batch deadline reached before every code finished");
     o.seconds_kernel = eng.kernel_seconds;
+    o.wave_s_table = (double)eng.h_g->ticks_table / eng.wall_hz;
+    o.wave_s_pair = (double)eng.h_g->ticks_pair / eng.wall_hz;
+    o.wave_s_flush = (double)eng.h_g->ticks_flush / eng.wall_hz;
+    o.waves = eng.waves;
+    o.chunks_table = eng.h_g->chunks_table;
+    o.chunks_pair = eng.h_g->chunks_pair;
+    if (o.done_s) {
+        uint64_t t0 = ~0ull;
+        for (int s = 0; s < L; ++s)
+            if (eng.h_codes[s].t_open) t0 = std::min<uint64_t>(t0, eng.h_codes[s].t_open);
+        for (int i = 0; i < B; ++i) o.done_s[i] = -1.0;
+        for (int s = 0; s < L; ++s) {
+            const BatchCode &bc = eng.h_codes[s];
+            if (bc.t_done && t0 != ~0ull) o.done_s[live[s]] = (double)(bc.t_done - t0) / eng.wall_hz;
+        }
+    }
     o.seconds_prep = std::chrono::duration<double>(t_prep - t0).count();
     o.executed_total = executed;
     o.seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -382,16 +465,21 @@ int Engine::run(int blocks_per_cu, uint32_t tile_min, uint32_t tile_max, bool gr
     a.serving = 0;
     a.tile_min = tile_min;
     a.tile_max = tile_max;
-    if (deadline_s > 0) {
+    {
         int khz = 0;
         int dev = 0;
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
             khz = 100000;
-        a.deadline_ticks = (uint64_t)(deadline_s * khz * 1000.0);
+        wall_hz = khz * 1000.0;
+        if (deadline_s > 0) a.deadline_ticks = (uint64_t)(deadline_s * wall_hz);
     }
     if (!a.binom) return fail(MINDIST_E_NOMEM, "binomial table upload failed");
-    const int blocks = cus * blocks_per_cu;
+    // a persistent grid larger than what is resident would only start its
+    // last blocks once the first ones leave
+    const int resident = persistent_resident_blocks_per_cu();
+    const int blocks = cus * (resident > 0 && blocks_per_cu > resident ? resident : blocks_per_cu);
+    waves = blocks * 4;
     auto enqueue = [&]() -> int {
         if (hipMemcpyAsync(d_codes, h_codes, sizeof(BatchCode) * (size_t)slots, hipMemcpyHostToDevice, stream) != hipSuccess ||
             hipMemcpyAsync(d_g, h_g, sizeof(BatchGlobal), hipMemcpyHostToDevice, stream) != hipSuccess ||

@@ -20,7 +20,7 @@
 namespace md {
 
 constexpr int kBatchMaxSets = 32;     // information sets per code
-constexpr int kBatchMaxB = 4;         // right tables b = 0..4 per set
+constexpr int kBatchMaxB = 6;         // right tables b = 0..6 per set
 constexpr int kBatchMaxPairs = 256;   // jobs per code (table job + pairs)
 constexpr int kBatchMaxD = 8;         // 32-bit words carried per row (n <= 256)
 constexpr int kBatchItems = 2;        // left subsets per lane
@@ -48,7 +48,15 @@ struct BatchSet {
     int32_t D, dp, stripped, bcap;
 };
 
-// one job of a code; GroupEntry groups[ngroups] follow the struct
+constexpr int kJobCounters = 8;       // chunk dispensers per job (one cache line each)
+
+// one job of a code; GroupEntry groups[ngroups] follow the struct.
+// Chunks are handed out by nctr counters: counter r hands out chunks
+// r, r + nctr, r + 2*nctr, ...; a wave starts at its home counter and moves
+// on when that one is drained, so claims spread over nctr cache lines.
+// Waves count their completed chunks (and fold their pair minimum and
+// evaluated combinations) privately and add them to `done` once, when they
+// find the job drained.
 struct alignas(128) BatchJob {
     int32_t kind;                 // 0 = table job, 1 = enumeration pair
     int32_t j, w, a, b;
@@ -58,21 +66,27 @@ struct alignas(128) BatchJob {
     uint32_t pair_min, exit_flag, L_after, U_after;
     uint64_t executed;
     uint64_t expected;            // chunks that complete before the job closes
-    uint64_t pad_b[5];
-    alignas(128) uint64_t claim;  // chunk dispenser
-    uint64_t pad_c[15];
+    uint32_t nctr, pad_a;         // counters in use (1..kJobCounters)
+    uint64_t pad_b[4];
     alignas(128) uint64_t done;   // completed chunks
     uint64_t pad_d[15];
+    struct alignas(128) Counter {
+        uint64_t v;
+        uint64_t pad[15];
+    } claim[kJobCounters];
 };
 
 struct BatchCode {
     int32_t n, k, m_full, k_m, n_gamma, W;
     int32_t status;               // kSlot* or a negative error
     int32_t njobs;                // jobs opened (the open one is njobs-1)
+    int32_t drained;              // njobs value whose open job was found fully
+                                  // claimed (a hint for waves looking for work)
     uint32_t U_found;             // least weight found (kInf = none)
     uint32_t tile_cap;            // largest right tile for this code
     uint32_t L_final, U_final;
     uint64_t seq;                 // submission sequence number (server)
+    uint64_t t_open, t_done;      // device wall clock: table job opened, code finished
     uint32_t job[kBatchMaxPairs]; // arena offsets (128-byte units) of the jobs
     Slot *slots;                  // n+1 witness slots
     uint64_t tab_off[kBatchTabs + 1];   // table entries before table t (t = j*(B+1)+b)
@@ -84,7 +98,12 @@ struct BatchGlobal {
     uint32_t pad0;
     uint64_t arena_next;          // 128-byte units handed out
     uint64_t arena_cap;
-    uint64_t pad1[13];
+    // profile (summed over waves at exit): wall-clock ticks spent in table
+    // chunks, in enumeration chunks, in flushes (with the job control they
+    // run); chunks of each kind
+    uint64_t ticks_table, ticks_pair, ticks_flush;
+    uint64_t chunks_table, chunks_pair;
+    uint64_t pad1[8];
 };
 
 struct BatchArgs {
@@ -102,5 +121,8 @@ struct BatchArgs {
 };
 
 int launch_persistent(const BatchArgs &a, int blocks, void *stream);
+// blocks of 256 threads of the persistent kernel that fit on one CU at once
+// (0 if the runtime cannot tell)
+int persistent_resident_blocks_per_cu();
 
 }  // namespace md

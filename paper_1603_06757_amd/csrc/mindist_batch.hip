@@ -1,7 +1,9 @@
 // mindist_batch.hip -- the persistent multi-code kernel (see mindist_batch.h).
 //
 // Waves walk the code slots, claim one chunk at a time from a code's open
-// job and stay on that code while it has chunks.  Jobs:
+// job (spread over the job's counters) and stay on that code while it has
+// chunks; a wave adds its completed chunks to the job once, when it finds
+// the job drained.  Jobs:
 //   * table job: the code's saved right sums (Section 3.4), 4096 entries per
 //     chunk;
 //   * pair (Gamma_j, w): the same left/right enumeration as the single-code
@@ -46,6 +48,12 @@ __device__ __forceinline__ uint64_t wave_fetch_add(uint64_t *p, uint64_t v) {
     return uni64((uint64_t)__shfl((long long)r, 0));
 }
 
+// counters for a job of `total` chunks: one per 64 chunks, at most kJobCounters
+__device__ __forceinline__ uint32_t job_counters(uint64_t total) {
+    const uint64_t c = total / 64;
+    return c < 1 ? 1u : (c > (uint64_t)kJobCounters ? (uint32_t)kJobCounters : (uint32_t)c);
+}
+
 __device__ __forceinline__ GroupEntry *job_groups(BatchJob *jb) {
     return reinterpret_cast<GroupEntry *>(jb + 1);
 }
@@ -81,6 +89,7 @@ __device__ void finish_code(const BatchArgs &A, int c, int32_t status, uint32_t 
     if (lane == 0) {
         cs->L_final = L;
         cs->U_final = U;
+        cs->t_done = wall_clock64();
     }
     __threadfence();
     if (lane == 0) {
@@ -199,7 +208,8 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
         jb->U_after = 0;
         jb->executed = 0;
         jb->expected = chunk_base;
-        jb->claim = 0;
+        jb->nctr = job_counters(chunk_base);
+        for (int r = 0; r < kJobCounters; ++r) jb->claim[r].v = 0;
         jb->done = 0;
         cs->job[p] = off;
     }
@@ -218,11 +228,13 @@ __device__ void open_tables(const BatchArgs &A, int c) {
     BatchJob *jb = job_at(A, off);
     if ((threadIdx.x & 63) == 0) {
         const uint64_t E = cs->tab_off[kBatchTabs];
+        cs->t_open = wall_clock64();
         jb->kind = 0;
         jb->j = -1;
         jb->total_chunks = (E + kTableChunk - 1) / kTableChunk;
         jb->expected = jb->total_chunks;
-        jb->claim = 0;
+        jb->nctr = job_counters(jb->total_chunks);
+        for (int r = 0; r < kJobCounters; ++r) jb->claim[r].v = 0;
         jb->done = 0;
         jb->executed = 0;
         jb->pair_min = kInf;
@@ -235,9 +247,81 @@ __device__ void open_tables(const BatchArgs &A, int c) {
     }
 }
 
-// Chunk ch of the table job: entries [ch*4096, ...) of the flattened list;
-// lane l fills 64 consecutive entries, the first by unranking, the rest by
-// the colex successor (one or two row additions each).
+// n consecutive entries of one saved table of level BL, from entry i on:
+// the first by unranking, the rest by the colex successor (one or two row
+// additions each).  Entry e is the sum of rows {kk-1-z : z in
+// colex_unrank_BL(e)}; an outer table (cnt != nullptr, rows [0, kk) with
+// kk = k - shift) also stores C(shift + min z, shift), the inner count.
+// BL is a template parameter so that the subset stays in registers; the run
+// is not inlined so that it does not set the persistent kernel's register
+// budget.
+template <int BL>
+__device__ __noinline__ void table_run(const uint64_t *bt, const uint32_t *rows, int dp, int D,
+                                          int kk, int shift, uint32_t *out, uint32_t *cnt,
+                                          uint64_t i, uint64_t n) {
+    int z[BL + 1];
+    uint32_t acc[kBatchMaxD];
+#pragma unroll
+    for (int d = 0; d < kBatchMaxD; ++d) acc[d] = 0;
+    auto add_row = [&](int zz) {
+        const uint32_t *row = rows + (size_t)(kk - 1 - zz) * dp;
+#pragma unroll
+        for (int d = 0; d < kBatchMaxD; ++d)
+            if (d < D) acc[d] ^= row[d];
+    };
+    {
+        uint64_t r = i;
+        int top = kk;
+#pragma unroll
+        for (int t = BL; t >= 1; --t) {
+            int l = t - 1, h = top - 1;
+            while (l < h) {
+                const int mid = (l + h + 1) >> 1;
+                if (binom(bt, mid, t) <= r) l = mid; else h = mid - 1;
+            }
+            r -= binom(bt, l, t);
+            top = l;
+            z[t - 1] = l;
+            add_row(l);
+        }
+    }
+    z[BL] = kk;                       // sentinel
+    for (uint64_t e = 0; e < n; ++e, ++i) {
+        uint32_t *o = out + (size_t)i * dp;
+        if (dp == 8) {
+            *reinterpret_cast<uint4 *>(o) = make_uint4(acc[0], acc[1], acc[2], acc[3]);
+            *reinterpret_cast<uint4 *>(o + 4) = make_uint4(acc[4], acc[5], acc[6], acc[7]);
+        } else if (dp == 4) {
+            *reinterpret_cast<uint4 *>(o) = make_uint4(acc[0], acc[1], acc[2], acc[3]);
+        } else if (dp == 2) {
+            *reinterpret_cast<uint2 *>(o) = make_uint2(acc[0], acc[1]);
+        } else {
+            o[0] = acc[0];
+        }
+        if (BL == 0) continue;
+        if (cnt) cnt[i] = (uint32_t)binom(bt, shift + z[0], shift);
+        if (e + 1 == n) break;
+        // colex successor: the lowest position that can move up by one
+        int t0 = BL - 1;
+#pragma unroll
+        for (int t = BL - 2; t >= 0; --t)
+            if (z[t] + 1 != z[t + 1]) t0 = t;
+#pragma unroll
+        for (int t = 0; t < BL; ++t)
+            if (t <= t0) add_row(z[t]);
+#pragma unroll
+        for (int t = 0; t < BL; ++t) {
+            if (t == t0) z[t] += 1;
+            else if (t < t0) z[t] = t;
+        }
+#pragma unroll
+        for (int t = 0; t < BL; ++t)
+            if (t <= t0) add_row(z[t]);
+    }
+}
+
+// Chunk ch of the table job: entries [ch*4096, ...) of the flattened list
+// of the code's tables; lane l fills 64 consecutive entries.
 __device__ void table_chunk(const BatchArgs &A, BatchCode *cs, uint64_t ch) {
     const int lane = threadIdx.x & 63;
     const uint64_t E = cs->tab_off[kBatchTabs];
@@ -255,51 +339,23 @@ __device__ void table_chunk(const BatchArgs &A, BatchCode *cs, uint64_t ch) {
         const bool outer = r0 > kBatchMaxB;
         const int b = outer ? r0 - (kBatchMaxB + 1) : r0;
         const int shift = outer ? set.bcap : 0;   // outer: rows [0, k-bcap)
-        const int kk = k - shift;
         const uint64_t size = cs->tab_off[lo + 1] - cs->tab_off[lo];
-        uint64_t i = idx - cs->tab_off[lo];
-        // z = colex_unrank_b(i), ascending; entry = rows {kk-1-z}
-        int z[kBatchMaxB + 1];
-        uint32_t acc[kBatchMaxD];
-        for (int d = 0; d < kBatchMaxD; ++d) acc[d] = 0;
-        {
-            uint64_t r = i;
-            int top = kk;
-            for (int t = b; t >= 1; --t) {
-                int l = t - 1, h = top - 1;
-                while (l < h) {
-                    const int mid = (l + h + 1) >> 1;
-                    if (binom(A.binom, mid, t) <= r) l = mid; else h = mid - 1;
-                }
-                r -= binom(A.binom, l, t);
-                top = l;
-                z[t - 1] = l;
-                const uint32_t *row = set.rows + (size_t)(kk - 1 - l) * set.dp;
-                for (int d = 0; d < set.D; ++d) acc[d] ^= row[d];
-            }
-        }
-        z[b] = kk;                        // sentinel
+        const uint64_t i = idx - cs->tab_off[lo];
+        const uint64_t n = min(left, size - i);
         uint32_t *out = outer ? set.otab[b] : set.rtab[b];
         uint32_t *cnt = outer ? set.ocnt[b] : nullptr;
-        for (; left > 0 && i < size; --left, ++i, ++idx) {
-            uint32_t *o = out + (size_t)i * set.dp;
-            for (int d = 0; d < set.dp; ++d) o[d] = d < set.D ? acc[d] : 0u;
-            if (cnt) cnt[i] = (uint32_t)binom(A.binom, shift + z[0], shift);
-            if (i + 1 == size || b == 0) continue;
-            // colex successor: the lowest position that can move up by one
-            int t0 = 0;
-            while (z[t0] + 1 == z[t0 + 1]) ++t0;
-            for (int t = 0; t <= t0; ++t) {
-                const uint32_t *row = set.rows + (size_t)(kk - 1 - z[t]) * set.dp;
-                for (int d = 0; d < set.D; ++d) acc[d] ^= row[d];
-            }
-            z[t0] += 1;
-            for (int t = 0; t < t0; ++t) z[t] = t;
-            for (int t = 0; t <= t0; ++t) {
-                const uint32_t *row = set.rows + (size_t)(kk - 1 - z[t]) * set.dp;
-                for (int d = 0; d < set.D; ++d) acc[d] ^= row[d];
-            }
+        const int kk = k - shift;
+        switch (b) {
+            case 0: table_run<0>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            case 1: table_run<1>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            case 2: table_run<2>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            case 3: table_run<3>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            case 4: table_run<4>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            case 5: table_run<5>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            default: table_run<6>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
         }
+        left -= n;
+        idx += n;
     }
 }
 
@@ -308,6 +364,8 @@ struct JobView {
     int c, p, kind;
     BatchJob *jb;
     uint64_t total;
+    uint32_t nctr;                // chunk counters of the job
+    uint32_t off;                 // the job's arena offset
     // pair jobs
     int j, a, b, b2, k, D, ngroups, gi;
     uint32_t T, offset, L_before;
@@ -316,13 +374,15 @@ struct JobView {
     const GroupEntry *gr;
 };
 
-__device__ void load_view(const BatchArgs &A, int c, int p, BatchJob *jb, JobView &v) {
+__device__ __forceinline__ void load_view(const BatchArgs &A, int c, int p, BatchJob *jb, JobView &v) {
     BatchCode *cs = &A.codes[c];
     v.c = c;
     v.p = p;
     v.jb = jb;
     v.kind = (int)uni32((uint32_t)jb->kind);
     v.total = uni64(jb->total_chunks);
+    v.nctr = uni32(jb->nctr);
+    v.offset = 0;
     if (v.kind == 0) return;
     v.j = (int)uni32((uint32_t)jb->j);
     v.a = (int)uni32((uint32_t)jb->a);
@@ -350,12 +410,17 @@ __device__ void load_view(const BatchArgs &A, int c, int p, BatchJob *jb, JobVie
 }
 
 // One chunk of pair job v.p of code v.c.
+// Adds the chunk's evaluated combinations to `exec` and lowers `wmin_out`
+// to its least weight (without the offset).
 template <int D>
-__device__ void pair_chunk(const BatchArgs &A, JobView &v, uint64_t ch) {
+__device__ __forceinline__ void pair_chunk(const BatchArgs &A, JobView &v, uint64_t ch, uint64_t &exec,
+                           uint32_t &wmin_out) {
     BatchCode *cs = &A.codes[v.c];
     BatchJob *jb = v.jb;
     const int lane = threadIdx.x & 63;
-    // group of chunk ch: a wave's claims on one job only grow
+    // group of chunk ch: claims from one counter only grow; a move to
+    // another counter may go back
+    if (ch < uni64(v.gr[v.gi].chunk_base)) v.gi = 0;
     while (v.gi + 1 < v.ngroups && uni64(v.gr[v.gi + 1].chunk_base) <= ch) ++v.gi;
     const GroupEntry *ge = v.gr + v.gi;
     const uint64_t base = uni64(ge->chunk_base), n_rt = uni64(ge->n_rt);
@@ -372,12 +437,9 @@ __device__ void pair_chunk(const BatchArgs &A, JobView &v, uint64_t ch) {
     uint64_t cnt;
     if (v.b2) run_chunk3<D, kBatchItems, false>(src, g, L, nr, lmin, cnt, ws);
     else run_chunk<D, kBatchItems, false>(src, g, L, nr, lmin, cnt, ws);
-    const uint32_t wmin = wave_min_u32(lmin);
-    const uint64_t wcnt = wave_sum_u64(cnt);
-    if (lane == 0) {
-        atomicAdd((unsigned long long *)&jb->executed, (unsigned long long)wcnt);
-        if (wmin != kInf) atomicMin(&jb->pair_min, wmin + v.offset);
-    }
+    const uint32_t wmin = uni32(wave_min_u32(lmin));
+    exec += uni64(wave_sum_u64(cnt));
+    if (wmin < wmin_out) wmin_out = wmin;
     if (wmin == kInf) return;
     const uint32_t val = wmin + v.offset;
     if (val >= uni32(ld_rlx(&cs->U_found))) return;
@@ -401,9 +463,15 @@ __device__ void pair_chunk(const BatchArgs &A, JobView &v, uint64_t ch) {
         // U reached the bound before this pair: stop handing out its chunks;
         // the pair closes once the chunks already claimed are done
         if (atomicExch(&jb->exit_flag, 1u) == 0u) {
-            const uint64_t claimed = atomicExch((unsigned long long *)&jb->claim, 1ull << 62);
-            const uint64_t total = jb->total_chunks;
-            st_rel(&jb->expected, claimed < total ? claimed : total);
+            // chunks handed out so far: counter r hands out at most
+            // ceil((total - r) / nctr) of them
+            uint64_t claimed = 0;
+            for (uint32_t r = 0; r < v.nctr; ++r) {
+                const uint64_t t = atomicExch((unsigned long long *)&jb->claim[r].v, 1ull << 62);
+                const uint64_t avail = v.total > r ? (v.total - r + v.nctr - 1) / v.nctr : 0;
+                claimed += t < avail ? t : avail;
+            }
+            st_rel(&jb->expected, claimed);
         }
     }
 }
@@ -440,19 +508,53 @@ __device__ void advance(const BatchArgs &A, int c, int p, BatchJob *jb) {
     open_pair(A, c, p + 1, j2, w2, L);
 }
 
-__device__ void complete_chunk(const BatchArgs &A, int c, int p, BatchJob *jb) {
-    // release: this chunk's atomics are performed before it counts as done
+// Next chunk of job jb (total chunks, nctr counters) for this wave, or ~0
+// once every counter is drained.  ctr: the counter tried next; dmask: the
+// counters found drained.
+__device__ __forceinline__ uint64_t claim_chunk(BatchJob *jb, uint64_t total, uint32_t nctr, uint32_t &ctr,
+                                uint32_t &dmask) {
+    const uint32_t all = (1u << nctr) - 1u;
+    while (dmask != all) {
+        const uint32_t r = ctr;
+        const uint64_t t = wave_fetch_add(&jb->claim[r].v, 1ull);
+        if (t < total) {
+            const uint64_t ch = (uint64_t)r + t * nctr;
+            if (ch < total) return ch;
+        }
+        dmask |= 1u << r;
+        for (uint32_t q = 1; q <= nctr; ++q) {
+            const uint32_t r2 = (r + q) % nctr;
+            if (!(dmask & (1u << r2))) { ctr = r2; break; }
+        }
+    }
+    return ~0ull;
+}
+
+// Add a wave's `done` completed chunks of job p of code c (with their
+// `exec` evaluated combinations and least weight `wmin` + offset) to the
+// job; the flush that brings the job's count to `expected` closes the job
+// and applies Algorithm 1's control.
+__device__ __noinline__ void flush(const BatchArgs &A, int c, int p, BatchJob *jb, uint64_t done, uint64_t exec,
+                      uint32_t wmin, uint32_t offset) {
+    if (done == 0) return;
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) {
+        if (exec) atomicAdd((unsigned long long *)&jb->executed, (unsigned long long)exec);
+        if (wmin != kInf) atomicMin(&jb->pair_min, wmin + offset);
+    }
+    // release: the chunks' results are performed before they count as done
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     uint64_t prev = 0, expected = 0;
-    if ((threadIdx.x & 63) == 0) {
-        prev = atomicAdd((unsigned long long *)&jb->done, 1ull);
-        // read-modify-write read: the coherent value, including an exit's
-        // lowered count stored before the exiting chunk counted as done
+    if (lane == 0) {
+        prev = atomicAdd((unsigned long long *)&jb->done, (unsigned long long)done);
+        // acquire through `done`: an exit's lowered count, stored before the
+        // exiting wave's own flush, is visible to every later flush
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         expected = atomicAdd((unsigned long long *)&jb->expected, 0ull);
     }
     prev = uni64((uint64_t)__shfl((long long)prev, 0));
     expected = uni64((uint64_t)__shfl((long long)expected, 0));
-    if (prev + 1 == expected) {
+    if (prev + done == expected) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         advance(A, c, p, jb);
     }
@@ -467,46 +569,85 @@ __global__ __launch_bounds__(256) void persistent_batch_kernel(BatchArgs A) {
     int cur = (int)(wave % (uint32_t)nc);
     const uint64_t t_start = wall_clock64();
     JobView v;
-    bool have = false;             // v describes an open job worth claiming on
+    bool have = false;             // v describes a job this wave claims on
+    // arena offset of the last job this wave found drained (an integer: a
+    // loop-carried pointer here costs the enumeration its scalar loads)
+    uint32_t drained = 0xFFFFFFFFu;
+    // claiming state and this wave's completed chunks of v's job not yet
+    // added to it
+    uint32_t ctr = 0, dmask = 0, pmin = kInf;
+    uint64_t pdone = 0, pexec = 0;
+    // profile: ticks in table chunks, enumeration chunks and flushes
+    uint64_t tk_table = 0, tk_pair = 0, tk_flush = 0, n_table = 0, n_pair = 0;
     for (;;) {
-        if (A.deadline_ticks && wall_clock64() - t_start > A.deadline_ticks) break;
+        bool stop = A.deadline_ticks && wall_clock64() - t_start > A.deadline_ticks;
         if (A.serving) {
-            const uint32_t stop = A.host_stop ? __hip_atomic_load(A.host_stop, __ATOMIC_RELAXED,
-                                                                  __HIP_MEMORY_SCOPE_SYSTEM)
-                                              : 1u;
-            if (uni32(stop)) break;
+            const uint32_t hs = A.host_stop ? __hip_atomic_load(A.host_stop, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_SYSTEM)
+                                            : 1u;
+            stop = stop || uni32(hs) != 0;
         } else if (uni32(ld_rlx(&A.g->codes_done)) >= (uint32_t)nc) {
+            stop = true;
+        }
+        if (stop) {
+            // every chunk this wave claimed is complete: count it before leaving
+            if (have) flush(A, v.c, v.p, v.jb, pdone, pexec, pmin, v.offset);
+            if (lane == 0) {
+                atomicAdd((unsigned long long *)&A.g->ticks_table, (unsigned long long)tk_table);
+                atomicAdd((unsigned long long *)&A.g->ticks_pair, (unsigned long long)tk_pair);
+                atomicAdd((unsigned long long *)&A.g->ticks_flush, (unsigned long long)tk_flush);
+                atomicAdd((unsigned long long *)&A.g->chunks_table, (unsigned long long)n_table);
+                atomicAdd((unsigned long long *)&A.g->chunks_pair, (unsigned long long)n_pair);
+            }
             break;
         }
         if (have) {
-            const uint64_t ch = wave_fetch_add(&v.jb->claim, 1ull);
-            if (ch < v.total) {
+            const uint64_t ch = claim_chunk(v.jb, v.total, v.nctr, ctr, dmask);
+            if (ch != ~0ull) {
+                const uint64_t t0 = wall_clock64();
                 if (v.kind == 0) {
                     table_chunk(A, &A.codes[v.c], ch);
+                    tk_table += wall_clock64() - t0;
+                    n_table += 1;
                 } else {
                     switch (v.D) {
-                        case 1: pair_chunk<1>(A, v, ch); break;
-                        case 2: pair_chunk<2>(A, v, ch); break;
-                        case 3: pair_chunk<3>(A, v, ch); break;
-                        case 4: pair_chunk<4>(A, v, ch); break;
-                        case 5: pair_chunk<5>(A, v, ch); break;
-                        case 6: pair_chunk<6>(A, v, ch); break;
-                        case 7: pair_chunk<7>(A, v, ch); break;
-                        default: pair_chunk<8>(A, v, ch); break;
+                        case 1: pair_chunk<1>(A, v, ch, pexec, pmin); break;
+                        case 2: pair_chunk<2>(A, v, ch, pexec, pmin); break;
+                        case 3: pair_chunk<3>(A, v, ch, pexec, pmin); break;
+                        case 4: pair_chunk<4>(A, v, ch, pexec, pmin); break;
+                        case 5: pair_chunk<5>(A, v, ch, pexec, pmin); break;
+                        case 6: pair_chunk<6>(A, v, ch, pexec, pmin); break;
+                        case 7: pair_chunk<7>(A, v, ch, pexec, pmin); break;
+                        default: pair_chunk<8>(A, v, ch, pexec, pmin); break;
                     }
+                    tk_pair += wall_clock64() - t0;
+                    n_pair += 1;
                 }
-                complete_chunk(A, v.c, v.p, v.jb);
+                pdone += 1;
                 continue;
             }
-            // this job is fully claimed: its code may open the next pair soon
+            // this job is drained for this wave: tell the others, count its
+            // chunks; its code may open the next pair soon
+            if (lane == 0) atomicMax(&A.codes[v.c].drained, v.p + 1);
+            const uint64_t t0 = wall_clock64();
+            flush(A, v.c, v.p, v.jb, pdone, pexec, pmin, v.offset);
+            tk_flush += wall_clock64() - t0;
+            drained = v.off;
             have = false;
             cur = v.c;
         }
-        // find a code with an open job: 64 slots per look, relaxed reads
+        // find a code with work: 64 slots per look, relaxed reads of the
+        // status, the jobs opened and the drained hint (a code whose open
+        // job is fully claimed is passed over without touching the job)
         const int probe = (cur + lane) % nc;
         const int32_t s = (int32_t)__hip_atomic_load(&A.codes[probe].status, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long live = __ballot(s == kSlotActive || s == kSlotPending);
+        const int32_t pj = __hip_atomic_load(&A.codes[probe].njobs, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t pd = __hip_atomic_load(&A.codes[probe].drained, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long live =
+            __ballot(s == kSlotPending || (s == kSlotActive && pj > 0 && pd < pj));
         if (!live) {
             cur = (cur + 64) % nc;
             __builtin_amdgcn_s_sleep(4);
@@ -527,21 +668,40 @@ __global__ __launch_bounds__(256) void persistent_batch_kernel(BatchArgs A) {
         const int nj = (int)uni32((uint32_t)__hip_atomic_load(&cs->njobs, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT));
         if (nj <= 0) { cur = (c + 1) % nc; continue; }
-        // acquire once per job: everything written before the job was
-        // published (record, groups, tables) is visible from here on
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int p = nj - 1;
-        BatchJob *jb = job_at(A, uni32(cs->job[p]));
-        if (have && v.jb == jb) { cur = (c + 1) % nc; __builtin_amdgcn_s_sleep(2); continue; }
-        load_view(A, c, p, jb, v);
-        if (uni64(jb->claim) >= v.total) {     // nothing left to claim here
+        // a relaxed look first (no fence while waiting on a drained job)
+        const uint32_t off0 = uni32(__hip_atomic_load(&cs->job[p], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT));
+        if (off0 == drained) {     // still waiting for its last chunks
             cur = (c + 1) % nc;
             __builtin_amdgcn_s_sleep(2);
             continue;
         }
+        // acquire once per job: everything written before the job was
+        // published (record, groups, tables) is visible from here on
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const uint32_t off = uni32(cs->job[p]);
+        if (off == drained) {
+            cur = (c + 1) % nc;
+            continue;
+        }
+        BatchJob *jb = job_at(A, off);
+        load_view(A, c, p, jb, v);
+        v.off = off;
+        ctr = wave % v.nctr;
+        dmask = 0;
+        pdone = pexec = 0;
+        pmin = kInf;
         have = true;
         cur = c;
     }
+}
+
+int persistent_resident_blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, persistent_batch_kernel, 256, 0) != hipSuccess)
+        return 0;
+    return n;
 }
 
 int launch_persistent(const BatchArgs &a, int blocks, void *stream) {

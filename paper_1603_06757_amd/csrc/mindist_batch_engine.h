@@ -30,6 +30,11 @@ struct SlotPlace {
 };
 
 int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &hc);
+// device bytes of a prepared code from its per-set table levels (bcap)
+void size_tables(HostCode &hc);
+// lower the table levels of the codes with the largest tables until all
+// tables together fit in `budget` bytes (or every set is down to one level)
+void fit_tables(std::vector<HostCode *> &codes, uint64_t budget);
 void fill_slot(const HostCode &hc, const SlotPlace &pl, unsigned char *rows_stage,
                uint32_t tile_cap, uint64_t seq, BatchCode &bc);
 int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *arena,
@@ -55,6 +60,8 @@ struct Engine {
     bool own_stream = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     double kernel_seconds = 0;
+    double wall_hz = 1e8;               // device wall-clock rate
+    int waves = 0;                      // waves of the last launch
     std::vector<unsigned char> arena_host;
 
     int init(int slots, size_t rows_bytes, size_t tab_bytes, size_t slot_bytes,

@@ -274,6 +274,7 @@ __device__ __forceinline__ int find_witness(const ItemSrc &s, const ChunkGeo &g,
     hit_i = kInf;
     int hit_t = -1;
     cu32 *ct = (cu32 *)s.table;
+#pragma unroll 1
     for (uint32_t i = g.i_begin; i < g.i_end && hit_t < 0; ++i) {
         uint32_t e[D];
         load_entry<D>(ct, i, e);
@@ -448,10 +449,14 @@ __device__ __forceinline__ int find_witness3(const ItemSrc &s, const ChunkGeo &g
     int hit_t = -1;
     cu32 *ct = (cu32 *)s.table;
     cu32 *c2 = (cu32 *)s.table2;
+    // rare path (a new least weight): kept rolled so that it does not set
+    // the kernel's register budget
+#pragma unroll 1
     for (uint32_t i1 = g.i_begin; i1 < g.i_end && hit_t < 0; ++i1) {
         uint32_t s1[D];
         load_entry<D>(ct, i1, s1);
         const uint32_t n2 = s.cnt2[i1];
+#pragma unroll 1
         for (uint32_t i2 = 0; i2 < n2 && hit_t < 0; ++i2) {
             uint32_t e[D];
             load_entry<D>(c2, i2, e);

@@ -217,6 +217,75 @@ typedef struct mindist_batch_opts {
 int mindist_run_batch(const uint64_t *const *G, const int *n, const int *k, int B,
                       mindist_result *out, mindist_batch_opts *opts);
 
+/* ---- serving: continuous batching of arriving codes ---------------------
+ *
+ * A server owns one GPU stream and a set of code slots on the device.  A
+ * manager thread keeps the persistent multi-code kernel of mindist_run_batch
+ * running over the resident codes; codes submitted while it runs wait in a
+ * queue and are admitted, in submission order among those that fit, as
+ * slots and device memory free up: the launch is stopped (every wave
+ * finishes the chunk it holds, so no work is lost), the new codes' slots are
+ * written and the kernel is launched again over old and new codes together.
+ * A code's information sets, Gamma_j, saved tables, bounds and job records
+ * stay on the device from admission to completion; finished codes are read
+ * back while the others keep running.  A code's result equals
+ * mindist_run's with default options (d, visited pairs, counts, pair
+ * minima); witnesses may differ but have weight d. */
+typedef struct mindist_server mindist_server;
+
+typedef struct mindist_server_opts {
+    int32_t max_active;       /* code slots resident on the device (0 = 256) */
+    int32_t blocks_per_cu;    /* resident workgroups per CU (0 = 4) */
+    int64_t device_bytes;     /* device memory for resident codes' rows, saved tables and
+                                 witness slots, a code is admitted only when its share
+                                 fits (0 = 8 GiB) */
+    double  epoch_min_ms;     /* least running time of a launch before waiting codes are
+                                 admitted (0 = 0.5 ms) */
+    int32_t table_kib;        /* cap on one saved table in KiB (0 = 65536) */
+    int32_t jobs_per_code;    /* job records per slot (0 = 96); a code needing more ends
+                                 with MINDIST_E_LIMIT */
+} mindist_server_opts;
+
+#define MINDIST_SERVER_MAX_PAIRS 256
+
+typedef struct mindist_server_result {
+    uint64_t tag;             /* the caller's tag from submit */
+    int32_t  status;          /* MINDIST_OK or a negative MINDIST_E_* */
+    int32_t  n_pairs;         /* entries of pairs[] */
+    mindist_result result;
+    double   t_submit, t_admit, t_done;   /* seconds on the server clock */
+    mindist_pair pairs[MINDIST_SERVER_MAX_PAIRS];   /* visited pairs, in order */
+} mindist_server_result;
+
+typedef struct mindist_server_stats {
+    uint64_t submitted, admitted, completed;
+    uint64_t epochs;          /* launches of the persistent kernel */
+    double   seconds_kernel;  /* summed launch time (HIP events) */
+    int32_t  resident;        /* codes on the device now */
+    int32_t  pending;         /* codes waiting for admission now */
+} mindist_server_stats;
+
+/* Start a server on the current HIP device (opts may be NULL).  *out is
+ * released with mindist_server_destroy. */
+int mindist_server_create(const mindist_server_opts *opts, mindist_server **out);
+/* Validate and copy G (layout as in mindist_create), compute its
+ * information sets and Gamma_j on the calling thread, and queue it.
+ * Returns at once with MINDIST_OK, or the error of that preprocessing
+ * (nothing is queued then).  Thread-safe. */
+int mindist_server_submit(mindist_server *s, const uint64_t *G, int n, int k, uint64_t tag);
+/* Non-blocking: move up to cap finished results (caller-owned array) to
+ * out, oldest first; *n_out receives their number.  Thread-safe. */
+int mindist_server_poll(mindist_server *s, mindist_server_result *out, int cap, int *n_out);
+/* Block until no code is waiting or resident, or timeout_s seconds passed
+ * (MINDIST_E_TIMEOUT); results stay queued for poll. */
+int mindist_server_wait(mindist_server *s, double timeout_s);
+/* seconds since the server started (the clock of t_submit/t_admit/t_done) */
+double mindist_server_clock(const mindist_server *s);
+int mindist_server_stats_get(const mindist_server *s, mindist_server_stats *out);
+/* Stop the kernel and the manager thread; unfinished codes are dropped.
+ * NULL-safe. */
+void mindist_server_destroy(mindist_server *s);
+
 #ifdef __cplusplus
 }
 #endif

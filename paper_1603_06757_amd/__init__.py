@@ -81,14 +81,25 @@ class BatchOpts(C.Structure):
                 ("chunks_table", C.c_uint64), ("chunks_pair", C.c_uint64), ("done_s", C.c_void_p)]
 
 
+SERVER_MAX_PAIRS = 256
+
+
 class ServerOpts(C.Structure):
-    _fields_ = [("max_active", C.c_int32), ("tile_t", C.c_int32), ("device_bytes", C.c_int64)]
+    _fields_ = [("max_active", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("device_bytes", C.c_int64), ("epoch_min_ms", C.c_double),
+                ("table_kib", C.c_int32), ("jobs_per_code", C.c_int32)]
 
 
 class ServerResult(C.Structure):
-    _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("n_pairs", C.c_int32),
                 ("result", Result), ("t_submit", C.c_double), ("t_admit", C.c_double),
-                ("t_done", C.c_double)]
+                ("t_done", C.c_double), ("pairs", Pair * SERVER_MAX_PAIRS)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
+                ("epochs", C.c_uint64), ("seconds_kernel", C.c_double),
+                ("resident", C.c_int32), ("pending", C.c_int32)]
 
 
 _lib = None
@@ -122,6 +133,8 @@ def lib():
             L.mindist_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(vp)]
             L.mindist_server_submit.argtypes = [vp, u64p, C.c_int, C.c_int, C.c_uint64]
             L.mindist_server_poll.argtypes = [vp, C.POINTER(ServerResult), C.c_int, ip]
+            L.mindist_server_wait.argtypes = [vp, C.c_double]
+            L.mindist_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
             L.mindist_server_clock.argtypes = [vp]
             L.mindist_server_clock.restype = C.c_double
             L.mindist_server_destroy.argtypes = [vp]
@@ -274,6 +287,69 @@ def run_batch(codes, tile_min: int = 0, tile_max: int = 0, blocks_per_cu: int = 
             "chunks_table": o.chunks_table, "chunks_pair": o.chunks_pair,
             "done_s": list(done)}
     return results, info
+
+
+class Server:
+    """Continuous batching of arriving codes on the current GPU (the
+    mindist_server_* entry points).  submit() returns at once; poll()
+    returns finished results as dicts with the request's tag, its result,
+    its visited pairs and t_submit / t_admit / t_done on the server clock."""
+
+    def __init__(self, max_active: int = 0, blocks_per_cu: int = 0, device_bytes: int = 0,
+                 epoch_min_ms: float = 0.0, table_kib: int = 0, jobs_per_code: int = 0):
+        o = ServerOpts(max_active, blocks_per_cu, device_bytes, epoch_min_ms, table_kib, jobs_per_code)
+        h = C.c_void_p()
+        _check(lib().mindist_server_create(C.byref(o), C.byref(h)))
+        self._h = h
+        self._buf = (ServerResult * 64)()
+
+    def submit(self, G, n: int, k: int, tag: int):
+        m = _mat(G, n, k)
+        _check(lib().mindist_server_submit(self._h, _u64(m), n, k, tag))
+
+    def poll(self) -> list:
+        out = []
+        while True:
+            got = C.c_int(0)
+            _check(lib().mindist_server_poll(self._h, self._buf, len(self._buf), C.byref(got)))
+            for t in range(got.value):
+                r = self._buf[t]
+                d = {"tag": r.tag, "status": r.status, "t_submit": r.t_submit,
+                     "t_admit": r.t_admit, "t_done": r.t_done}
+                if r.status == 0:
+                    d.update(r.result.to_dict())
+                    d["pairs"] = [r.pairs[i].to_dict() for i in range(r.n_pairs)]
+                out.append(d)
+            if got.value < len(self._buf):
+                return out
+
+    def wait(self, timeout_s: float = 60.0):
+        _check(lib().mindist_server_wait(self._h, timeout_s))
+
+    def clock(self) -> float:
+        return lib().mindist_server_clock(self._h)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().mindist_server_stats_get(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().mindist_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def min_distance(G, n: int, k: int, **options) -> dict:

@@ -182,7 +182,8 @@ void fill_slot(const HostCode &hc, const SlotPlace &pl, unsigned char *rows_stag
 }
 
 int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *arena,
-                const Slot *slots, mindist_result &out, std::vector<mindist_pair> &trace) {
+                uint64_t arena_lo, const Slot *slots, mindist_result &out,
+                std::vector<mindist_pair> &trace) {
     std::memset(&out, 0, sizeof(out));
     trace.clear();
     const int n = hc.n, k = hc.k;
@@ -199,7 +200,7 @@ int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *ar
     const uint32_t singleton = (uint32_t)(n - k + 1);
     uint64_t executed = 0, canonical = 0;
     for (int p = 1; p < bc.njobs; ++p) {
-        const BatchJob *jb = reinterpret_cast<const BatchJob *>(arena + (size_t)bc.job[p] * 128);
+        const BatchJob *jb = reinterpret_cast<const BatchJob *>(arena + (size_t)(bc.job[p] - arena_lo) * 128);
         mindist_pair r{};
         r.j = jb->j;
         r.w = jb->w;
@@ -232,7 +233,7 @@ int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *ar
         const Slot s = slots[bc.U_found];
         if (s.pair < 1 || s.pair >= (uint32_t)bc.njobs)
             return fail(MINDIST_E_HIP, "batch witness slot holds an invalid job index");
-        const BatchJob *jb = reinterpret_cast<const BatchJob *>(arena + (size_t)bc.job[s.pair] * 128);
+        const BatchJob *jb = reinterpret_cast<const BatchJob *>(arena + (size_t)(bc.job[s.pair] - arena_lo) * 128);
         const int j = jb->j;
         const std::vector<int> rows = witness_rows(k, jb->a, jb->b, jb->b2, s);
         if ((int)rows.size() != jb->w)
@@ -358,7 +359,7 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
     parallel_for(L, host_threads(), [&](int s) {
         const int i = live[s];
         const Slot *slots = reinterpret_cast<const Slot *>(eng.h_slots + so[s]);
-        drc[s] = decode_code(hc[i], eng.h_codes[s], eng.h_arena, slots, out[i], traces[s]);
+        drc[s] = decode_code(hc[i], eng.h_codes[s], eng.h_arena, 0, slots, out[i], traces[s]);
         if (drc[s]) derr[s] = last_error_text();
     });
     for (int s = 0; s < L; ++s) {

@@ -76,7 +76,7 @@ struct alignas(128) BatchJob {
     } claim[kJobCounters];
 };
 
-struct BatchCode {
+struct alignas(16) BatchCode {
     int32_t n, k, m_full, k_m, n_gamma, W;
     int32_t status;               // kSlot* or a negative error
     int32_t njobs;                // jobs opened (the open one is njobs-1)
@@ -87,15 +87,29 @@ struct BatchCode {
     uint32_t L_final, U_final;
     uint64_t seq;                 // submission sequence number (server)
     uint64_t t_open, t_done;      // device wall clock: table job opened, code finished
+    // serving: the code's own job arena segment [arena_lo, arena_hi) and its
+    // next free unit (the batch path allocates from BatchGlobal::arena_next)
+    uint64_t arena_lo, arena_hi, arena_next;
     uint32_t job[kBatchMaxPairs]; // arena offsets (128-byte units) of the jobs
     Slot *slots;                  // n+1 witness slots
     uint64_t tab_off[kBatchTabs + 1];   // table entries before table t (t = j*(B+1)+b)
     BatchSet sets[kBatchMaxSets];
 };
 
+// Serving: what a finished code leaves in pinned host memory for the host
+// to decode while the kernel keeps running -- its descriptor up to the job
+// offsets, the first cache line of each job record (every field the host
+// reads lives there) and the witness slot at its least weight.
+constexpr size_t kMirrorCodeBytes = offsetof(BatchCode, slots);
+struct ServeMirror {
+    unsigned char code[(kMirrorCodeBytes + 15) / 16 * 16];
+    unsigned char jobs[kBatchMaxPairs][128];
+    Slot witness;
+};
+
 struct BatchGlobal {
     uint32_t codes_done;          // batch: codes finished (done or error)
-    uint32_t pad0;
+    uint32_t stop;                // serving: the host's stop request, mirrored on the device
     uint64_t arena_next;          // 128-byte units handed out
     uint64_t arena_cap;
     // profile (summed over waves at exit): wall-clock ticks spent in table
@@ -112,6 +126,7 @@ struct BatchArgs {
     unsigned char *arena;
     const uint64_t *binom;
     uint32_t *host_done;          // serving: per slot completion word in pinned host memory
+    ServeMirror *mirror;          // serving: per slot result mirror in pinned host memory
     const uint32_t *host_stop;    // serving: set by the host to end the launch
     int32_t n_codes;              // code slots
     int32_t serving;              // 0: end when every code is done; 1: end on host_stop

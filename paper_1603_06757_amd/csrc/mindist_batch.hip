@@ -75,12 +75,37 @@ __device__ int bound_after_dev(int k, int m_full, int k_m, int ng, int j, int w)
 
 // Allocate a job record with room for `ngroups_cap` group entries; returns
 // its arena offset or 0xFFFFFFFF when the arena is full.
-__device__ uint32_t alloc_job(const BatchArgs &A, int ngroups_cap) {
+__device__ uint32_t alloc_job(const BatchArgs &A, int c, int ngroups_cap) {
     const uint64_t bytes = sizeof(BatchJob) + sizeof(GroupEntry) * (uint64_t)ngroups_cap;
     const uint64_t units = (bytes + 127) / 128;
+    if (A.serving) {              // the code's own segment (reset when its slot is reused)
+        BatchCode *cs = &A.codes[c];
+        const uint64_t off = wave_fetch_add(&cs->arena_next, units);
+        if (off + units > cs->arena_hi || off + units > 0xFFFFFFFFull) return 0xFFFFFFFFu;
+        return (uint32_t)off;
+    }
     const uint64_t off = wave_fetch_add(&A.g->arena_next, units);
     if (off + units > A.g->arena_cap || off + units > 0xFFFFFFFFull) return 0xFFFFFFFFu;
     return (uint32_t)off;
+}
+
+// Serving: copy what the host needs to decode code c into its mirror in
+// pinned host memory (16-byte stores spread over the wave's lanes).
+__device__ void mirror_code(const BatchArgs &A, int c) {
+    const int lane = threadIdx.x & 63;
+    const BatchCode *cs = &A.codes[c];
+    ServeMirror *m = A.mirror + c;
+    const uint4 *src = reinterpret_cast<const uint4 *>(cs);
+    uint4 *dst = reinterpret_cast<uint4 *>(m->code);
+    for (int q = lane; q < (int)(sizeof(m->code) / 16); q += 64) dst[q] = src[q];
+    const int nj = cs->njobs < kBatchMaxPairs ? cs->njobs : kBatchMaxPairs;
+    for (int q = lane; q < nj * 8; q += 64) {
+        const uint4 *jl = reinterpret_cast<const uint4 *>(job_at(A, cs->job[q >> 3]));
+        reinterpret_cast<uint4 *>(m->jobs[q >> 3])[q & 7] = jl[q & 7];
+    }
+    const uint32_t u = cs->U_found;
+    if (u != kInf && u <= (uint32_t)cs->n && lane < 2)
+        reinterpret_cast<uint4 *>(&m->witness)[lane] = reinterpret_cast<const uint4 *>(&cs->slots[u])[lane];
 }
 
 __device__ void finish_code(const BatchArgs &A, int c, int32_t status, uint32_t L, uint32_t U) {
@@ -95,11 +120,14 @@ __device__ void finish_code(const BatchArgs &A, int c, int32_t status, uint32_t 
     if (lane == 0) {
         st_rel(&cs->status, status);
         atomicAdd(&A.g->codes_done, 1u);
-        if (A.host_done) {
-            __threadfence_system();
+    }
+    if (A.host_done) {
+        __threadfence();
+        if (A.mirror) mirror_code(A, c);
+        __threadfence_system();
+        if (lane == 0)
             __hip_atomic_store(&A.host_done[c], (uint32_t)cs->seq, __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_SYSTEM);
-        }
     }
 }
 
@@ -136,7 +164,7 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
         T = 1;
         while (T < 1024 && T * 2 <= want) T <<= 1;
     }
-    const uint32_t off = alloc_job(A, k + 2);
+    const uint32_t off = alloc_job(A, c, k + 2);
     if (off == 0xFFFFFFFFu) {
         finish_code(A, c, -5 /* MINDIST_E_LIMIT */, L_before, min(cs->U_found, (uint32_t)(cs->n - k + 1)));
         return;
@@ -220,7 +248,7 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
 // The table job (job 0): every right table of every set of the code.
 __device__ void open_tables(const BatchArgs &A, int c) {
     BatchCode *cs = &A.codes[c];
-    const uint32_t off = alloc_job(A, 0);
+    const uint32_t off = alloc_job(A, c, 0);
     if (off == 0xFFFFFFFFu) {
         finish_code(A, c, -5, 1, (uint32_t)(cs->n - cs->k + 1));
         return;
@@ -582,10 +610,16 @@ __global__ __launch_bounds__(256) void persistent_batch_kernel(BatchArgs A) {
     for (;;) {
         bool stop = A.deadline_ticks && wall_clock64() - t_start > A.deadline_ticks;
         if (A.serving) {
-            const uint32_t hs = A.host_stop ? __hip_atomic_load(A.host_stop, __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_SYSTEM)
-                                            : 1u;
-            stop = stop || uni32(hs) != 0;
+            // wave 0 watches the host's flag (pinned memory, read over the
+            // bus) and mirrors it on the device for every other wave
+            if (wave == 0) {
+                const uint32_t hs = A.host_stop ? __hip_atomic_load(A.host_stop, __ATOMIC_RELAXED,
+                                                                    __HIP_MEMORY_SCOPE_SYSTEM)
+                                                : 1u;
+                if (uni32(hs) != 0 && lane == 0)
+                    __hip_atomic_store(&A.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            stop = stop || uni32(ld_rlx(&A.g->stop)) != 0;
         } else if (uni32(ld_rlx(&A.g->codes_done)) >= (uint32_t)nc) {
             stop = true;
         }

@@ -37,8 +37,10 @@ void size_tables(HostCode &hc);
 void fit_tables(std::vector<HostCode *> &codes, uint64_t budget);
 void fill_slot(const HostCode &hc, const SlotPlace &pl, unsigned char *rows_stage,
                uint32_t tile_cap, uint64_t seq, BatchCode &bc);
+// arena: host copy of the job arena from unit arena_lo on
 int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *arena,
-                const Slot *slots, mindist_result &out, std::vector<mindist_pair> &trace);
+                uint64_t arena_lo, const Slot *slots, mindist_result &out,
+                std::vector<mindist_pair> &trace);
 size_t job_bytes(int k);
 void parallel_for(int count, int threads, const std::function<void(int)> &fn);
 int host_threads();

@@ -1,0 +1,493 @@
+// mindist_server.cpp -- continuous batching of arriving codes on one GPU.
+//
+// The persistent multi-code kernel runs in "epochs": one launch keeps every
+// resident code moving (pair after pair, Algorithm 1's control on the
+// device) until the manager thread asks it to stop because codes are
+// waiting and room has freed up.  Waves finish the chunk they hold and add
+// it to its job before leaving, so a stopped code resumes exactly where it
+// was in the next launch.  Between launches the manager writes the admitted
+// codes into free slots (descriptor, packed rows; tables are built on the
+// device by each code's first job) and relaunches over old and new codes
+// together.  While a launch runs, a finished code's last wave copies what the
+// host needs (descriptor, job records, witness slot) into pinned host memory
+// and then sets the code's completion word there; the manager decodes it
+// without stopping the others and without any device copy.
+//
+// Device memory: slot descriptors and per-slot job arena segments are sized
+// at creation; rows, saved tables and witness slots of each code come from
+// one pool allocated at creation and handed out first-fit, so admission
+// never allocates device memory while the kernel runs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/mindist.h"
+#include "mindist_batch.h"
+#include "mindist_batch_engine.h"
+#include "mindist_plan.h"
+#include "mindist_pool.h"
+
+namespace md {
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// first-fit allocator over [0, size) with coalescing of freed ranges
+class RangePool {
+public:
+    explicit RangePool(size_t size = 0) { if (size) free_[0] = size; }
+    bool alloc(size_t n, size_t &off) {
+        n = round_up(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            off = it->first;
+            const size_t rest = it->second - n;
+            free_.erase(it);
+            if (rest) free_[off + n] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = round_up(n);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+private:
+    std::map<size_t, size_t> free_;
+};
+
+struct Request {
+    uint64_t tag = 0;
+    HostCode hc;
+    double t_submit = 0, t_admit = 0;
+    size_t bytes = 0;            // rows + tables + witness slots
+};
+
+struct Resident {
+    std::unique_ptr<Request> req;
+    size_t off = 0;              // in the device pool
+    uint64_t seq = 0;
+    bool fresh = false;          // admitted, not yet written to the device
+};
+
+}  // namespace
+}  // namespace md
+
+struct mindist_server {
+    mindist_server_opts o{};
+    int device = 0;
+    int cus = 256;
+    std::chrono::steady_clock::time_point t0;
+
+    std::mutex mu;
+    std::condition_variable cv;       // submits, completions, shutdown
+    std::deque<std::unique_ptr<md::Request>> pending;
+    std::deque<std::unique_ptr<mindist_server_result>> done;
+    std::vector<md::Resident> slots;
+    int resident = 0;
+    bool quit = false;
+    mindist_server_stats st{};
+
+    // device state
+    md::BatchCode *d_codes = nullptr;
+    md::BatchGlobal *d_g = nullptr;
+    unsigned char *d_arena = nullptr;
+    unsigned char *d_pool = nullptr;
+    md::BatchCode *h_codes = nullptr;       // pinned staging of descriptors
+    md::BatchGlobal *h_g = nullptr;
+    uint32_t *h_done = nullptr, *h_stop = nullptr;   // pinned, coherent
+    uint32_t *dv_done = nullptr, *dv_stop = nullptr; // their device addresses
+    md::ServeMirror *h_mirror = nullptr, *dv_mirror = nullptr;   // finished codes' records
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    uint64_t seg_units = 0;                 // job arena units per slot
+    md::RangePool pool;
+    uint64_t next_seq = 1;
+    std::thread mgr;
+    std::string fatal;                      // first device error seen by the manager
+
+    double clock() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace md {
+namespace {
+
+// Decode the finished code in slot s from the mirror the kernel wrote to
+// pinned host memory; frees its slot and pool range.  Called by the manager
+// thread while the kernel may still be running (no device copy involved).
+void collect(mindist_server *S, int s, std::vector<unsigned char> &arena_host,
+             std::vector<Slot> &slot_host) {
+    Resident &r = S->slots[s];
+    HostCode &hc = r.req->hc;
+    auto res = std::make_unique<mindist_server_result>();
+    std::memset(res.get(), 0, sizeof(*res));
+    res->tag = r.req->tag;
+    res->t_submit = r.req->t_submit;
+    res->t_admit = r.req->t_admit;
+    const ServeMirror &m = S->h_mirror[s];
+    BatchCode bc;
+    std::memset(&bc, 0, sizeof(bc));
+    std::memcpy(&bc, m.code, kMirrorCodeBytes);
+    // job p's first line sits at m.jobs[p]
+    const int nj = std::max(0, std::min<int>(bc.njobs, kBatchMaxPairs));
+    arena_host.assign((size_t)std::max(nj, 1) * 128, 0);
+    for (int p = 0; p < nj; ++p) {
+        std::memcpy(arena_host.data() + (size_t)p * 128, m.jobs[p], 128);
+        bc.job[p] = (uint32_t)p;
+    }
+    slot_host.assign((size_t)hc.n + 1, Slot{});
+    if (bc.U_found != kInf && bc.U_found <= (uint32_t)hc.n) slot_host[bc.U_found] = m.witness;
+    std::vector<mindist_pair> trace;
+    int status = decode_code(hc, bc, arena_host.data(), 0, slot_host.data(), res->result, trace);
+    res->n_pairs = (int)std::min<size_t>(trace.size(), MINDIST_SERVER_MAX_PAIRS);
+    for (int t = 0; t < res->n_pairs; ++t) res->pairs[t] = trace[t];
+    res->status = status;
+    if (status != MINDIST_OK && res->result.d >= 0) res->result.d = status;
+    res->t_done = S->clock();
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->pool.release(r.off, r.req->bytes);
+    r.req.reset();
+    r.fresh = false;
+    --S->resident;
+    ++S->st.completed;
+    S->done.push_back(std::move(res));
+    S->cv.notify_all();
+}
+
+// Move waiting requests that fit into free slots (submission order among
+// those that fit).  Caller holds the lock.
+int admit_locked(mindist_server *S) {
+    int admitted = 0;
+    for (auto it = S->pending.begin(); it != S->pending.end();) {
+        int free_slot = -1;
+        for (int s = 0; s < (int)S->slots.size(); ++s)
+            if (!S->slots[s].req) { free_slot = s; break; }
+        if (free_slot < 0) break;
+        size_t off = 0;
+        if (!S->pool.alloc((*it)->bytes, off)) { ++it; continue; }
+        Resident &r = S->slots[free_slot];
+        r.req = std::move(*it);
+        r.req->t_admit = S->clock();
+        r.off = off;
+        r.seq = S->next_seq++;
+        r.fresh = true;
+        ++S->resident;
+        ++S->st.admitted;
+        ++admitted;
+        it = S->pending.erase(it);
+    }
+    return admitted;
+}
+
+// Write the freshly admitted slots to the device (the kernel is stopped).
+int upload_fresh(mindist_server *S, const uint32_t tile_max) {
+    std::vector<std::vector<unsigned char>> stage;
+    for (int s = 0; s < (int)S->slots.size(); ++s) {
+        Resident &r = S->slots[s];
+        if (!r.req || !r.fresh) continue;
+        HostCode &hc = r.req->hc;
+        unsigned char *base = S->d_pool + r.off;
+        SlotPlace pl{base, base + round_up(hc.rows_bytes), base + round_up(hc.rows_bytes) + round_up(hc.tab_bytes)};
+        stage.emplace_back(round_up(hc.rows_bytes));
+        fill_slot(hc, pl, stage.back().data(), tile_max, r.seq, S->h_codes[s]);
+        S->h_codes[s].arena_lo = (uint64_t)s * S->seg_units;
+        S->h_codes[s].arena_hi = (uint64_t)(s + 1) * S->seg_units;
+        S->h_codes[s].arena_next = S->h_codes[s].arena_lo;
+        S->h_done[s] = 0;
+        if (hipMemcpyAsync(S->d_codes + s, S->h_codes + s, sizeof(BatchCode), hipMemcpyHostToDevice, S->stream) != hipSuccess ||
+            hipMemcpyAsync(pl.rows, stage.back().data(), hc.rows_bytes, hipMemcpyHostToDevice, S->stream) != hipSuccess)
+            return fail(MINDIST_E_HIP, "server: slot upload failed");
+        r.fresh = false;
+    }
+    if (hipStreamSynchronize(S->stream) != hipSuccess) return fail(MINDIST_E_HIP, "server: slot upload failed");
+    return MINDIST_OK;
+}
+
+void manager(mindist_server *S) {
+    (void)hipSetDevice(S->device);
+    const uint32_t tile_min = 256, tile_max = 2048;
+    const int bpc_req = S->o.blocks_per_cu > 0 ? S->o.blocks_per_cu : 4;
+    const int resident_bpc = persistent_resident_blocks_per_cu();
+    const int blocks = S->cus * (resident_bpc > 0 && bpc_req > resident_bpc ? resident_bpc : bpc_req);
+    const double epoch_min = (S->o.epoch_min_ms > 0 ? S->o.epoch_min_ms : 0.5) * 1e-3;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, S->device) != hipSuccess || khz <= 0)
+        khz = 100000;
+    std::vector<unsigned char> arena_host;
+    std::vector<Slot> slot_host;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            admit_locked(S);
+            if (S->resident == 0) {
+                if (S->quit) return;
+                S->cv.wait(lk, [&] { return S->quit || !S->pending.empty(); });
+                continue;
+            }
+        }
+        if (upload_fresh(S, tile_max)) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->fatal = last_error_text();
+            S->quit = true;
+            S->cv.notify_all();
+            return;
+        }
+        // one epoch
+        std::memset(S->h_g, 0, sizeof(BatchGlobal));
+        *reinterpret_cast<volatile uint32_t *>(S->h_stop) = 0;
+        std::atomic_thread_fence(std::memory_order_seq_cst);
+        BatchArgs a{};
+        a.codes = S->d_codes;
+        a.g = S->d_g;
+        a.arena = S->d_arena;
+        a.binom = device_binom_from(BN().t.data());
+        a.host_done = S->dv_done;
+        a.host_stop = S->dv_stop;
+        a.mirror = S->dv_mirror;
+        a.n_codes = (int)S->slots.size();
+        a.serving = 1;
+        a.tile_min = tile_min;
+        a.tile_max = tile_max;
+        a.deadline_ticks = (uint64_t)(10.0 * khz * 1000.0);   // a launch never outlives 10 s
+        if (!a.binom ||
+            hipMemcpyAsync(S->d_g, S->h_g, sizeof(BatchGlobal), hipMemcpyHostToDevice, S->stream) != hipSuccess ||
+            hipEventRecord(S->ev0, S->stream) != hipSuccess || launch_persistent(a, blocks, S->stream) ||
+            hipEventRecord(S->ev1, S->stream) != hipSuccess) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->fatal = "server: launch failed";
+            S->quit = true;
+            S->cv.notify_all();
+            return;
+        }
+        const double t_launch = S->clock();
+        bool stop_sent = false;
+        for (;;) {
+            const hipError_t q = hipEventQuery(S->ev1);
+            // completions announced by the kernel
+            for (int s = 0; s < (int)S->slots.size(); ++s) {
+                Resident &r = S->slots[s];
+                if (!r.req || r.fresh) continue;
+                const uint32_t v = __atomic_load_n(&S->h_done[s], __ATOMIC_ACQUIRE);
+                if (v == (uint32_t)r.seq) collect(S, s, arena_host, slot_host);
+            }
+            if (q != hipErrorNotReady) break;
+            bool stop = false;
+            {
+                std::unique_lock<std::mutex> lk(S->mu);
+                if (S->quit || S->resident == 0) stop = true;
+                else if (!S->pending.empty() && S->clock() - t_launch >= epoch_min) {
+                    // stop only if a waiting code would fit now
+                    bool has_slot = false;
+                    for (auto &r : S->slots) has_slot = has_slot || !r.req;
+                    stop = has_slot;
+                }
+                if (!stop) S->cv.wait_for(lk, std::chrono::microseconds(50));
+            }
+            if (stop && !stop_sent) {
+                __atomic_store_n(S->h_stop, 1u, __ATOMIC_RELEASE);
+                stop_sent = true;
+            }
+        }
+        if (hipStreamSynchronize(S->stream) != hipSuccess) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->fatal = std::string("server: kernel failed: ") + hipGetErrorString(hipGetLastError());
+            S->quit = true;
+            S->cv.notify_all();
+            return;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, S->ev0, S->ev1);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            ++S->st.epochs;
+            S->st.seconds_kernel += ms * 1e-3;
+        }
+        // codes that finished right before the launch ended
+        for (int s = 0; s < (int)S->slots.size(); ++s) {
+            Resident &r = S->slots[s];
+            if (!r.req || r.fresh) continue;
+            if (__atomic_load_n(&S->h_done[s], __ATOMIC_ACQUIRE) == (uint32_t)r.seq)
+                collect(S, s, arena_host, slot_host);
+        }
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->quit) return;
+    }
+}
+
+void release(mindist_server *S) {
+    if (S->stream) (void)hipStreamSynchronize(S->stream);
+    dev_free(S->d_codes);
+    dev_free(S->d_g);
+    dev_free(S->d_arena);
+    dev_free(S->d_pool);
+    pinned_free(S->h_codes);
+    pinned_free(S->h_g);
+    if (S->h_done) (void)hipHostFree(S->h_done);
+    if (S->h_stop) (void)hipHostFree(S->h_stop);
+    if (S->h_mirror) (void)hipHostFree(S->h_mirror);
+    if (S->stream) stream_put(S->stream);
+    if (S->ev0) event_put(S->ev0);
+    if (S->ev1) event_put(S->ev1);
+}
+
+}  // namespace
+}  // namespace md
+
+using namespace md;
+
+extern "C" int mindist_server_create(const mindist_server_opts *opts, mindist_server **out) {
+    if (!out) return fail(MINDIST_E_ARG, "null output pointer");
+    *out = nullptr;
+    auto S = std::make_unique<mindist_server>();
+    if (opts) S->o = *opts;
+    const int slots = S->o.max_active > 0 ? S->o.max_active : 256;
+    if (slots > 65536) return fail(MINDIST_E_ARG, "max_active too large");
+    const size_t pool_bytes = S->o.device_bytes > 0 ? (size_t)S->o.device_bytes : (size_t)8 << 30;
+    const int jobs = S->o.jobs_per_code > 0 ? S->o.jobs_per_code : 96;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&S->device) != hipSuccess || hipGetDeviceProperties(&prop, S->device) != hipSuccess)
+        return fail(MINDIST_E_HIP, "no HIP device");
+    S->cus = prop.multiProcessorCount;
+    S->t0 = std::chrono::steady_clock::now();
+    S->slots.resize(slots);
+    S->seg_units = (uint64_t)jobs * job_bytes(MINDIST_MAX_N / 2) / 128;
+    S->d_codes = static_cast<BatchCode *>(dev_alloc(sizeof(BatchCode) * (size_t)slots));
+    S->d_g = static_cast<BatchGlobal *>(dev_alloc(sizeof(BatchGlobal)));
+    S->d_arena = static_cast<unsigned char *>(dev_alloc(S->seg_units * 128 * (size_t)slots));
+    S->d_pool = static_cast<unsigned char *>(dev_alloc(pool_bytes));
+    S->h_codes = static_cast<BatchCode *>(pinned_alloc(sizeof(BatchCode) * (size_t)slots));
+    S->h_g = static_cast<BatchGlobal *>(pinned_alloc(sizeof(BatchGlobal)));
+    if (!S->d_codes || !S->d_g || !S->d_arena || !S->d_pool || !S->h_codes || !S->h_g) {
+        release(S.get());
+        return fail(MINDIST_E_NOMEM, "server: device or pinned allocation failed");
+    }
+    if (hipHostMalloc((void **)&S->h_done, sizeof(uint32_t) * (size_t)slots,
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostMalloc((void **)&S->h_stop, 256, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&S->dv_done, S->h_done, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&S->dv_stop, S->h_stop, 0) != hipSuccess ||
+        hipHostMalloc((void **)&S->h_mirror, sizeof(ServeMirror) * (size_t)slots,
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&S->dv_mirror, S->h_mirror, 0) != hipSuccess) {
+        release(S.get());
+        return fail(MINDIST_E_NOMEM, "server: pinned flag allocation failed");
+    }
+    std::memset(S->h_done, 0, sizeof(uint32_t) * (size_t)slots);
+    *S->h_stop = 0;
+    // every slot starts empty on the device
+    std::memset(S->h_codes, 0, sizeof(BatchCode) * (size_t)slots);
+    for (int s = 0; s < slots; ++s) S->h_codes[s].status = kSlotEmpty;
+    S->stream = stream_get();
+    S->ev0 = event_get();
+    S->ev1 = event_get();
+    if (!S->stream || !S->ev0 || !S->ev1 ||
+        hipMemcpyAsync(S->d_codes, S->h_codes, sizeof(BatchCode) * (size_t)slots, hipMemcpyHostToDevice,
+                       S->stream) != hipSuccess ||
+        hipStreamSynchronize(S->stream) != hipSuccess) {
+        release(S.get());
+        return fail(MINDIST_E_HIP, "server: stream setup failed");
+    }
+    S->pool = RangePool(pool_bytes);
+    mindist_server *raw = S.get();
+    raw->mgr = std::thread(manager, raw);
+    *out = S.release();
+    return MINDIST_OK;
+}
+
+extern "C" int mindist_server_submit(mindist_server *S, const uint64_t *G, int n, int k, uint64_t tag) {
+    if (!S || !G) return fail(MINDIST_E_ARG, "null argument");
+    auto r = std::make_unique<Request>();
+    r->tag = tag;
+    r->t_submit = S->clock();
+    const uint64_t table_cap = (uint64_t)(S->o.table_kib > 0 ? S->o.table_kib : 65536) << 10;
+    int e = prepare_code(G, n, k, table_cap, r->hc);
+    if (e) return e;
+    const size_t pool_bytes = S->o.device_bytes > 0 ? (size_t)S->o.device_bytes : (size_t)8 << 30;
+    // one code may take at most a quarter of the pool: lower its table levels if needed
+    std::vector<HostCode *> one{&r->hc};
+    fit_tables(one, pool_bytes / 4);
+    r->bytes = round_up(r->hc.rows_bytes) + round_up(r->hc.tab_bytes) + round_up(r->hc.slot_bytes);
+    if (r->bytes > pool_bytes) return fail(MINDIST_E_NOMEM, "code does not fit the server's device memory");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->quit) return fail(MINDIST_E_STATE, S->fatal.empty() ? "server is shutting down" : S->fatal);
+    S->pending.push_back(std::move(r));
+    ++S->st.submitted;
+    S->cv.notify_all();
+    return MINDIST_OK;
+}
+
+extern "C" int mindist_server_poll(mindist_server *S, mindist_server_result *out, int cap, int *n_out) {
+    if (!S || !n_out || (cap > 0 && !out)) return fail(MINDIST_E_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    int n = 0;
+    while (n < cap && !S->done.empty()) {
+        out[n++] = *S->done.front();
+        S->done.pop_front();
+    }
+    *n_out = n;
+    if (n == 0 && S->quit && !S->fatal.empty()) return fail(MINDIST_E_HIP, S->fatal);
+    return MINDIST_OK;
+}
+
+extern "C" int mindist_server_wait(mindist_server *S, double timeout_s) {
+    if (!S) return fail(MINDIST_E_ARG, "null server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    const auto until = std::chrono::steady_clock::now() +
+                       std::chrono::microseconds((int64_t)(std::max(timeout_s, 0.0) * 1e6));
+    const bool ok = S->cv.wait_until(lk, until, [&] {
+        return S->quit || (S->pending.empty() && S->resident == 0);
+    });
+    if (!S->fatal.empty()) return fail(MINDIST_E_HIP, S->fatal);
+    return ok ? MINDIST_OK : fail(MINDIST_E_TIMEOUT, "server: codes still waiting or running");
+}
+
+extern "C" double mindist_server_clock(const mindist_server *S) { return S ? S->clock() : 0.0; }
+
+extern "C" int mindist_server_stats_get(const mindist_server *S, mindist_server_stats *out) {
+    if (!S || !out) return fail(MINDIST_E_ARG, "null argument");
+    auto *M = const_cast<mindist_server *>(S);
+    std::lock_guard<std::mutex> lk(M->mu);
+    *out = M->st;
+    out->resident = M->resident;
+    out->pending = (int32_t)M->pending.size();
+    return MINDIST_OK;
+}
+
+extern "C" void mindist_server_destroy(mindist_server *S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->quit = true;
+        S->cv.notify_all();
+    }
+    if (S->h_stop) __atomic_store_n(S->h_stop, 1u, __ATOMIC_RELEASE);
+    if (S->mgr.joinable()) S->mgr.join();
+    release(S);
+    delete S;
+}

@@ -1,0 +1,121 @@
+"""GPU tests of the serving loop (continuous batching of arriving codes).
+
+Each request's result in the mix must be exactly its result alone (d, the
+visited pairs, their bounds, counts and minima), with a valid witness; codes
+that arrive while others run are admitted without waiting for them to end.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import paper_1603_06757_amd as md
+from paper_1603_06757_amd.gen import batch_code, serving_request
+from tests.test_gpu_batch import light_codes, same_as_single
+from tests.test_gpu_parity import check_witness, estimated_work
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def collect(srv, count, timeout=120.0):
+    got = {}
+    t_end = time.time() + timeout
+    while len(got) < count:
+        for r in srv.poll():
+            got[r["tag"]] = r
+        assert time.time() < t_end, f"only {len(got)} of {count} results"
+        time.sleep(0.002)
+    return got
+
+
+def test_server_results_equal_alone_with_staggered_arrivals():
+    cs = light_codes(48, seed=91)
+    say("server: 48 light codes in 4 waves of arrivals, 16 slots")
+    with md.Server(max_active=16) as srv:
+        for i, (n, k, G) in enumerate(cs):
+            srv.submit(G, n, k, tag=i)
+            if i % 12 == 11:
+                time.sleep(0.003)
+        got = collect(srv, len(cs))
+        st = srv.stats()
+    assert st["completed"] == len(cs) and st["admitted"] == len(cs)
+    for i, (n, k, G) in enumerate(cs):
+        r = got[i]
+        assert r["status"] == 0, (i, r["status"])
+        s = md.min_distance(G, n, k)
+        same_as_single(r, s)
+        check_witness(G, n, k, r)
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+
+
+def test_server_admits_while_others_run():
+    """A heavier code is submitted first; light codes submitted while it runs
+    are admitted into free slots after it started and finish before it ends
+    (their work overlaps on the device), and every result equals the code's
+    result alone."""
+    heavy = None
+    for i in range(2000):
+        n, k, G = batch_code(i)
+        if 5e10 <= estimated_work(n, k) <= 3e11:
+            heavy = (n, k, G)
+            break
+    assert heavy is not None
+    light = light_codes(24, seed=92)
+    say("server: heavy", heavy[:2], "then 24 light codes while it runs")
+    with md.Server(max_active=8) as srv:
+        srv.submit(heavy[2], heavy[0], heavy[1], tag=1000)
+        time.sleep(0.002)
+        for i, (n, k, G) in enumerate(light):
+            srv.submit(G, n, k, tag=i)
+        got = collect(srv, len(light) + 1)
+        st = srv.stats()
+    h = got[1000]
+    assert h["status"] == 0
+    same_as_single(h, md.min_distance(heavy[2], heavy[0], heavy[1]))
+    check_witness(heavy[2], heavy[0], heavy[1], h)
+    say("heavy admitted", h["t_admit"], "done", h["t_done"], "stats", st)
+    say("light (admit, done):", [(round(got[i]["t_admit"], 4), round(got[i]["t_done"], 4))
+                                 for i in range(len(light))])
+    overlap = [h["t_admit"] < got[i]["t_admit"] and got[i]["t_done"] < h["t_done"]
+               for i in range(len(light))]
+    assert sum(overlap) >= 7, "no light code ran while the heavy one was on the device"
+    assert st["epochs"] >= 2
+    for i, (n, k, G) in enumerate(light):
+        assert got[i]["status"] == 0
+        same_as_single(got[i], md.min_distance(G, n, k))
+
+
+def test_server_admission_by_device_memory():
+    """A small device budget keeps few codes resident at once; every code
+    still completes with the result it has alone."""
+    cs = [serving_request(i) for i in range(40)]
+    cs = [(n, k, G) for n, k, G in cs if n <= 120][:16]
+    say("server: 16 serving-stream codes, 24 MiB of device memory")
+    with md.Server(max_active=64, device_bytes=24 << 20) as srv:
+        for i, (n, k, G) in enumerate(cs):
+            srv.submit(G, n, k, tag=i)
+        got = collect(srv, len(cs), timeout=300)
+    for i, (n, k, G) in enumerate(cs):
+        assert got[i]["status"] == 0
+        same_as_single(got[i], md.min_distance(G, n, k))
+
+
+def test_server_submit_errors_and_wait():
+    with md.Server(max_active=4) as srv:
+        G = np.zeros((3, 1), dtype=np.uint64)
+        G[0, 0] = 0b0011
+        G[1, 0] = 0b0110
+        G[2, 0] = 0b0101           # row 2 = row 0 + row 1: rank 2 < k = 3
+        with pytest.raises(md.MindistError) as e:
+            srv.submit(G, 4, 3, tag=1)
+        assert e.value.code == -2
+        n, k, G = light_codes(1, seed=93)[0]
+        srv.submit(G, n, k, tag=7)
+        srv.wait(60.0)
+        got = srv.poll()
+        assert [r["tag"] for r in got] == [7] and got[0]["status"] == 0
+        assert srv.poll() == []

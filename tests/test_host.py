@@ -31,6 +31,7 @@ def test_library_exports_every_declared_symbol():
     L = ctypes.CDLL(md.LIB_PATH)
     syms = declared_symbols()
     assert "mindist_create" in syms and "mindist_run" in syms
+    assert "mindist_run_batch" in syms and "mindist_server_submit" in syms
     for s in syms:
         assert hasattr(L, s), s
 

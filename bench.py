@@ -14,7 +14,11 @@ Prints one JSON line:
              lane instructions, peak = 256 CU x 64 lanes x 2.4 GHz / 2
   cpu_baseline  the CPU oracle (stack-based BZ enumeration, all threads it
              was given) on a bounded sample of the same pair
-  batch      (if present) batched vs one-run-per-code codes/s
+  batch      a uniform sample of the 4096-code batch stream: one persistent
+             launch vs one mindist_run per code (codes/s, identical results)
+  serving    open-loop Poisson arrivals of the serving stream at one rate:
+             p50/p99 latency and codes/s (requests above a work cap are left
+             out and counted); --serving-sweep runs the whole rate sweep
 """
 from __future__ import annotations
 
@@ -101,6 +105,107 @@ def cpu_baseline(w, seconds: float = 12.0):
                       f"{t_used:.1f}s, stack-based enumeration, full-width rows"}
 
 
+def estimated_work(md, G, n: int, k: int) -> float:
+    """Codewords Algorithm 1 is expected to evaluate on a random [n,k] code:
+    the pair sequence's bound against the Gilbert-Varshamov distance (the
+    smallest d with sum_{i<=d} C(n,i) >= 2^(n-k)), summing C(k,w) per pair.
+    Used only to stratify and cap synthetic workloads."""
+    import math
+    full, part, _ = md.plan(G, n, k)
+    mf, km = len(full), len(part)
+    ng = mf + (1 if km >= 1 else 0)
+    acc, d = 0, n - k + 1
+    for i in range(n + 1):
+        acc += math.comb(n, i)
+        if acc >= 2 ** (n - k):
+            d = i
+            break
+    f = lambda i, h: h + 1 if i < mf else max(0, h + 1 - (k - km))
+    L, work = 1, 0.0
+    for w in range(1, k + 1):
+        for j in range(ng):
+            if L >= d:
+                return work
+            work += math.comb(k, w)
+            L = sum(f(i, w if i <= j else w - 1) for i in range(ng))
+    return work
+
+
+def batch_leg(codes_total: int, stride: int):
+    """Codes i = 0, stride, 2*stride, ... of the 4096-code batch stream:
+    all of them in one persistent launch (hipGraph) vs one mindist_run per
+    code, same GPU, results compared."""
+    import paper_1603_06757_amd as md
+    from paper_1603_06757_amd.gen import batch_code
+    idx = list(range(0, codes_total, stride))
+    codes = [batch_code(i) for i in idx]
+    md.run_batch(codes[:4], pairs=False)
+    t0 = time.perf_counter()
+    res, info = md.run_batch(codes, pairs=False, deadline_s=600)
+    tb = time.perf_counter() - t0
+    print(f"[bench] batch of {len(codes)} codes: {tb:.2f}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    plain = [md.min_distance(G, n, k) for n, k, G in codes]
+    tp = time.perf_counter() - t0
+    print(f"[bench] one run per code: {tp:.2f}s", file=sys.stderr, flush=True)
+    same = all(r.get("d") == p["d"] and r.get("canonical_total") == p["canonical_total"]
+               for r, p in zip(res, plain))
+    return {"codes": len(codes), "sample": f"codes 0,{stride},...,{codes_total - stride} of the "
+                                            f"{codes_total}-code stream" if stride > 1 else
+                                            f"all {codes_total} codes",
+            "batched_s": tb, "plain_s": tp, "codes_per_s_batched": len(codes) / tb,
+            "codes_per_s_plain": len(codes) / tp, "speedup": tp / tb, "identical": same,
+            "kernel_s": info["seconds_kernel"],
+            "codewords": info["executed_total"],
+            "codewords_per_s_kernel": info["executed_total"] / info["seconds_kernel"]}
+
+
+def serving_leg(rate: float, seconds: float, cap: float, max_requests: int = 4000):
+    """Open-loop Poisson arrivals of the serving stream at `rate` per second
+    for about `seconds`; requests whose estimated work exceeds `cap`
+    codewords are left out of the stream (counted in the report)."""
+    import numpy as np
+    import paper_1603_06757_amd as md
+    from paper_1603_06757_amd.gen import serving_request, poisson_arrivals
+    want = min(max_requests, max(8, int(rate * seconds)))
+    kept, skipped, i = [], 0, 0
+    while len(kept) < want:
+        n, k, G = serving_request(i)
+        i += 1
+        if estimated_work(md, G, n, k) > cap:
+            skipped += 1
+            continue
+        kept.append((n, k, G))
+    arr = poisson_arrivals(len(kept), rate)
+    with md.Server() as srv:
+        t_start = time.perf_counter()
+        for tag, (t, (n, k, G)) in enumerate(zip(arr, kept)):
+            dt = t - (time.perf_counter() - t_start)
+            if dt > 0:
+                time.sleep(dt)
+            srv.submit(G, n, k, tag=tag)
+        got, t_say = [], time.perf_counter()
+        while len(got) < len(kept) and time.perf_counter() - t_start < 600:
+            got += srv.poll()
+            if time.perf_counter() - t_say > 2.0:
+                print(f"[bench] serving {rate}/s: {len(got)}/{len(kept)} done",
+                      file=sys.stderr, flush=True)
+                t_say = time.perf_counter()
+            time.sleep(0.01)
+        t_end = max(r["t_done"] for r in got) - min(r["t_submit"] for r in got) if got else 0.0
+        t_end += t_start
+        st = srv.stats()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in got]) if got else np.zeros(1)
+    ok = sum(1 for r in got if r["status"] == 0)
+    return {"rate_per_s": rate, "requests": len(kept), "completed_ok": ok,
+            "skipped_over_cap": skipped, "work_cap_codewords": cap,
+            "offered_s": float(arr[-1]), "wall_s": t_end - t_start,
+            "codes_per_s": len(got) / (t_end - t_start),
+            "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "epochs": st["epochs"], "kernel_s": st["seconds_kernel"]}
+
+
 def copy_probe(mib: int):
     """Plain device-to-device copies of a known size: the reference reading
     for the FETCH_SIZE / WRITE_SIZE counters (each copy reads and writes
@@ -125,6 +230,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run plain device copies of this size (counter reference) and exit")
+    ap.add_argument("--batch-codes", type=int, default=4096, help="size of the batch stream")
+    ap.add_argument("--batch-stride", type=int, default=8,
+                    help="batch leg: every stride-th code of the stream (1 = all)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="only run the serving sweep (one JSON line per arrival rate) and exit")
+    ap.add_argument("--serving-cap", type=float, default=2e10,
+                    help="serving: leave out requests above this many estimated codewords")
     a = ap.parse_args()
     if a.gpus != 1:
         print("this benchmark runs on one GPU only (single-GPU build); use --gpus 1",
@@ -132,6 +246,11 @@ def main():
         sys.exit(2)
     if a.copy_probe_mib:
         copy_probe(a.copy_probe_mib)
+        return
+    if a.serving_sweep:
+        for rate in (10, 30, 100, 300, 1000):
+            print(json.dumps({"serving": serving_leg(rate, 4.0 if rate >= 100 else 10.0,
+                                                     a.serving_cap)}), flush=True)
         return
     w, results, dt = single_code_leg(a.steps, a.warmup)
     ref = results[0]
@@ -162,6 +281,12 @@ def main():
         "time_to_d_ms": dt / a.steps * 1e3,
         "roofline": roof,
     }
+    if not a.no_batch:
+        print("[bench] batch leg", file=sys.stderr, flush=True)
+        line["batch"] = batch_leg(a.batch_codes, max(1, a.batch_stride))
+    if not a.no_serving:
+        print("[bench] serving leg", file=sys.stderr, flush=True)
+        line["serving"] = serving_leg(300.0, 3.0, a.serving_cap)
     if not a.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)

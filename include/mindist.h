@@ -126,6 +126,9 @@ typedef struct mindist_pair {
     int32_t  split_a;         /* rows per lane subset */
     int32_t  split_b;         /* rows from the (outer) right table */
     int32_t  split_b2;        /* rows from the inner table (0: two-level split) */
+    int32_t  reserved;
+    double   t_start_ms;      /* batch and serving: when the pair's job opened, ms after the
+                                 code's first job opened (ms is then the open-to-close time) */
 } mindist_pair;
 
 /* Section 2 and Algorithm 1 preprocessing: validate and copy G, greedy
@@ -182,6 +185,10 @@ typedef struct mindist_batch_opts {
     int32_t use_graph;        /* 1 = run as one captured hipGraph (default), 0 = plain launch */
     int32_t table_kib;        /* cap on one saved right-sum table in KiB (0 = 65536) */
     int32_t jobs_per_code;    /* job-arena sizing: average jobs per code (0 = 96) */
+    int32_t chunks_per_visit; /* chunks a wave runs on one code's job before it moves on to
+                                 the next code with work (0 = 4; -1 = until the job is fully
+                                 claimed): the share of waves each live code gets */
+    int32_t reserved0;
     double  deadline_s;       /* wall-clock limit of the launch; waves leave after it and the
                                  call returns MINDIST_E_TIMEOUT (0 = none) */
     int64_t stream;           /* hipStream_t, 0 = private */
@@ -244,6 +251,8 @@ typedef struct mindist_server_opts {
     int32_t table_kib;        /* cap on one saved table in KiB (0 = 65536) */
     int32_t jobs_per_code;    /* job records per slot (0 = 96); a code needing more ends
                                  with MINDIST_E_LIMIT */
+    int32_t chunks_per_visit; /* as in mindist_batch_opts (0 = 4) */
+    int32_t reserved0;
 } mindist_server_opts;
 
 #define MINDIST_SERVER_MAX_PAIRS 256

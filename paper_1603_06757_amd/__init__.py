@@ -64,7 +64,8 @@ class Pair(C.Structure):
                 ("L_after", C.c_int32), ("U_after", C.c_int32), ("pair_min", C.c_int32),
                 ("count", C.c_uint64), ("executed", C.c_uint64), ("wsum", C.c_uint64),
                 ("ms", C.c_double), ("dwords", C.c_int32), ("split_a", C.c_int32),
-                ("split_b", C.c_int32), ("split_b2", C.c_int32)]
+                ("split_b", C.c_int32), ("split_b2", C.c_int32), ("reserved", C.c_int32),
+                ("t_start_ms", C.c_double)]
 
     def to_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -73,6 +74,7 @@ class Pair(C.Structure):
 class BatchOpts(C.Structure):
     _fields_ = [("tile_min", C.c_int32), ("tile_max", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("use_graph", C.c_int32), ("table_kib", C.c_int32), ("jobs_per_code", C.c_int32),
+                ("chunks_per_visit", C.c_int32), ("reserved0", C.c_int32),
                 ("deadline_s", C.c_double), ("stream", C.c_int64), ("pairs", C.c_void_p), ("pairs_cap", C.c_int64),
                 ("pairs_index", C.c_void_p), ("seconds_kernel", C.c_double),
                 ("seconds_total", C.c_double), ("seconds_prep", C.c_double),
@@ -87,7 +89,8 @@ SERVER_MAX_PAIRS = 256
 class ServerOpts(C.Structure):
     _fields_ = [("max_active", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("device_bytes", C.c_int64), ("epoch_min_ms", C.c_double),
-                ("table_kib", C.c_int32), ("jobs_per_code", C.c_int32)]
+                ("table_kib", C.c_int32), ("jobs_per_code", C.c_int32),
+                ("chunks_per_visit", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class ServerResult(C.Structure):
@@ -243,7 +246,7 @@ BATCH_MAX_PAIRS = 256
 
 def run_batch(codes, tile_min: int = 0, tile_max: int = 0, blocks_per_cu: int = 0,
               use_graph: int = 1, table_kib: int = 0, jobs_per_code: int = 0,
-              pairs: bool = True, deadline_s: float = 60.0):
+              pairs: bool = True, deadline_s: float = 60.0, chunks_per_visit: int = 0):
     """Solve many codes in one persistent launch.
 
     codes: iterable of (n, k, G).  Returns (results, info): results[i] is the
@@ -261,6 +264,7 @@ def run_batch(codes, tile_min: int = 0, tile_max: int = 0, blocks_per_cu: int = 
     o.tile_min, o.tile_max, o.blocks_per_cu = tile_min, tile_max, blocks_per_cu
     o.use_graph, o.table_kib, o.jobs_per_code = use_graph, table_kib, jobs_per_code
     o.deadline_s = deadline_s
+    o.chunks_per_visit = chunks_per_visit
     done = (C.c_double * B)()
     o.done_s = C.cast(done, C.c_void_p)
     if pairs:
@@ -296,8 +300,10 @@ class Server:
     its visited pairs and t_submit / t_admit / t_done on the server clock."""
 
     def __init__(self, max_active: int = 0, blocks_per_cu: int = 0, device_bytes: int = 0,
-                 epoch_min_ms: float = 0.0, table_kib: int = 0, jobs_per_code: int = 0):
-        o = ServerOpts(max_active, blocks_per_cu, device_bytes, epoch_min_ms, table_kib, jobs_per_code)
+                 epoch_min_ms: float = 0.0, table_kib: int = 0, jobs_per_code: int = 0,
+                 chunks_per_visit: int = 0):
+        o = ServerOpts(max_active, blocks_per_cu, device_bytes, epoch_min_ms, table_kib,
+                       jobs_per_code, chunks_per_visit, 0)
         h = C.c_void_p()
         _check(lib().mindist_server_create(C.byref(o), C.byref(h)))
         self._h = h

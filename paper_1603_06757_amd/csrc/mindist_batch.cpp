@@ -82,9 +82,16 @@ int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &
         }
         hc.bcap[j] = bc;
     }
-    // the balanced split of the expected top level needs b = top/2
-    const int want = std::max(1, expected_top_level(hc) / 2);
-    for (int &b : hc.bcap) b = std::min(b, want);
+    // the balanced split of the expected top level needs b = top/2; a table
+    // is built only if the largest expected pair reads it many times over
+    // (C(k,b) at most 1/64 of C(k,top)): building it costs about as much per
+    // entry as enumerating one codeword
+    const int top = expected_top_level(hc);
+    const int want = std::max(1, top / 2);
+    for (int &b : hc.bcap) {
+        b = std::min(b, want);
+        while (b > 1 && B(k, b) > B(k, top) / 64) --b;
+    }
     size_tables(hc);
     return MINDIST_OK;
 }
@@ -183,7 +190,7 @@ void fill_slot(const HostCode &hc, const SlotPlace &pl, unsigned char *rows_stag
 
 int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *arena,
                 uint64_t arena_lo, const Slot *slots, mindist_result &out,
-                std::vector<mindist_pair> &trace) {
+                std::vector<mindist_pair> &trace, double wall_hz) {
     std::memset(&out, 0, sizeof(out));
     trace.clear();
     const int n = hc.n, k = hc.k;
@@ -214,6 +221,11 @@ int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *ar
         r.split_a = jb->a;
         r.split_b = jb->b;
         r.split_b2 = jb->b2;
+        if (jb->t_open && bc.t_open) {
+            const double hz = wall_hz > 0 ? wall_hz : 1e8;
+            r.t_start_ms = (double)(jb->t_open - bc.t_open) / hz * 1e3;
+            if (jb->t_close >= jb->t_open) r.ms = (double)(jb->t_close - jb->t_open) / hz * 1e3;
+        }
         trace.push_back(r);
         executed += r.executed;
         canonical += r.count;
@@ -345,7 +357,9 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
         SlotPlace pl{eng.d_rows + ro[s], eng.d_tabs + to[s], eng.d_slots + so[s]};
         fill_slot(hc[live[s]], pl, eng.h_rows + ro[s], tile_max, (uint64_t)s + 1, eng.h_codes[s]);
     });
-    e = eng.run(bpc, tile_min, tile_max, use_graph, o.deadline_s > 0 ? o.deadline_s : 0);
+    const uint32_t quantum = o.chunks_per_visit > 0 ? (uint32_t)o.chunks_per_visit
+                             : o.chunks_per_visit < 0 ? 0u : 4u;
+    e = eng.run(bpc, tile_min, tile_max, use_graph, o.deadline_s > 0 ? o.deadline_s : 0, quantum);
     if (e) return e;
     e = eng.fetch_all();
     if (e) return e;
@@ -359,7 +373,7 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
     parallel_for(L, host_threads(), [&](int s) {
         const int i = live[s];
         const Slot *slots = reinterpret_cast<const Slot *>(eng.h_slots + so[s]);
-        drc[s] = decode_code(hc[i], eng.h_codes[s], eng.h_arena, 0, slots, out[i], traces[s]);
+        drc[s] = decode_code(hc[i], eng.h_codes[s], eng.h_arena, 0, slots, out[i], traces[s], eng.wall_hz);
         if (drc[s]) derr[s] = last_error_text();
     });
     for (int s = 0; s < L; ++s) {
@@ -454,7 +468,7 @@ int Engine::init(int slots_, size_t rb, size_t tb, size_t sb, uint64_t au, int64
 }
 
 int Engine::run(int blocks_per_cu, uint32_t tile_min, uint32_t tile_max, bool graph,
-                double deadline_s) {
+                double deadline_s, uint32_t quantum) {
     std::memset(h_g, 0, sizeof(BatchGlobal));
     h_g->arena_cap = arena_units;
     BatchArgs a{};
@@ -466,6 +480,7 @@ int Engine::run(int blocks_per_cu, uint32_t tile_min, uint32_t tile_max, bool gr
     a.serving = 0;
     a.tile_min = tile_min;
     a.tile_max = tile_max;
+    a.quantum = quantum;
     {
         int khz = 0;
         int dev = 0;

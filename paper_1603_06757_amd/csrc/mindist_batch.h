@@ -67,7 +67,8 @@ struct alignas(128) BatchJob {
     uint64_t executed;
     uint64_t expected;            // chunks that complete before the job closes
     uint32_t nctr, pad_a;         // counters in use (1..kJobCounters)
-    uint64_t pad_b[4];
+    uint64_t t_open, t_close;     // device wall clock: job opened, last chunk counted
+    uint64_t pad_b[2];
     alignas(128) uint64_t done;   // completed chunks
     uint64_t pad_d[15];
     struct alignas(128) Counter {
@@ -133,6 +134,8 @@ struct BatchArgs {
     uint32_t tile_min;            // right tile length bounds
     uint32_t tile_max;
     uint64_t deadline_ticks;      // wall-clock ticks after which every wave leaves (0 = none)
+    uint32_t quantum;             // chunks a wave runs on one job per visit (0 = until drained)
+    uint32_t pad_q;
 };
 
 int launch_persistent(const BatchArgs &a, int blocks, void *stream);

@@ -91,7 +91,7 @@ __device__ uint32_t alloc_job(const BatchArgs &A, int c, int ngroups_cap) {
 
 // Serving: copy what the host needs to decode code c into its mirror in
 // pinned host memory (16-byte stores spread over the wave's lanes).
-__device__ void mirror_code(const BatchArgs &A, int c) {
+__device__ __noinline__ void mirror_code(const BatchArgs &A, int c) {
     const int lane = threadIdx.x & 63;
     const BatchCode *cs = &A.codes[c];
     ServeMirror *m = A.mirror + c;
@@ -108,7 +108,7 @@ __device__ void mirror_code(const BatchArgs &A, int c) {
         reinterpret_cast<uint4 *>(&m->witness)[lane] = reinterpret_cast<const uint4 *>(&cs->slots[u])[lane];
 }
 
-__device__ void finish_code(const BatchArgs &A, int c, int32_t status, uint32_t L, uint32_t U) {
+__device__ __noinline__ void finish_code(const BatchArgs &A, int c, int32_t status, uint32_t L, uint32_t U) {
     BatchCode *cs = &A.codes[c];
     const int lane = threadIdx.x & 63;
     if (lane == 0) {
@@ -236,6 +236,8 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
         jb->U_after = 0;
         jb->executed = 0;
         jb->expected = chunk_base;
+        jb->t_open = wall_clock64();
+        jb->t_close = 0;
         jb->nctr = job_counters(chunk_base);
         for (int r = 0; r < kJobCounters; ++r) jb->claim[r].v = 0;
         jb->done = 0;
@@ -261,6 +263,8 @@ __device__ void open_tables(const BatchArgs &A, int c) {
         jb->j = -1;
         jb->total_chunks = (E + kTableChunk - 1) / kTableChunk;
         jb->expected = jb->total_chunks;
+        jb->t_open = wall_clock64();
+        jb->t_close = 0;
         jb->nctr = job_counters(jb->total_chunks);
         for (int r = 0; r < kJobCounters; ++r) jb->claim[r].v = 0;
         jb->done = 0;
@@ -455,12 +459,18 @@ __device__ __forceinline__ void pair_chunk(const BatchArgs &A, JobView &v, uint6
     const uint64_t offc = ch - base;
     ChunkGeo g;
     g.lt = uni64(ge->lt_begin) + offc / n_rt;
-    g.i_begin = (uint32_t)(offc % n_rt) * v.T;
-    g.i_end = min(g.i_begin + v.T, uni32(ge->nr_first));
+    g.i_begin = uni32((uint32_t)(offc % n_rt) * v.T);
+    g.i_end = uni32(min(g.i_begin + v.T, uni32(ge->nr_first)));
     g.e_first = uni32(ge->e);
     g.clip = false;
-    const ItemSrc src{v.rows, v.tab, nullptr, A.binom, A.binom + v.a, A.binom + v.b, kBinomT, kBinomT,
-                      v.n_items, v.k, v.a, v.b, v.b2, v.tab2, v.cnt2};
+    // every address and size of the enumeration re-broadcast from lane 0 at
+    // the point of use: the table reads stay scalar loads whatever the
+    // scheduler loop around this call looks like to the compiler
+    const int a = (int)uni32((uint32_t)v.a), b = (int)uni32((uint32_t)v.b);
+    const ItemSrc src{(const uint32_t *)uni64((uint64_t)v.rows), (const uint32_t *)uni64((uint64_t)v.tab),
+                      nullptr, A.binom, A.binom + a, A.binom + b, kBinomT, kBinomT,
+                      uni64(v.n_items), (int)uni32((uint32_t)v.k), a, b, (int)uni32((uint32_t)v.b2),
+                      (const uint32_t *)uni64((uint64_t)v.tab2), (const uint32_t *)uni64((uint64_t)v.cnt2)};
     uint32_t L[kBatchItems][D], nr[kBatchItems], lmin, ws;
     uint64_t cnt;
     if (v.b2) run_chunk3<D, kBatchItems, false>(src, g, L, nr, lmin, cnt, ws);
@@ -507,6 +517,7 @@ __device__ __forceinline__ void pair_chunk(const BatchArgs &A, JobView &v, uint6
 // Job p of code c has completed: Algorithm 1's control for that code.
 __device__ void advance(const BatchArgs &A, int c, int p, BatchJob *jb) {
     BatchCode *cs = &A.codes[c];
+    if ((threadIdx.x & 63) == 0) jb->t_close = wall_clock64();
     __threadfence();
     const int k = cs->k, n = cs->n, ng = cs->n_gamma;
     const uint32_t singleton = (uint32_t)(n - k + 1);
@@ -590,7 +601,9 @@ __device__ __noinline__ void flush(const BatchArgs &A, int c, int p, BatchJob *j
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void persistent_batch_kernel(BatchArgs A) {
+// At most 128 VGPRs (4 waves per SIMD, 4 blocks of 256 per CU): the few
+// values this spills live outside the enumeration loops.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void persistent_batch_kernel(BatchArgs A) {
     const int lane = threadIdx.x & 63;
     const uint32_t wave = uni32(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const int nc = A.n_codes;
@@ -603,7 +616,7 @@ __global__ __launch_bounds__(256) void persistent_batch_kernel(BatchArgs A) {
     uint32_t drained = 0xFFFFFFFFu;
     // claiming state and this wave's completed chunks of v's job not yet
     // added to it
-    uint32_t ctr = 0, dmask = 0, pmin = kInf;
+    uint32_t ctr = 0, dmask = 0, pmin = kInf, visit = 0;
     uint64_t pdone = 0, pexec = 0;
     // profile: ticks in table chunks, enumeration chunks and flushes
     uint64_t tk_table = 0, tk_pair = 0, tk_flush = 0, n_table = 0, n_pair = 0;
@@ -636,7 +649,8 @@ __global__ __launch_bounds__(256) void persistent_batch_kernel(BatchArgs A) {
             break;
         }
         if (have) {
-            const uint64_t ch = claim_chunk(v.jb, v.total, v.nctr, ctr, dmask);
+            const bool turn_over = A.quantum && visit >= A.quantum;
+            const uint64_t ch = turn_over ? ~0ull : claim_chunk(v.jb, v.total, v.nctr, ctr, dmask);
             if (ch != ~0ull) {
                 const uint64_t t0 = wall_clock64();
                 if (v.kind == 0) {
@@ -658,17 +672,18 @@ __global__ __launch_bounds__(256) void persistent_batch_kernel(BatchArgs A) {
                     n_pair += 1;
                 }
                 pdone += 1;
+                visit += 1;
                 continue;
             }
-            // this job is drained for this wave: tell the others, count its
-            // chunks; its code may open the next pair soon
-            if (lane == 0) atomicMax(&A.codes[v.c].drained, v.p + 1);
+            // this job is drained for this wave (tell the others), or this
+            // visit's share is used up: count its chunks and move on
+            if (!turn_over && lane == 0) atomicMax(&A.codes[v.c].drained, v.p + 1);
             const uint64_t t0 = wall_clock64();
             flush(A, v.c, v.p, v.jb, pdone, pexec, pmin, v.offset);
             tk_flush += wall_clock64() - t0;
-            drained = v.off;
+            if (!turn_over) drained = v.off;
             have = false;
-            cur = v.c;
+            cur = turn_over ? (v.c + 1) % nc : v.c;
         }
         // find a code with work: 64 slots per look, relaxed reads of the
         // status, the jobs opened and the drained hint (a code whose open
@@ -726,6 +741,7 @@ __global__ __launch_bounds__(256) void persistent_batch_kernel(BatchArgs A) {
         dmask = 0;
         pdone = pexec = 0;
         pmin = kInf;
+        visit = 0;
         have = true;
         cur = c;
     }

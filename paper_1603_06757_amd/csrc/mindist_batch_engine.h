@@ -40,7 +40,7 @@ void fill_slot(const HostCode &hc, const SlotPlace &pl, unsigned char *rows_stag
 // arena: host copy of the job arena from unit arena_lo on
 int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *arena,
                 uint64_t arena_lo, const Slot *slots, mindist_result &out,
-                std::vector<mindist_pair> &trace);
+                std::vector<mindist_pair> &trace, double wall_hz = 1e8);
 size_t job_bytes(int k);
 void parallel_for(int count, int threads, const std::function<void(int)> &fn);
 int host_threads();
@@ -72,7 +72,7 @@ struct Engine {
     // persistent kernel (inside one captured hipGraph when graph is set) and
     // wait for it
     int run(int blocks_per_cu, uint32_t tile_min, uint32_t tile_max, bool graph,
-            double deadline_s = 0);
+            double deadline_s = 0, uint32_t quantum = 4);
     // read back the descriptors, the used part of the job arena and the slots
     int fetch_all();
     ~Engine();

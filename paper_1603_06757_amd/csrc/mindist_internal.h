@@ -151,12 +151,16 @@ int launch_peak(const uint32_t *tab, uint32_t steps, uint32_t *out, int D, int b
 // (maximum e at the expected position (k-b)a/(a+1)) has at least
 // kSplitShortRun right entries.  Otherwise the right side takes a second
 // table level of b2 = bcap rows (min(bcap, w-2) unless fixed_b2) and the
-// smallest left size a that still gives kSplitMinItems left subsets and no
-// more than kSplitMaxInner inner entries per outer entry on average (so one
-// outer entry never holds more than a few microseconds of work).
+// smallest left size a that still gives kSplitMinItems left subsets, no
+// more than kSplitMaxInner inner entries per outer entry on average, and no
+// more than kSplitMaxInnerWorst inner entries behind any single outer entry
+// (the lowest Y1, right above the lowest left subset: C(k-a-b1, b2)).  A
+// chunk holds whole inner ranges, so that worst range bounds the work one
+// wave can be stuck with while the rest of the pair waits.
 constexpr uint64_t kSplitShortRun = 256;
 constexpr uint64_t kSplitMinItems = 2048;
 constexpr uint64_t kSplitMaxInner = 4096;
+constexpr uint64_t kSplitMaxInnerWorst = 1u << 15;
 
 template <class BinomFn>
 MD_HD inline void split_rows(int k, int w, int bcap, bool fixed_b2, const BinomFn &C,
@@ -174,6 +178,7 @@ MD_HD inline void split_rows(int k, int w, int bcap, bool fixed_b2, const BinomF
         if (b1 < 1) break;
         if (b1 > bcap) continue;
         if (C(k - b1 - s2, aa) < kSplitMinItems) continue;
+        if (C(k - aa - b1, s2) > kSplitMaxInnerWorst) continue;
         const int e = (k - b1 - s2) * aa / (aa + 1);
         const uint64_t outer = C(k - 1 - s2 - e, b1);
         const uint64_t both = C(k - 1 - e, b1 + s2);

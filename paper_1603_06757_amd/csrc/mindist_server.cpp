@@ -127,6 +127,7 @@ struct mindist_server {
     uint64_t seg_units = 0;                 // job arena units per slot
     md::RangePool pool;
     uint64_t next_seq = 1;
+    double wall_hz = 1e8;                   // device wall-clock rate
     std::thread mgr;
     std::string fatal;                      // first device error seen by the manager
 
@@ -164,7 +165,8 @@ void collect(mindist_server *S, int s, std::vector<unsigned char> &arena_host,
     slot_host.assign((size_t)hc.n + 1, Slot{});
     if (bc.U_found != kInf && bc.U_found <= (uint32_t)hc.n) slot_host[bc.U_found] = m.witness;
     std::vector<mindist_pair> trace;
-    int status = decode_code(hc, bc, arena_host.data(), 0, slot_host.data(), res->result, trace);
+    int status = decode_code(hc, bc, arena_host.data(), 0, slot_host.data(), res->result, trace,
+                             S->wall_hz);
     res->n_pairs = (int)std::min<size_t>(trace.size(), MINDIST_SERVER_MAX_PAIRS);
     for (int t = 0; t < res->n_pairs; ++t) res->pairs[t] = trace[t];
     res->status = status;
@@ -239,6 +241,7 @@ void manager(mindist_server *S) {
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, S->device) != hipSuccess || khz <= 0)
         khz = 100000;
+    S->wall_hz = khz * 1000.0;
     std::vector<unsigned char> arena_host;
     std::vector<Slot> slot_host;
     for (;;) {
@@ -275,6 +278,8 @@ void manager(mindist_server *S) {
         a.tile_min = tile_min;
         a.tile_max = tile_max;
         a.deadline_ticks = (uint64_t)(10.0 * khz * 1000.0);   // a launch never outlives 10 s
+        a.quantum = S->o.chunks_per_visit > 0 ? (uint32_t)S->o.chunks_per_visit
+                    : S->o.chunks_per_visit < 0 ? 0u : 4u;
         if (!a.binom ||
             hipMemcpyAsync(S->d_g, S->h_g, sizeof(BatchGlobal), hipMemcpyHostToDevice, S->stream) != hipSuccess ||
             hipEventRecord(S->ev0, S->stream) != hipSuccess || launch_persistent(a, blocks, S->stream) ||

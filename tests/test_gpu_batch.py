@@ -152,3 +152,13 @@ def test_batch_single_code_and_repeat():
         res, info = md.run_batch([(w.n, w.k, w.matrix())])
         assert res[0]["d"] == gold["d"]
         compare_with_trace(res[0], gold["trace"], gold["counts"], gold["pair_min"], None, w.k)
+
+
+def test_batch_kernel_keeps_four_blocks_per_cu():
+    """The persistent kernel must fit 4 blocks of 256 threads per CU (at
+    most 128 VGPRs): a larger register budget silently drops a quarter of
+    the resident waves."""
+    cs = light_codes(4, seed=95)
+    res, info = md.run_batch(cs)
+    say("waves", info["waves"])
+    assert info["waves"] == 256 * 4 * 4      # MI355X: 256 CUs, 4 blocks of 4 waves

@@ -248,7 +248,7 @@ def test_chunk_orders_and_dispensers(order, counters, items, left):
         compare_with_trace(res, gold["trace"], gold["counts"], gold["pair_min"], gold["wsum"], w.k)
 
 
-@pytest.mark.parametrize("table_mib", [1, 4])
+@pytest.mark.parametrize("table_mib", [1, 2])
 def test_three_level_split_small_tables(table_mib):
     """Small saved tables force the three-level split (lane subset, outer
     table, inner table) on the larger levels of [255,40], whose two-level

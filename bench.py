@@ -59,6 +59,32 @@ def single_code_leg(steps: int, warmup: int):
     return w, results, t1 - t0
 
 
+KERNEL_SOURCES = ["paper_1603_06757_amd/csrc/mindist_kernels.hip",
+                  "paper_1603_06757_amd/csrc/mindist_device.h",
+                  "paper_1603_06757_amd/csrc/mindist_internal.h"]
+COUNTERS = os.path.join(ROOT, "profiles", "enum_pair_kernel_rand150x75_counters.txt")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the enumeration kernel from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's
+    reading), or None once the kernel sources differ from the ones the
+    counters were taken with."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    vals = dict(line.split(":", 1) for line in text.splitlines()
+                if line.startswith(("traffic_bytes_per_launch:", "kernel_sources_sha256_16:")))
+    if vals.get("kernel_sources_sha256_16", "").split()[:1] != [h.hexdigest()[:16]]:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def roofline(results):
     # dominant kernel: the enumeration instance (dwords carried) with the most time
     per_d = {}
@@ -76,7 +102,8 @@ def roofline(results):
         "peak": PEAK_DWORD_OPS / 1e12,
         "unit": "T 32-bit xor+popcount/s",
         "frac": achieved / PEAK_DWORD_OPS,
-        "traffic": None,
+        "traffic": measured_traffic(),
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
         "kernel": f"md::enum_pair_kernel<{D}, {LANE_ITEMS}, false>",
         "launches": launches,
         "avg_launch_us": sec / launches * 1e6,

@@ -164,11 +164,26 @@ def batch_leg(codes_total: int, stride: int):
     code, same GPU, results compared."""
     import paper_1603_06757_amd as md
     from paper_1603_06757_amd.gen import batch_code
+    from paper_1603_06757_amd.autotune import tuned_options
     idx = list(range(0, codes_total, stride))
     codes = [batch_code(i) for i in idx]
-    md.run_batch(codes[:4], pairs=False)
+
+    def tuning_sample():
+        # other codes of the same stream, without the heaviest (tuning in seconds)
+        out = []
+        for i in range(4, codes_total, 32):
+            n, k, G = batch_code(i)
+            if estimated_work(md, G, n, k) <= 2e11:
+                out.append((n, k, G))
+        return out
+
     t0 = time.perf_counter()
-    res, info = md.run_batch(codes, pairs=False, deadline_s=600)
+    opts = tuned_options(f"batch stream of {codes_total} codes", tuning_sample,
+                         log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+    t_tune = time.perf_counter() - t0
+    md.run_batch(codes[:4], pairs=False, **opts)
+    t0 = time.perf_counter()
+    res, info = md.run_batch(codes, pairs=False, deadline_s=600, **opts)
     tb = time.perf_counter() - t0
     print(f"[bench] batch of {len(codes)} codes: {tb:.2f}s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -182,7 +197,7 @@ def batch_leg(codes_total: int, stride: int):
                                             f"all {codes_total} codes",
             "batched_s": tb, "plain_s": tp, "codes_per_s_batched": len(codes) / tb,
             "codes_per_s_plain": len(codes) / tp, "speedup": tp / tb, "identical": same,
-            "kernel_s": info["seconds_kernel"],
+            "kernel_s": info["seconds_kernel"], "autotuned": opts, "autotune_s": t_tune,
             "codewords": info["executed_total"],
             "codewords_per_s_kernel": info["executed_total"] / info["seconds_kernel"]}
 

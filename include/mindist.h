@@ -164,6 +164,11 @@ const char *mindist_last_error(void);
  * enumeration's achieved rate is compared against. */
 int mindist_calibrate(int dwords, int blocks_per_cu, double *codewords_per_s, double *seconds);
 
+/* The current HIP device: its architecture name (e.g. "gfx950", written to
+ * name with at most cap bytes including the terminator) and its compute
+ * unit count.  Either output may be NULL. */
+int mindist_device(char *name, int cap, int *compute_units);
+
 /* Host-only planning (no device needed): the greedy partition and the
  * systematic matrices.  sets: n ints (full sets of k columns each, then the
  * partial set); gammas: n_gamma * k * W words (full sets first, partial last;

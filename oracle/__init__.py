@@ -52,6 +52,8 @@ def lib():
                                C.c_int, u64p, u64p, u64p, u64p]
         L.orc_combo_codeword.restype = C.c_int
         L.orc_combo_codeword.argtypes = [u64p, C.c_int, C.c_int, C.c_int, C.c_uint64, ip, u64p]
+        L.orc_set_fault.restype = None
+        L.orc_set_fault.argtypes = [C.c_int]
         L.orc_bz.restype = C.c_int
         L.orc_bz.argtypes = [u64p, C.c_int, C.c_int, C.c_void_p, C.c_int,
                              ip, u64p, ip, u64p, ip, C.c_int, ip, u64p, ip, u64p]
@@ -84,6 +86,22 @@ def _check(rc):
     if rc < 0:
         raise OracleError({-1: "E_ARG", -2: "E_RANK", -4: "E_NOMEM", -6: "E_LIMIT"}.get(rc, rc))
     return rc
+
+
+class planted:
+    """Context manager for the tests that show the pins catch mistakes:
+    plants mistake `fault` (see the list in mindist_oracle.c) in the oracle
+    for the duration of the block."""
+
+    def __init__(self, fault: int):
+        self.fault = fault
+
+    def __enter__(self):
+        lib().orc_set_fault(self.fault)
+        return self
+
+    def __exit__(self, *exc):
+        lib().orc_set_fault(0)
 
 
 def binom(n: int, r: int) -> int:

@@ -53,10 +53,22 @@
 enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_RANK = -2, ORC_E_NOMEM = -4,
        ORC_E_LIMIT = -6 };
 
+/*
+ * Planted mistakes, for the tests that show the pins catch them (0 = none,
+ * the only value outside those tests):
+ *   1 full sets contribute h instead of h+1 to the lower bound (a dropped term)
+ *   2 every set is counted at level g in the per-pair bound (a wrong index)
+ *   3 each pair stops one combination early
+ *   4 Gamma_j is reduced only below each pivot (not the reduced echelon form)
+ *   5 the weight ignores the last word of a codeword
+ */
+static int orc_fault = 0;
+void orc_set_fault(int f) { orc_fault = f; }
+
 static int popw(const uint64_t *x, int W)
 {
     int s = 0;
-    for (int i = 0; i < W; i++) s += __builtin_popcountll(x[i]);
+    for (int i = 0; i < W - (orc_fault == 5 && W > 1 ? 1 : 0); i++) s += __builtin_popcountll(x[i]);
     return s;
 }
 
@@ -230,7 +242,7 @@ int orc_gamma(const uint64_t *G, int n, int k, const int *first, int nfirst, uin
                 Gamma[(size_t)p * W + t] = Gamma[(size_t)r * W + t];
                 Gamma[(size_t)r * W + t] = tmp;
             }
-        for (int i = 0; i < k; i++)
+        for (int i = (orc_fault == 4 ? r + 1 : 0); i < k; i++)
             if (i != r && getbit(Gamma + (size_t)i * W, c))
                 for (int t = 0; t < W; t++) Gamma[(size_t)i * W + t] ^= Gamma[(size_t)r * W + t];
         r++;
@@ -305,6 +317,7 @@ static void walk_range(const pair_job *jb, uint64_t start, uint64_t len, pair_ac
         acc->count++;
         if (w < acc->minw) { acc->minw = w; acc->min_rank = rank; }
         if (s + 1 == len) break;
+        if (orc_fault == 3 && s + 2 == len && start + len >= orc_binom(k, g)) break;
         int i = g - 1;
         while (i >= 0 && c[i] == k - g + i) i--;
         if (i < 0) break;
@@ -399,7 +412,7 @@ typedef struct {
 /* bound contribution of set j after its level h has been enumerated */
 static int f_bound(int j, int h, int m_full, int k, int k_m)
 {
-    if (j < m_full) return h + 1;
+    if (j < m_full) return orc_fault == 1 ? h : h + 1;
     int v = h + 1 - (k - k_m);
     return v > 0 ? v : 0;
 }
@@ -468,7 +481,7 @@ int orc_bz(const uint64_t *G, int n, int k, const orc_opts *opt, int nsets_cap,
             if (pm < U_found) { U_found = pm; wj = j; wg = g; wrank = mr; }
             if (!per_level) {
                 int s = 0;
-                for (int i = 0; i < ng; i++) s += f_bound(i, i <= j ? g : g - 1, m_full, k, k_m);
+                for (int i = 0; i < ng; i++) s += f_bound(i, (i <= j || orc_fault == 2) ? g : g - 1, m_full, k, k_m);
                 L = s;
             }
             U = U_found < singleton ? U_found : singleton;

@@ -129,6 +129,7 @@ def lib():
         L.mindist_bound_after.argtypes = [C.c_int] * 6
         L.mindist_calibrate.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
+        L.mindist_device.argtypes = [C.c_char_p, C.c_int, ip]
         if hasattr(L, "mindist_run_batch"):
             L.mindist_run_batch.argtypes = [C.POINTER(u64p), ip, ip, C.c_int,
                                             C.POINTER(Result), C.POINTER(BatchOpts)]
@@ -183,6 +184,14 @@ def calibrate(dwords: int = 3, blocks_per_cu: int = 4):
     r, t = C.c_double(), C.c_double()
     _check(lib().mindist_calibrate(dwords, blocks_per_cu, C.byref(r), C.byref(t)))
     return r.value, t.value
+
+
+def device() -> dict:
+    """Architecture name and compute-unit count of the current GPU."""
+    buf = C.create_string_buffer(64)
+    cus = C.c_int(0)
+    _check(lib().mindist_device(buf, 64, C.byref(cus)))
+    return {"arch": buf.value.decode(), "compute_units": cus.value}
 
 
 def bound_after(k, m_full, k_partial, include_partial, j, w) -> int:

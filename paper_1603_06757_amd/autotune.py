@@ -1,0 +1,110 @@
+"""Autotuner for the persistent multi-code kernel.
+
+The batch and serving kernel has three shape parameters whose best values
+depend on the mix of codes:
+
+* ``chunks_per_visit`` -- chunks a wave runs on one code's job before it
+  moves on to the next code with work: the share of waves each live code
+  gets (small = fair to short codes, large = fewer completions);
+* ``tile_max`` -- the longest right tile of a chunk (chunk size);
+* ``blocks_per_cu`` -- resident workgroups per CU (occupancy).
+
+Words per row are not tuned: each code carries the fewest 32-bit words its
+columns need (identity columns of full sets stripped), and more words only
+add work.
+
+``tune`` runs a coordinate search over these parameters on a seeded sample
+of the workload, keeps only configurations whose results equal the first
+run's (d and the canonical count of every code), and returns the fastest by
+kernel time.  ``tuned_options`` caches the result per device and workload
+key in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import run_batch
+
+SEARCH = [
+    ("chunks_per_visit", [1, 2, 4, 8, -1]),
+    ("tile_max", [1024, 2048, 4096, 8192]),
+    ("blocks_per_cu", [2, 3, 4]),
+]
+DEFAULT = {"chunks_per_visit": 4, "tile_max": 2048, "blocks_per_cu": 4}
+CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1603_06757_amd", "autotune.json")
+
+
+def _key(results):
+    return [(r.get("d"), r.get("canonical_total")) for r in results]
+
+
+def tune(codes, repeats: int = 1, log=None) -> dict:
+    """Coordinate search on `codes` (a list of (n, k, G)).  Returns
+    {"best": options, "trials": [(options, seconds_kernel), ...]}."""
+    best = dict(DEFAULT)
+    ref = None
+    trials = []
+
+    def measure(opts):
+        nonlocal ref
+        t = None
+        for _ in range(repeats):
+            res, info = run_batch(codes, pairs=False, **opts)
+            key = _key(res)
+            if ref is None:
+                ref = key
+            if key != ref:
+                return None            # results differ: never choose it
+            t = info["seconds_kernel"] if t is None else min(t, info["seconds_kernel"])
+        trials.append((dict(opts), t))
+        if log:
+            log(f"autotune {opts}: {t:.4f} s")
+        return t
+
+    best_t = measure(best)
+    for name, values in SEARCH:
+        for v in values:
+            if v == best[name]:
+                continue
+            cand = dict(best)
+            cand[name] = v
+            t = measure(cand)
+            if t is not None and t < best_t:
+                best, best_t = cand, t
+    return {"best": best, "seconds_kernel": best_t, "trials": trials}
+
+
+def device_name() -> str:
+    """Cache label of the current GPU: architecture and compute units."""
+    from . import device
+    d = device()
+    return f"{d['arch']}x{d['compute_units']}"
+
+
+def tuned_options(workload: str, sample_fn, path: str = CACHE, retune: bool = False,
+                  log=None) -> dict:
+    """Options for the batch kernel on `workload`, tuned once per device on
+    the codes `sample_fn()` returns and cached in `path`."""
+    dev = device_name()
+    key = f"{dev}|{workload}"
+    cache = {}
+    if os.path.exists(path):
+        try:
+            cache = json.load(open(path))
+        except (OSError, ValueError):
+            cache = {}
+    if not retune and key in cache:
+        return cache[key]["best"]
+    t0 = time.time()
+    out = tune(sample_fn(), log=log)
+    out["tuned_at"] = t0
+    out["tune_seconds"] = time.time() - t0
+    cache[key] = {k: v for k, v in out.items() if k != "trials"}
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        json.dump(cache, open(path, "w"), indent=1)
+    except OSError:
+        pass
+    return out["best"]

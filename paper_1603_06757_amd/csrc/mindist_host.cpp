@@ -638,3 +638,16 @@ extern "C" int mindist_calibrate(int dwords, int blocks_per_cu, double *codeword
     event_put(e1);
     return rc;
 }
+
+extern "C" int mindist_device(char *name, int cap, int *compute_units) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return md::fail(MINDIST_E_HIP, "no HIP device");
+    if (name && cap > 0) {
+        std::strncpy(name, prop.gcnArchName, (size_t)cap - 1);
+        name[cap - 1] = 0;
+    }
+    if (compute_units) *compute_units = prop.multiProcessorCount;
+    return MINDIST_OK;
+}

@@ -338,3 +338,37 @@ def test_bz_per_pair_matches_printed_formula_at_level_ends():
                 assert La == mf * (g + 1) + max(0, g + 1 - k + km)
             if j == 0 and g > 1:
                 assert Lb == mf * g + max(0, g - k + km)
+
+
+# ---- the pins catch plausible mistakes ----------------------------------------
+
+def _fails(pin):
+    try:
+        pin()
+    except (AssertionError, oracle.OracleError):
+        return True
+    return False
+
+
+# planted mistake -> pins expected to catch it (see the list in mindist_oracle.c)
+_CATCHERS = {
+    1: [test_bz_per_level_bound_is_the_printed_formula,
+        test_bz_per_pair_matches_printed_formula_at_level_ends],
+    2: [test_bz_equals_brute_random_codes, test_bz_equals_brute_k20],
+    3: [lambda: test_stack_cost_lemma(8, 4), lambda: test_pair_weight_sum_closed_form(100, 30, 5),
+        test_bz_counts_are_binomials_and_bound_sound],
+    4: [test_gamma_is_systematic_and_row_equivalent],
+    5: [lambda: test_pair_weight_sum_closed_form(150, 75, 2),
+        lambda: test_bz_reed_muller_large_k(2, 7, 32)],
+}
+
+
+@pytest.mark.parametrize("fault", sorted(_CATCHERS))
+def test_planted_mistakes_are_caught(fault):
+    """Each planted mistake (a dropped bound term, a wrong level index, a
+    skipped combination, an incomplete reduction, a dropped word) makes at
+    least one pin fail; with no mistake planted all of them pass."""
+    with oracle.planted(fault):
+        caught = [_fails(p) for p in _CATCHERS[fault]]
+    assert any(caught), f"mistake {fault} passed every pin"
+    assert not any(_fails(p) for p in _CATCHERS[fault])

@@ -88,6 +88,16 @@ extern "C" {
 #define MINDIST_OPT_CHUNK_ORDER      14
 /* chunk dispensers per pair: 8 (default) interleaved counters, or 1. */
 #define MINDIST_OPT_COUNTERS         15
+/* kernel shape: left subsets a pair's split should provide so that one
+ * pair keeps every resident wave busy; the split moves rows from the right
+ * to the left side (shorter right runs, at least 64 entries) until it does.
+ * 0 = always the balanced split. */
+#define MINDIST_OPT_MIN_ITEMS        16
+/* a pair with at most this many combinations is launched right behind the
+ * previous one, before that one's result is read (default 2^28; 0 = off).
+ * If Algorithm 1 stops before it, it finds nothing below U, leaves at once
+ * and is not reported. */
+#define MINDIST_OPT_SPECULATE        17
 
 typedef struct mindist_ctx mindist_ctx;
 

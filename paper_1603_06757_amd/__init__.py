@@ -20,7 +20,7 @@ E_NAMES = {0: "OK", -1: "E_ARG", -2: "E_RANK", -3: "E_NOMEM", -4: "E_HIP", -5: "
 OPT = {"term": 1, "midpair_exit": 2, "partial": 3, "verify": 4, "stream": 5,
        "deadline_ms": 6, "tile_t": 7, "blocks_per_cu": 8, "profile": 9,
        "cancel_after_chunks": 10, "table_mib": 11, "lane_items": 12,
-       "left_tables": 13, "chunk_order": 14, "counters": 15}
+       "left_tables": 13, "chunk_order": 14, "counters": 15, "min_items": 16, "speculate": 17}
 
 MAX_WORDS = 8
 

@@ -64,6 +64,9 @@ struct mindist_ctx {
     int counters = kCounters;  // chunk dispensers (1 or kCounters)
     int left_tables = 1;       // read left subsets from saved tables when they fit
     uint64_t table_cap = 256ull << 20;
+    uint64_t min_items = 0;    // left subsets a pair's split should give (0 = balanced split)
+    uint64_t speculate = 1ull << 28;   // launch the next pair before the current one's result
+                                       // is read when it has at most this many combinations
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0, cus = 256;
@@ -76,9 +79,12 @@ struct mindist_ctx {
     uint64_t *d_rprefix = nullptr, *h_rprefix = nullptr;
     size_t rprefix_cap = 0;
     // pinned host staging
-    GroupEntry *h_groups = nullptr;
-    unsigned char *h_read = nullptr;    // DevState + PairStat + Slot readback
+    GroupEntry *h_groups = nullptr;     // two buffers of groups_cap entries (next pair staged
+                                        // while the current one runs); d_groups likewise
+    unsigned char *h_read = nullptr;    // Slot readback
+    PairMail *h_mail = nullptr, *d_mail = nullptr;   // pinned mailboxes of pairs (by parity)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> pair_ev;    // profile: start/end event of every pair
     std::vector<uint64_t> rprefix_host;
     // last run
     std::vector<mindist_pair> trace;
@@ -87,6 +93,8 @@ struct mindist_ctx {
 
 static void free_ctx(mindist_ctx *c) {
     if (!c) return;
+    // a launched-ahead pair may still read this context's buffers
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto &g : c->gd) {
         dev_free(g.rows);
         for (auto &kv : g.tabs) {
@@ -100,8 +108,10 @@ static void free_ctx(mindist_ctx *c) {
     pinned_free(c->h_rprefix);
     pinned_free(c->h_groups);
     pinned_free(c->h_read);
+    mapped_free(c->h_mail);
     event_put(c->ev0);
     event_put(c->ev1);
+    for (hipEvent_t e : c->pair_ev) event_put(e);
     if (c->own_stream && c->stream) stream_put(c->stream);
     delete c;
 }
@@ -220,13 +230,18 @@ extern "C" int mindist_create(const uint64_t *G, int n, int k, mindist_ctx **out
     c->max_pairs = c->n_gamma * std::min(k, MINDIST_MAX_LEVEL) + 1;
     c->d_state = static_cast<DevState *>(dev_alloc(state_bytes(c->max_pairs)));
     c->groups_cap = k + 2;
-    c->d_groups = static_cast<GroupEntry *>(dev_alloc(sizeof(GroupEntry) * c->groups_cap));
-    c->h_groups = static_cast<GroupEntry *>(pinned_alloc(sizeof(GroupEntry) * c->groups_cap));
+    c->d_groups = static_cast<GroupEntry *>(dev_alloc(sizeof(GroupEntry) * c->groups_cap * 2));
+    c->h_groups = static_cast<GroupEntry *>(pinned_alloc(sizeof(GroupEntry) * c->groups_cap * 2));
     c->h_read = static_cast<unsigned char *>(pinned_alloc(4096));
+    {
+        void *dm = nullptr;
+        c->h_mail = static_cast<PairMail *>(mapped_alloc(2 * sizeof(PairMail), &dm));
+        c->d_mail = static_cast<PairMail *>(dm);
+    }
     c->ev0 = event_get();
     c->ev1 = event_get();
     if (!c->stream || !c->d_binom || !c->d_state || !c->d_groups || !c->h_groups || !c->h_read ||
-        !c->ev0 || !c->ev1) {
+        !c->h_mail || !c->ev0 || !c->ev1) {
         free_ctx(c);
         return fail(MINDIST_E_NOMEM, "device or pinned allocation failed");
     }
@@ -268,6 +283,12 @@ extern "C" int mindist_set_option(mindist_ctx *c, int key, int64_t v) {
             c->tile_t = (uint32_t)v; break;
         case MINDIST_OPT_LEFT_TABLES: c->left_tables = v ? 1 : 0; break;
         case MINDIST_OPT_CHUNK_ORDER: c->order = v ? 1 : 0; break;
+        case MINDIST_OPT_SPECULATE:
+            if (v < 0) return fail(MINDIST_E_ARG, "speculate must be >= 0");
+            c->speculate = (uint64_t)v; break;
+        case MINDIST_OPT_MIN_ITEMS:
+            if (v < 0 || v > (int64_t)1 << 40) return fail(MINDIST_E_ARG, "min_items out of range");
+            c->min_items = (uint64_t)v; break;
         case MINDIST_OPT_COUNTERS:
             if (v != 1 && v != kCounters) return fail(MINDIST_E_ARG, "counters must be 1 or 8");
             c->counters = (int)v; break;
@@ -329,7 +350,7 @@ PairPlan plan_pair(const mindist_ctx *c, int j, int w, GroupEntry *groups,
     const int k = c->P.k;
     const Binom &B = BN();
     PairPlan pp;
-    const Split sp = choose_split(k, w, c->gd[j].bcap, false);
+    const Split sp = choose_split(k, w, c->gd[j].bcap, false, c->min_items);
     pp.a = sp.a;
     pp.b = sp.b;
     pp.b2 = sp.b2;
@@ -407,134 +428,251 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
     int launches = 0;
     const int midpair = c->midpair_exit && !c->term_per_level;
     int status = MINDIST_OK;
-    bool stop = false;
-    for (int w = 1; w <= k && !stop; ++w) {
-        int U = (int)std::min<uint32_t>(U_found, (uint32_t)singleton);
-        if (L >= U) break;
-        for (int j = 0; j < ng; ++j) {
-            U = (int)std::min<uint32_t>(U_found, (uint32_t)singleton);
-            if (!c->term_per_level && L >= U) { stop = true; break; }
-            if (w > MINDIST_MAX_LEVEL || B(k, w) >= (1ull << 63)) {
-                status = fail(MINDIST_E_LIMIT, "pair (" + std::to_string(j) + "," +
-                                                   std::to_string(w) + ") exceeds the rank-space limit");
-                stop = true;
+
+    // A pair prepared ahead: its plan, tables (built in stream order) and
+    // chunk groups (staged in buffer `buf` and copied in stream order).  The
+    // next pair is prepared while the current one runs, assuming the run
+    // goes on; if it stops, the prepared work is simply not used.
+    struct Prep {
+        int j = 0, w = 0, buf = 0;
+        PairPlan pp;
+        uint32_t *table = nullptr, *ltable = nullptr, *table2 = nullptr, *cnt2 = nullptr;
+    };
+    auto prepare = [&](Prep &q, int j, int w, int buf) -> int {
+        q.j = j;
+        q.w = w;
+        q.buf = buf;
+        GroupEntry *hg = c->h_groups + (size_t)buf * c->groups_cap;
+        std::vector<uint64_t> &rpre = c->rprefix_host;
+        q.pp = plan_pair(c, j, w, hg, c->order ? &rpre : nullptr);
+        q.table = q.ltable = q.table2 = q.cnt2 = nullptr;
+        int e = get_table(c, j, q.pp.b, 1, q.pp.b2, &q.table, &q.cnt2);
+        if (e) return e;
+        if (q.pp.b2) {
+            e = get_table(c, j, q.pp.b2, 1, 0, &q.table2);
+            if (e) return e;
+        }
+        if (c->left_tables && left_table_fits(c, j, q.pp.a)) {
+            e = get_table(c, j, q.pp.a, 0, 0, &q.ltable);
+            if (e) return e;
+        }
+        if (hipMemcpyAsync(c->d_groups + (size_t)buf * c->groups_cap, hg, sizeof(GroupEntry) * q.pp.ngroups,
+                           hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return fail(MINDIST_E_HIP, "group upload failed");
+        return MINDIST_OK;
+    };
+    // the right-major order's prefix table is uploaded right before its launch
+    auto upload_rprefix = [&]() -> int {
+        std::vector<uint64_t> &rpre = c->rprefix_host;
+        if (rpre.size() > c->rprefix_cap) {
+            dev_free(c->d_rprefix);
+            pinned_free(c->h_rprefix);
+            c->rprefix_cap = std::max<size_t>(rpre.size(), 2 * c->rprefix_cap);
+            c->d_rprefix = static_cast<uint64_t *>(dev_alloc(c->rprefix_cap * 8));
+            c->h_rprefix = static_cast<uint64_t *>(pinned_alloc(c->rprefix_cap * 8));
+            if (!c->d_rprefix || !c->h_rprefix) {
+                c->rprefix_cap = 0;
+                return fail(MINDIST_E_NOMEM, "chunk-order table allocation failed");
+            }
+        }
+        std::memcpy(c->h_rprefix, rpre.data(), rpre.size() * 8);
+        if (hipMemcpyAsync(c->d_rprefix, c->h_rprefix, rpre.size() * 8, hipMemcpyHostToDevice,
+                           c->stream) != hipSuccess)
+            return fail(MINDIST_E_HIP, "chunk-order table upload failed");
+        return MINDIST_OK;
+    };
+    // wait for the mailbox of pair `pr` (the kernel's last wave fills it)
+    auto wait_mail = [&](int pr) -> int {
+        const uint32_t *seq = &c->h_mail[pr & 1].seq;
+        std::chrono::steady_clock::time_point idle_since{};
+        bool idle = false;
+        for (uint64_t spin = 1;; ++spin) {
+            if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) == (uint32_t)pr + 1) return MINDIST_OK;
+            if ((spin & 255) == 0) {
+                const hipError_t q = hipStreamQuery(c->stream);
+                if (q != hipSuccess && q != hipErrorNotReady)
+                    return fail(MINDIST_E_HIP, std::string("enumeration kernel failed: ") + hipGetErrorString(q));
+                if (q == hipSuccess) {
+                    // the stream can report completion before the kernel's
+                    // last write to host memory has landed: allow it a moment
+                    const auto now = std::chrono::steady_clock::now();
+                    if (!idle) { idle = true; idle_since = now; }
+                    else if (now - idle_since > std::chrono::milliseconds(50))
+                        return fail(MINDIST_E_HIP, "enumeration kernel ended without publishing its pair");
+                }
+            }
+            __builtin_ia32_pause();
+        }
+    };
+    if (c->profile) {
+        while (c->pair_ev.size() < (size_t)2 * c->max_pairs) {
+            hipEvent_t e = event_get();
+            if (!e) return fail(MINDIST_E_HIP, "event creation failed");
+            c->pair_ev.push_back(e);
+        }
+    }
+
+    // Launch one prepared pair as pair index `idx` with bound L_prev.
+    auto launch = [&](const Prep &q, int idx, int L_prev) -> int {
+        const GammaDev &g = c->gd[q.j];
+        const PairPlan &pp = q.pp;
+        PairArgs pa{};
+        pa.rows = g.rows;
+        pa.table = q.table;
+        pa.ltable = q.ltable;
+        pa.binom = c->d_binom;
+        pa.groups = c->d_groups + (size_t)q.buf * c->groups_cap;
+        pa.st = c->d_state;
+        pa.n_items = pp.n_items;
+        pa.total_chunks = pp.total_chunks;
+        pa.cancel_after = c->cancel_after;
+        pa.ngroups = pp.ngroups;
+        pa.k = k;
+        pa.a = pp.a;
+        pa.b = pp.b;
+        pa.b2 = pp.b2;
+        pa.table2 = q.table2;
+        pa.cnt2 = q.cnt2;
+        pa.T = pp.T;
+        pa.offset = g.stripped ? (uint32_t)q.w : 0u;
+        pa.L_prev = (uint32_t)L_prev;
+        pa.pair = (uint32_t)idx;
+        pa.midpair_exit = (uint32_t)midpair;
+        pa.max_pairs = c->max_pairs;
+        pa.rprefix = c->d_rprefix;
+        pa.order = (uint32_t)c->order;
+        pa.n_rt = pp.n_rt;
+        pa.counters = (uint32_t)c->counters;
+        const uint64_t want = ceil_div(pp.total_chunks, 4);
+        const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->cus * c->blocks_per_cu));
+        pa.waves = (uint32_t)blocks * 4u;
+        pa.mail = c->d_mail + (idx & 1);
+        __atomic_store_n(&c->h_mail[idx & 1].seq, 0u, __ATOMIC_RELEASE);
+        if (c->profile && hipEventRecord(c->pair_ev[2 * idx], c->stream) != hipSuccess)
+            return fail(MINDIST_E_HIP, "event record failed");
+        if (launch_enum_pair(pa, g.D, c->items, c->verify, blocks, c->stream))
+            return fail(MINDIST_E_HIP, "enumeration kernel launch failed");
+        if (c->profile && hipEventRecord(c->pair_ev[2 * idx + 1], c->stream) != hipSuccess)
+            return fail(MINDIST_E_HIP, "event record failed");
+        ++launches;
+        return MINDIST_OK;
+    };
+    // the bound after pair (j, w) if it completes (known before its result)
+    auto L_after_pair = [&](int j, int w, int L_now) {
+        if (!c->term_per_level) return bound_after(k, P.m_full, P.k_m, ng, j, w);
+        if (j != ng - 1) return L_now;
+        int sum = 0;
+        for (int i = 0; i < ng; ++i) sum += bound_f(i, w, P.m_full, k, P.k_m);
+        return sum;
+    };
+
+    Prep cur, nxt;
+    int buf = 0;
+    bool cur_launched = false;   // cur was launched ahead (speculatively) as pair `pairs`
+    if (ng >= 1 && k >= 1) {
+        int e = prepare(cur, 0, 1, buf);
+        if (e) return e;
+    }
+    for (bool more = ng >= 1 && k >= 1; more;) {
+        const int j = cur.j, w = cur.w;
+        const int U = (int)std::min<uint32_t>(U_found, (uint32_t)singleton);
+        // Algorithm 1's test: before every pair (per-pair rule) or before a
+        // level (literal per-level rule)
+        if (L >= U && (!c->term_per_level || j == 0)) break;
+        if (w > MINDIST_MAX_LEVEL || B(k, w) >= (1ull << 63)) {
+            status = fail(MINDIST_E_LIMIT, "pair (" + std::to_string(j) + "," + std::to_string(w) +
+                                               ") exceeds the rank-space limit");
+            break;
+        }
+        if (c->deadline_ms) {
+            const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (el * 1000.0 > (double)c->deadline_ms) {
+                status = fail(MINDIST_E_TIMEOUT, "deadline reached");
                 break;
             }
-            if (c->deadline_ms) {
-                const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-                if (el * 1000.0 > (double)c->deadline_ms) {
-                    status = fail(MINDIST_E_TIMEOUT, "deadline reached");
-                    stop = true;
-                    break;
-                }
-            }
-            const GammaDev &g = c->gd[j];
-            std::vector<uint64_t> &rpre = c->rprefix_host;
-            PairPlan pp = plan_pair(c, j, w, c->h_groups, c->order ? &rpre : nullptr);
-            if (c->order) {
-                if (rpre.size() > c->rprefix_cap) {
-                    dev_free(c->d_rprefix);
-                    pinned_free(c->h_rprefix);
-                    c->rprefix_cap = std::max<size_t>(rpre.size(), 2 * c->rprefix_cap);
-                    c->d_rprefix = static_cast<uint64_t *>(dev_alloc(c->rprefix_cap * 8));
-                    c->h_rprefix = static_cast<uint64_t *>(pinned_alloc(c->rprefix_cap * 8));
-                    if (!c->d_rprefix || !c->h_rprefix) {
-                        c->rprefix_cap = 0;
-                        return fail(MINDIST_E_NOMEM, "chunk-order table allocation failed");
-                    }
-                }
-                std::memcpy(c->h_rprefix, rpre.data(), rpre.size() * 8);
-                HIPCHK(hipMemcpyAsync(c->d_rprefix, c->h_rprefix, rpre.size() * 8,
-                                      hipMemcpyHostToDevice, c->stream));
-            }
-            uint32_t *table = nullptr, *ltable = nullptr, *table2 = nullptr, *cnt2 = nullptr;
-            int e = get_table(c, j, pp.b, 1, pp.b2, &table, &cnt2);
-            if (e) return e;
-            if (pp.b2) {
-                e = get_table(c, j, pp.b2, 1, 0, &table2);
-                if (e) return e;
-            }
-            if (c->left_tables && left_table_fits(c, j, pp.a)) {
-                e = get_table(c, j, pp.a, 0, 0, &ltable);
-                if (e) return e;
-            }
-            HIPCHK(hipMemcpyAsync(c->d_groups, c->h_groups, sizeof(GroupEntry) * pp.ngroups,
-                                  hipMemcpyHostToDevice, c->stream));
-            PairArgs pa{};
-            pa.rows = g.rows;
-            pa.table = table;
-            pa.ltable = ltable;
-            pa.binom = c->d_binom;
-            pa.groups = c->d_groups;
-            pa.st = c->d_state;
-            pa.n_items = pp.n_items;
-            pa.total_chunks = pp.total_chunks;
-            pa.cancel_after = c->cancel_after;
-            pa.ngroups = pp.ngroups;
-            pa.k = k;
-            pa.a = pp.a;
-            pa.b = pp.b;
-            pa.b2 = pp.b2;
-            pa.table2 = table2;
-            pa.cnt2 = cnt2;
-            pa.T = pp.T;
-            pa.offset = g.stripped ? (uint32_t)w : 0u;
-            pa.L_prev = (uint32_t)L;
-            pa.pair = (uint32_t)pairs;
-            pa.midpair_exit = (uint32_t)midpair;
-            pa.max_pairs = c->max_pairs;
-            pa.rprefix = c->d_rprefix;
-            pa.order = (uint32_t)c->order;
-            pa.n_rt = pp.n_rt;
-            pa.counters = (uint32_t)c->counters;
-            const uint64_t want = ceil_div(pp.total_chunks, 4);
-            const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->cus * c->blocks_per_cu));
-            if (c->profile) HIPCHK(hipEventRecord(c->ev0, c->stream));
-            if (launch_enum_pair(pa, g.D, c->items, c->verify, blocks, c->stream))
-                return fail(MINDIST_E_HIP, "enumeration kernel launch failed");
-            if (c->profile) HIPCHK(hipEventRecord(c->ev1, c->stream));
-            ++launches;
-            // read back the run state and this pair's statistics
-            HIPCHK(hipMemcpyAsync(c->h_read, c->d_state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(hipMemcpyAsync(c->h_read + 64, state_pairs(c->d_state) + pairs, sizeof(PairStat),
-                                  hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(hipStreamSynchronize(c->stream));
-            float ms = 0;
-            if (c->profile) {
-                HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-                enum_s += ms * 1e-3;
-            }
-            const DevState *hs = reinterpret_cast<const DevState *>(c->h_read);
-            const PairStat *hp = reinterpret_cast<const PairStat *>(c->h_read + 64);
-            U_found = hs->U_found;
-            const int Lb = L;
-            const bool cut = hs->exit_flag != 0 && hp->executed < B(k, w);
-            if (!c->term_per_level && !cut) L = bound_after(k, P.m_full, P.k_m, ng, j, w);
-            mindist_pair rec{};
-            rec.j = j; rec.w = w; rec.L_before = Lb; rec.L_after = L;
-            rec.U_after = (int)std::min<uint32_t>(U_found, (uint32_t)singleton);
-            rec.pair_min = hp->pair_min == kInf ? -1 : (int)hp->pair_min;
-            rec.count = B(k, w);
-            rec.executed = hp->executed;
-            rec.wsum = hp->wsum;
-            rec.ms = ms;
-            rec.dwords = g.D;
-            rec.split_a = pp.a;
-            rec.split_b = pp.b;
-            rec.split_b2 = pp.b2;
-            c->trace.push_back(rec);
-            executed_total += hp->executed;
-            canonical_total += rec.count;
-            ++pairs;
-            last_j = j;
-            last_w = w;
-            if (hs->cancelled) { status = fail(MINDIST_E_CANCELLED, "cancelled after the chunk budget"); stop = true; break; }
-            if (cut) { exited = 1; stop = true; break; }
         }
-        if (c->term_per_level && !stop) {
-            int s = 0;
-            for (int i = 0; i < ng; ++i) s += bound_f(i, w, P.m_full, k, P.k_m);
-            L = s;
+        if (c->order) {
+            // right-major order: plan again here (the staged plan's prefix
+            // table belongs to the last pair prepared)
+            int e = prepare(cur, j, w, cur.buf);
+            if (e) return e;
+            e = upload_rprefix();
+            if (e) return e;
+        }
+        if (!cur_launched) {
+            int e = launch(cur, pairs, L);
+            if (e) return e;
+        }
+        // stage the next pair while this one runs; a small one is launched
+        // at once (if the run ends here it finds nothing below U and exits)
+        int j2 = j + 1, w2 = w;
+        if (j2 >= ng) { j2 = 0; w2 = w + 1; }
+        const bool have_next = w2 <= k && w2 <= MINDIST_MAX_LEVEL && B(k, w2) < (1ull << 63) && !c->order &&
+                               pairs + 1 < c->max_pairs;
+        bool next_launched = false;
+        if (have_next) {
+            int e = prepare(nxt, j2, w2, buf ^ 1);
+            if (e) return e;
+            if (c->speculate && B(k, w2) <= c->speculate && !c->cancel_after) {
+                e = launch(nxt, pairs + 1, L_after_pair(j, w, L));
+                if (e) return e;
+                next_launched = true;
+            }
+        }
+        int e = wait_mail(pairs);
+        if (e) return e;
+        const GammaDev &g = c->gd[j];
+        const PairPlan &pp = cur.pp;
+        const PairMail hm = c->h_mail[pairs & 1];
+        U_found = std::min(U_found, hm.U_found);
+        const int Lb = L;
+        const bool cut = hm.exit_flag != 0 && hm.executed < B(k, w);
+        if (!c->term_per_level && !cut) L = bound_after(k, P.m_full, P.k_m, ng, j, w);
+        mindist_pair rec{};
+        rec.j = j; rec.w = w; rec.L_before = Lb; rec.L_after = L;
+        rec.U_after = (int)std::min<uint32_t>(U_found, (uint32_t)singleton);
+        rec.pair_min = hm.pair_min == kInf ? -1 : (int)hm.pair_min;
+        rec.count = B(k, w);
+        rec.executed = hm.executed;
+        rec.wsum = hm.wsum;
+        rec.dwords = g.D;
+        rec.split_a = pp.a;
+        rec.split_b = pp.b;
+        rec.split_b2 = pp.b2;
+        c->trace.push_back(rec);
+        executed_total += hm.executed;
+        canonical_total += rec.count;
+        ++pairs;
+        last_j = j;
+        last_w = w;
+        if (hm.cancelled) { status = fail(MINDIST_E_CANCELLED, "cancelled after the chunk budget"); break; }
+        if (cut) { exited = 1; break; }
+        if (c->term_per_level && j == ng - 1) L = L_after_pair(j, w, L);
+        if (w2 > k) break;
+        if (!have_next) {
+            if (w2 > MINDIST_MAX_LEVEL || B(k, w2) >= (1ull << 63)) {
+                status = fail(MINDIST_E_LIMIT, "pair (" + std::to_string(j2) + "," + std::to_string(w2) +
+                                                   ") exceeds the rank-space limit");
+                break;
+            }
+            cur.j = j2;         // right-major order: planned at its launch
+            cur.w = w2;
+            cur_launched = false;
+            continue;
+        }
+        buf ^= 1;
+        std::swap(cur, nxt);
+        cur_launched = next_launched;
+    }
+    // a pair launched ahead of a stop still runs (it finds nothing below U
+    // and leaves at once): return with the stream idle
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->profile && pairs) {
+        for (int t = 0; t < pairs; ++t) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, c->pair_ev[2 * t], c->pair_ev[2 * t + 1]));
+            c->trace[t].ms = ms;
+            enum_s += ms * 1e-3;
         }
     }
     out->n = n;

@@ -53,7 +53,22 @@ struct PairStat {
     uint32_t pad;
     uint64_t executed;     // combinations evaluated
     uint64_t wsum;         // sum of weights (verify mode)
-    uint64_t pad2;
+    uint64_t waves_done;   // waves of the pair's launch that have finished
+};
+
+// What the last wave of a pair's launch leaves in pinned host memory: the
+// run state and the pair's statistics, published by seq = pair + 1 once the
+// rest is written (the host waits on seq instead of synchronising and
+// copying back).
+struct PairMail {
+    uint32_t seq;
+    uint32_t U_found;
+    uint32_t exit_flag;
+    uint32_t cancelled;
+    uint32_t pair_min;
+    uint32_t pad;
+    uint64_t executed;
+    uint64_t wsum;
 };
 
 struct Slot {              // witness of weight v: written once, by the wave
@@ -119,7 +134,8 @@ struct PairArgs {
     uint32_t order;            // 0: chunk = (left tile, right tile) left-major, 1: right-major
     uint32_t n_rt;             // right tiles (order = 1)
     uint32_t counters;         // chunk dispensers in use (1 or kCounters)
-    uint32_t pad;
+    uint32_t waves;            // waves of this launch (grid blocks x 4)
+    PairMail *mail;            // pinned host mailbox, or nullptr
 };
 
 // Saved sums of r-subsets: entry i is the sum of the rows of colex_unrank_r(i)
@@ -161,13 +177,28 @@ constexpr uint64_t kSplitShortRun = 256;
 constexpr uint64_t kSplitMinItems = 2048;
 constexpr uint64_t kSplitMaxInner = 4096;
 constexpr uint64_t kSplitMaxInnerWorst = 1u << 15;
+constexpr uint64_t kSplitMinRun = 64;
 
 template <class BinomFn>
 MD_HD inline void split_rows(int k, int w, int bcap, bool fixed_b2, const BinomFn &C,
-                             int &a, int &b, int &b2) {
+                             int &a, int &b, int &b2, uint64_t min_items = 0) {
     b = w / 2 < bcap ? w / 2 : bcap;
     a = w - b;
     b2 = 0;
+    // a launch for one pair alone: if the balanced split leaves fewer than
+    // min_items left subsets (too few to keep every wave busy), move rows to
+    // the left side while the typical right run keeps kSplitMinRun entries
+    if (min_items && C(k - b, a) < min_items) {
+        bool moved = false;
+        while (b > 1 && C(k - b, a) < min_items) {
+            const int e2 = (k - (b - 1)) * (a + 1) / (a + 2);
+            if (C(k - 1 - e2, b - 1) < kSplitMinRun) break;
+            --b;
+            ++a;
+            moved = true;
+        }
+        if (moved) return;
+    }
     if (w < 5) return;
     const int e_typ = (k - b) * a / (a + 1);
     if (C(k - 1 - e_typ, b) >= kSplitShortRun) return;

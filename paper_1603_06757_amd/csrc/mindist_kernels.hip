@@ -141,6 +141,25 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
                       (unsigned long long)(wws + (uint64_t)p.offset * wcnt));
         if (wmin != kInf) atomicMin(&ps->pair_min, wmin + p.offset);
     }
+    if (p.mail) {
+        // the last wave to finish publishes the pair to the host
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        uint64_t prev = 0;
+        if (lane == 0) prev = atomicAdd((unsigned long long *)&ps->waves_done, 1ull);
+        prev = uni64((uint64_t)__shfl((long long)prev, 0));
+        if (prev + 1 == p.waves && lane == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            PairMail *m = p.mail;
+            m->U_found = __hip_atomic_load(&p.st->U_found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            m->exit_flag = __hip_atomic_load(&p.st->exit_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            m->cancelled = __hip_atomic_load(&p.st->cancelled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            m->pair_min = __hip_atomic_load(&ps->pair_min, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            m->executed = __hip_atomic_load(&ps->executed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            m->wsum = __hip_atomic_load(&ps->wsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence_system();
+            __hip_atomic_store(&m->seq, p.pair + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
 }
 
 // Calibration: the hot loop of enum_pair_kernel with nothing around it.
@@ -230,6 +249,7 @@ __global__ void init_state_kernel(DevState *st, int max_pairs) {
         ps[p].pair_min = kInf;
         ps[p].executed = 0;
         ps[p].wsum = 0;
+        ps[p].waves_done = 0;
     }
 }
 

@@ -155,10 +155,11 @@ void colex_unrank(uint64_t rho, int r, int hi, int *out) {
 }
 
 
-Split choose_split(int k, int w, int bcap, bool fixed_b2) {
+Split choose_split(int k, int w, int bcap, bool fixed_b2, uint64_t min_items) {
     const Binom &B = BN();
     Split sp{0, 0, 0};
-    split_rows(k, w, bcap, fixed_b2, [&](int x, int r) { return B(x, r); }, sp.a, sp.b, sp.b2);
+    split_rows(k, w, bcap, fixed_b2, [&](int x, int r) { return B(x, r); }, sp.a, sp.b, sp.b2,
+               min_items);
     return sp;
 }
 

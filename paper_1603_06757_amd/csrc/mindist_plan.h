@@ -65,7 +65,9 @@ void colex_unrank(uint64_t rho, int r, int hi, int *out);
 // three-level split with b2 = min(bcap, w-2) (fixed_b2: exactly bcap) and the
 // smallest a leaving at least 2048 lane subsets.
 struct Split { int a, b, b2; };
-Split choose_split(int k, int w, int bcap, bool fixed_b2);
+// min_items > 0: a pair launched alone; favour at least that many left
+// subsets (see split_rows)
+Split choose_split(int k, int w, int bcap, bool fixed_b2, uint64_t min_items = 0);
 // outer-table entries per chunk of a three-level pair: about 256K codewords
 // per chunk of tile_items lane subsets
 uint32_t outer_tile(int k, const Split &sp, uint32_t tile_items);

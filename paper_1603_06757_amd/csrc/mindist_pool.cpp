@@ -119,6 +119,47 @@ void pinned_free(void *p) {
     g_live.erase(it);
 }
 
+namespace {
+struct Mapped { size_t size; void *dev; };
+std::unordered_map<void *, Mapped> g_mapped_live;
+std::map<size_t, std::vector<std::pair<void *, void *>>> g_mapped_free;
+}  // namespace
+
+void *mapped_alloc(size_t bytes, void **device) {
+    const size_t sz = round_size(bytes);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_mapped_free.find(sz);
+    if (it != g_mapped_free.end() && !it->second.empty()) {
+        auto pr = it->second.back();
+        it->second.pop_back();
+        g_mapped_live[pr.first] = {sz, pr.second};
+        *device = pr.second;
+        return pr.first;
+    }
+    void *p = nullptr, *d = nullptr;
+    if (hipHostMalloc(&p, sz, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(p);
+        return nullptr;
+    }
+    g_mapped_live[p] = {sz, d};
+    *device = d;
+    return p;
+}
+
+void mapped_free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_mapped_live.find(p);
+    if (it == g_mapped_live.end()) return;
+    g_mapped_free[it->second.size].push_back({p, it->second.dev});
+    g_mapped_live.erase(it);
+}
+
 hipStream_t stream_get() {
     const int dev = cur_dev();
     {

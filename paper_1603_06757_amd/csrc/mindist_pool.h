@@ -16,6 +16,11 @@ void dev_free(void *p);
 // page-locked host memory
 void *pinned_alloc(size_t bytes);
 void pinned_free(void *p);
+// page-locked, coherent host memory mapped into the device's address space
+// (device writes reach the host without copies); *device receives the
+// address kernels use
+void *mapped_alloc(size_t bytes, void **device);
+void mapped_free(void *p);
 // non-blocking streams at the default priority, and timing events
 hipStream_t stream_get();
 void stream_put(hipStream_t s);

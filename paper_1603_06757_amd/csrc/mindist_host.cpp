@@ -360,11 +360,13 @@ PairPlan plan_pair(const mindist_ctx *c, int j, int w, GroupEntry *groups,
         pp.T = c->tile_t;
     } else if (pp.b2 == 0) {
         // right tile length: about 12 chunks per resident wave so the last
-        // chunks of the pair leave little idle time, within [256, 1024] so the
-        // per-chunk setup stays amortised
+        // chunks of the pair leave little idle time, at most 1024, and at
+        // least 512 once the pair is large enough for the per-chunk setup
+        // (claim, left sums) to matter (128 below: small pairs are
+        // latency-bound and want every wave busy)
         const uint64_t waves = (uint64_t)c->cus * c->blocks_per_cu * 4;
         const uint64_t want = B(k, w) / (TB * waves * 12);
-        uint32_t T = 256;
+        uint32_t T = B(k, w) >= 50000000ull ? 512 : 128;
         while (T < 1024 && T < want) T <<= 1;
         pp.T = T;
     } else {

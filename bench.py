@@ -43,8 +43,8 @@ def single_code_leg(steps: int, warmup: int):
     G = w.matrix()
     results = []
 
-    def one():
-        with md.MinDist(G, w.n, w.k, profile=1) as m:
+    def one(profile=0):
+        with md.MinDist(G, w.n, w.k, profile=profile) as m:
             r = m.run()
         return r
 
@@ -56,7 +56,11 @@ def single_code_leg(steps: int, warmup: int):
         results.append(one())
     t1 = time.perf_counter()
     print(f"[bench] timed {steps} steps in {t1 - t0:.3f}s", file=sys.stderr, flush=True)
-    return w, results, t1 - t0
+    # untimed: the same runs with HIP events around every enumeration launch
+    # (each event adds a few microseconds between kernels, so they stay out
+    # of the timed steps); their kernel times cross-check the device clock
+    events = [one(profile=1) for _ in range(2)]
+    return w, results, t1 - t0, events
 
 
 KERNEL_SOURCES = ["paper_1603_06757_amd/csrc/mindist_kernels.hip",
@@ -85,16 +89,23 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
-def roofline(results):
-    # dominant kernel: the enumeration instance (dwords carried) with the most time
-    per_d = {}
-    for r in results:
-        for p in r["pairs"]:
-            t = per_d.setdefault(p["dwords"], [0.0, 0, 0])
-            t[0] += p["ms"] * 1e-3
-            t[1] += p["executed"]
-            t[2] += 1
+def roofline(results, events):
+    # dominant kernel: the enumeration instance (dwords carried) with the most
+    # time.  Launch times of the timed steps come from the device clock (the
+    # kernel's first wave start to its last wave end, published with each
+    # pair); HIP events on the kernel's stream in untimed runs cross-check them.
+    def per_dwords(runs, field):
+        per_d = {}
+        for r in runs:
+            for p in r["pairs"]:
+                t = per_d.setdefault(p["dwords"], [0.0, 0, 0])
+                t[0] += p[field] * 1e-3
+                t[1] += p["executed"]
+                t[2] += 1
+        return per_d
+    per_d = per_dwords(results, "dev_ms")
     D, (sec, cw, launches) = max(per_d.items(), key=lambda kv: kv[1][0])
+    ev_sec, ev_cw, ev_launches = per_dwords(events, "ms").get(D, (0.0, 0, 0))
     achieved = cw * D / sec
     return D, {
         "bound": "alu",
@@ -107,6 +118,9 @@ def roofline(results):
         "kernel": f"md::enum_pair_kernel<{D}, {LANE_ITEMS}, false>",
         "launches": launches,
         "avg_launch_us": sec / launches * 1e6,
+        "timing": "device clock per launch in the timed steps; HIP events in 2 untimed runs",
+        "avg_launch_us_events": ev_sec / ev_launches * 1e6 if ev_launches else None,
+        "codewords_per_s_kernel_events": ev_cw / ev_sec if ev_sec else None,
         "ops_per_launch": cw * D / launches,
         "codewords_per_s_kernel": cw / sec,
     }
@@ -294,12 +308,12 @@ def main():
             print(json.dumps({"serving": serving_leg(rate, 4.0 if rate >= 100 else 10.0,
                                                      a.serving_cap)}), flush=True)
         return
-    w, results, dt = single_code_leg(a.steps, a.warmup)
+    w, results, dt, events = single_code_leg(a.steps, a.warmup)
     ref = results[0]
     for r in results:
         assert r["d"] == ref["d"]
     executed = sum(r["executed_total"] for r in results)
-    D, roof = roofline(results)
+    D, roof = roofline(results, events)
     line = {
         "metric": "codewords/s (XOR+popcount) & time-to-d, [150,75]; batched vs plain codes/s",
         "value": executed / dt,

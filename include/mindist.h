@@ -65,7 +65,9 @@ extern "C" {
 /* wall-clock limit of one run in ms; 0 = none.  Checked between pairs. */
 #define MINDIST_OPT_DEADLINE_MS      6
 /* kernel shape: right-table entries per chunk; 0 (default) = chosen per
- * pair (about 12 chunks per resident wave, between 256 and 1024). */
+ * pair: the shortest tile (16..256) whose chunks fit one round of the
+ * resident waves, else the longest (128..1024) that leaves every wave at
+ * least max(2, D-1) chunks (D = 32-bit words per codeword). */
 #define MINDIST_OPT_TILE_T           7
 /* kernel shape: resident workgroups per CU for the enumeration launch
  * (default 4). */
@@ -93,10 +95,15 @@ extern "C" {
  * to the left side (shorter right runs, at least 64 entries) until it does.
  * 0 = always the balanced split. */
 #define MINDIST_OPT_MIN_ITEMS        16
-/* a pair with at most this many combinations is launched right behind the
- * previous one, before that one's result is read (default 2^28; 0 = off).
- * If Algorithm 1 stops before it, it finds nothing below U, leaves at once
- * and is not reported. */
+/* launching ahead: the next pair is launched right behind the current one,
+ * before that one's result is read, so the device never waits for the host
+ * between pairs.  0 = off; any other value: with mid-pair exit on (the
+ * default) and no deadline every next pair is launched ahead -- if
+ * Algorithm 1 stops before it, its waves read U <= its bound and leave at
+ * once, and it is not reported; otherwise only a pair of at most this many
+ * combinations is (it would run to its end), default 2^28.  Never when the
+ * bound after the current pair reaches the Singleton bound, nor with a
+ * chunk budget. */
 #define MINDIST_OPT_SPECULATE        17
 
 typedef struct mindist_ctx mindist_ctx;
@@ -137,8 +144,12 @@ typedef struct mindist_pair {
     int32_t  split_b;         /* rows from the (outer) right table */
     int32_t  split_b2;        /* rows from the inner table (0: two-level split) */
     int32_t  reserved;
-    double   t_start_ms;      /* batch and serving: when the pair's job opened, ms after the
-                                 code's first job opened (ms is then the open-to-close time) */
+    double   t_start_ms;      /* PROFILE=1: when the pair's kernel started, ms after the first
+                                 pair's; batch and serving: when the pair's job opened, ms after
+                                 the code's first job opened (ms is then the open-to-close time) */
+    double   dev_ms;          /* single path, always: the pair's enumeration kernel on the device
+                                 clock, from its first wave's start to its last wave's end (no
+                                 dispatch latency); 0 in batch and serving records */
 } mindist_pair;
 
 /* Section 2 and Algorithm 1 preprocessing: validate and copy G, greedy

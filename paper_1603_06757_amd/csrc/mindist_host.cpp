@@ -6,9 +6,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <tuple>
 #include <string>
@@ -46,6 +48,14 @@ struct GammaDev {
     int bcap = 0;              // largest b whose table fits the cap
 };
 
+struct PairPlan {
+    int a = 0, b = 0, b2 = 0;   // |X| per lane, outer |Y1| (or right |Y|), inner |Y2|
+    uint32_t T = 0;
+    uint32_t n_rt = 0;         // right tiles (right-major order)
+    uint64_t n_items = 0, total_chunks = 0;
+    int ngroups = 0;
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -70,19 +80,21 @@ struct mindist_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0, cus = 256;
+    double wall_hz = 1e8;      // device wall-clock rate
     // device buffers
     const uint64_t *d_binom = nullptr;   // shared per device
     DevState *d_state = nullptr;
     int max_pairs = 0;
-    GroupEntry *d_groups = nullptr;
-    int groups_cap = 0;
+    int groups_cap = 0;                 // chunk groups of one pair at most (k + 2)
     uint64_t *d_rprefix = nullptr, *h_rprefix = nullptr;
     size_t rprefix_cap = 0;
     // pinned host staging
-    GroupEntry *h_groups = nullptr;     // two buffers of groups_cap entries (next pair staged
-                                        // while the current one runs); d_groups likewise
-    unsigned char *h_read = nullptr;    // Slot readback
-    PairMail *h_mail = nullptr, *d_mail = nullptr;   // pinned mailboxes of pairs (by parity)
+    PairMail *h_mail = nullptr, *d_mail = nullptr;   // pinned mailboxes: pair p uses p % kMailRing
+    WavePart *d_parts = nullptr;        // per-wave totals of the running pair
+    uint64_t parts_cap = 0;
+    // plans of the pairs met so far, by (j, w) and the kernel shape options,
+    // with the device copy of their chunk groups
+    std::map<std::array<uint64_t, 6>, std::pair<PairPlan, const GroupEntry *>> plan_cache;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<hipEvent_t> pair_ev;    // profile: start/end event of every pair
     std::vector<uint64_t> rprefix_host;
@@ -103,12 +115,10 @@ static void free_ctx(mindist_ctx *c) {
         }
     }
     dev_free(c->d_state);
-    dev_free(c->d_groups);
     dev_free(c->d_rprefix);
     pinned_free(c->h_rprefix);
-    pinned_free(c->h_groups);
-    pinned_free(c->h_read);
     mapped_free(c->h_mail);
+    dev_free(c->d_parts);
     event_put(c->ev0);
     event_put(c->ev1);
     for (hipEvent_t e : c->pair_ev) event_put(e);
@@ -223,6 +233,11 @@ extern "C" int mindist_create(const uint64_t *G, int n, int k, mindist_ctx **out
     CHK(hipGetDevice(&c->device));
     CHK(hipGetDeviceProperties(&prop, c->device));
     c->cus = prop.multiProcessorCount;
+    {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && khz > 0)
+            c->wall_hz = khz * 1000.0;
+    }
 #undef CHK
     c->stream = stream_get();
     c->own_stream = true;
@@ -230,18 +245,14 @@ extern "C" int mindist_create(const uint64_t *G, int n, int k, mindist_ctx **out
     c->max_pairs = c->n_gamma * std::min(k, MINDIST_MAX_LEVEL) + 1;
     c->d_state = static_cast<DevState *>(dev_alloc(state_bytes(c->max_pairs)));
     c->groups_cap = k + 2;
-    c->d_groups = static_cast<GroupEntry *>(dev_alloc(sizeof(GroupEntry) * c->groups_cap * 2));
-    c->h_groups = static_cast<GroupEntry *>(pinned_alloc(sizeof(GroupEntry) * c->groups_cap * 2));
-    c->h_read = static_cast<unsigned char *>(pinned_alloc(4096));
     {
         void *dm = nullptr;
-        c->h_mail = static_cast<PairMail *>(mapped_alloc(2 * sizeof(PairMail), &dm));
+        c->h_mail = static_cast<PairMail *>(mapped_alloc(kMailRing * sizeof(PairMail), &dm));
         c->d_mail = static_cast<PairMail *>(dm);
     }
     c->ev0 = event_get();
     c->ev1 = event_get();
-    if (!c->stream || !c->d_binom || !c->d_state || !c->d_groups || !c->h_groups || !c->h_read ||
-        !c->h_mail || !c->ev0 || !c->ev1) {
+    if (!c->stream || !c->d_binom || !c->d_state || !c->h_mail || !c->ev0 || !c->ev1) {
         free_ctx(c);
         return fail(MINDIST_E_NOMEM, "device or pinned allocation failed");
     }
@@ -262,6 +273,7 @@ extern "C" void mindist_destroy(mindist_ctx *c) {
 
 extern "C" int mindist_set_option(mindist_ctx *c, int key, int64_t v) {
     if (!c) return fail(MINDIST_E_ARG, "ctx is NULL");
+    c->plan_cache.clear();        // shape options and the table cap change the plans
     switch (key) {
         case MINDIST_OPT_TERM: c->term_per_level = v ? 1 : 0; break;
         case MINDIST_OPT_MIDPAIR_EXIT: c->midpair_exit = v ? 1 : 0; break;
@@ -331,13 +343,6 @@ extern "C" int mindist_info(const mindist_ctx *c, int *m_full, int *k_partial, i
 // one pair of Algorithm 1 on the device
 namespace {
 
-struct PairPlan {
-    int a = 0, b = 0, b2 = 0;   // |X| per lane, outer |Y1| (or right |Y|), inner |Y2|
-    uint32_t T = 0;
-    uint32_t n_rt = 0;         // right tiles (right-major order)
-    uint64_t n_items = 0, total_chunks = 0;
-    int ngroups = 0;
-};
 
 // Chunks of a pair.  Left tiles are runs of 64*items consecutive left
 // subsets (colex order); a left tile whose first subset has largest element
@@ -359,15 +364,40 @@ PairPlan plan_pair(const mindist_ctx *c, int j, int w, GroupEntry *groups,
     if (c->tile_t) {
         pp.T = c->tile_t;
     } else if (pp.b2 == 0) {
-        // right tile length: about 12 chunks per resident wave so the last
-        // chunks of the pair leave little idle time, at most 1024, and at
-        // least 512 once the pair is large enough for the per-chunk setup
-        // (claim, left sums) to matter (128 below: small pairs are
-        // latency-bound and want every wave busy)
+        // Right tile length from the exact chunk count at each candidate.  A
+        // pair that fits one round of the resident waves (every chunk taken
+        // by its wave at launch, no claims) is bound by the latency of one
+        // wave's walk down its tile: the shortest tile that still fits one
+        // round.  A larger pair is bound by throughput: the longest tile
+        // (fewer chunk set-ups) that still leaves every wave max(2, D-1)
+        // chunks, so the last chunks leave little idle time (a chunk takes
+        // longer as D grows).  Measured per pair on D = 3 and D = 7 codes.
         const uint64_t waves = (uint64_t)c->cus * c->blocks_per_cu * 4;
-        const uint64_t want = B(k, w) / (TB * waves * 12);
-        uint32_t T = B(k, w) >= 50000000ull ? 512 : 128;
-        while (T < 1024 && T < want) T <<= 1;
+        // left tiles and right entries of each group, then chunks per T
+        std::vector<std::pair<uint64_t, uint64_t>> grp;
+        {
+            const uint64_t tiles_ = ceil_div(pp.n_items, TB);
+            for (int e = pp.a - 1; e <= k - 1 - pp.b; ++e) {
+                const uint64_t lt_lo = ceil_div(B(e, pp.a), TB);
+                const uint64_t lt_hi = std::min(ceil_div(B(e + 1, pp.a), TB), tiles_);
+                if (lt_hi > lt_lo) grp.emplace_back(lt_hi - lt_lo, B(k - 1 - e, pp.b));
+            }
+        }
+        auto chunks_at = [&](uint32_t T) {
+            const int sh = __builtin_ctz(T);
+            uint64_t n = 0;
+            for (const auto &g : grp) n += g.first * ((g.second + T - 1) >> sh);
+            return n;
+        };
+        uint32_t T = 0;
+        for (uint32_t t = 16; t <= 256 && !T; t <<= 1)
+            if (chunks_at(t) <= waves) T = t;
+        if (!T) {
+            const uint64_t per_wave = (uint64_t)std::max(2, c->gd[j].D - 1);
+            T = 128;
+            for (uint32_t t = 1024; t > 128; t >>= 1)
+                if (chunks_at(t) >= per_wave * waves) { T = t; break; }
+        }
         pp.T = T;
     } else {
         pp.T = outer_tile(k, sp, (uint32_t)TB);
@@ -431,36 +461,65 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
     const int midpair = c->midpair_exit && !c->term_per_level;
     int status = MINDIST_OK;
 
-    // A pair prepared ahead: its plan, tables (built in stream order) and
-    // chunk groups (staged in buffer `buf` and copied in stream order).  The
-    // next pair is prepared while the current one runs, assuming the run
-    // goes on; if it stops, the prepared work is simply not used.
+    // A pair ready to launch: its plan, chunk groups (device address) and
+    // tables (built in stream order).
     struct Prep {
-        int j = 0, w = 0, buf = 0;
+        int j = 0, w = 0;
         PairPlan pp;
+        const GroupEntry *groups = nullptr;   // device copy (shared per shape)
         uint32_t *table = nullptr, *ltable = nullptr, *table2 = nullptr, *cnt2 = nullptr;
     };
-    auto prepare = [&](Prep &q, int j, int w, int buf) -> int {
+    // per-wave totals: one entry per wave of the widest launch
+    {
+        const uint64_t max_waves = (uint64_t)c->cus * c->blocks_per_cu * 4;
+        if (max_waves > c->parts_cap) {
+            dev_free(c->d_parts);
+            c->d_parts = static_cast<WavePart *>(dev_alloc(sizeof(WavePart) * max_waves));
+            c->parts_cap = c->d_parts ? max_waves : 0;
+            if (!c->d_parts) return fail(MINDIST_E_NOMEM, "per-wave buffer allocation failed");
+        }
+    }
+    // The plan of pair (j, w) (cached per context) with the device copy of
+    // its chunk groups.  Groups depend only on (k, a, b, b2, T, lane items),
+    // so one copy per shape serves every context on the device.  In the
+    // right-major order the plan also fills the host prefix table.
+    std::vector<GroupEntry> plan_tmp(c->groups_cap);
+    auto plan = [&](Prep &q, int j, int w) -> int {
         q.j = j;
         q.w = w;
-        q.buf = buf;
-        GroupEntry *hg = c->h_groups + (size_t)buf * c->groups_cap;
-        std::vector<uint64_t> &rpre = c->rprefix_host;
-        q.pp = plan_pair(c, j, w, hg, c->order ? &rpre : nullptr);
         q.table = q.ltable = q.table2 = q.cnt2 = nullptr;
-        int e = get_table(c, j, q.pp.b, 1, q.pp.b2, &q.table, &q.cnt2);
+        const std::array<uint64_t, 6> key{(uint64_t)j << 32 | (uint32_t)w, (uint64_t)c->items,
+                                          (uint64_t)c->tile_t, (uint64_t)c->blocks_per_cu,
+                                          c->min_items, (uint64_t)c->order};
+        if (!c->order) {
+            auto it = c->plan_cache.find(key);
+            if (it != c->plan_cache.end()) {
+                q.pp = it->second.first;
+                q.groups = it->second.second;
+                return MINDIST_OK;
+            }
+        }
+        q.pp = plan_pair(c, j, w, plan_tmp.data(), c->order ? &c->rprefix_host : nullptr);
+        const uint32_t shape[6] = {(uint32_t)k, (uint32_t)q.pp.a, (uint32_t)q.pp.b, (uint32_t)q.pp.b2,
+                                   q.pp.T, (uint32_t)c->items};
+        q.groups = static_cast<const GroupEntry *>(
+            device_const(shape, sizeof(shape), plan_tmp.data(), sizeof(GroupEntry) * q.pp.ngroups));
+        if (!q.groups) return fail(MINDIST_E_NOMEM, "chunk group upload failed");
+        if (!c->order) c->plan_cache.emplace(key, std::make_pair(q.pp, q.groups));
+        return MINDIST_OK;
+    };
+    // tables of a planned pair (built in stream order on first use)
+    auto stage = [&](Prep &q) -> int {
+        int e = get_table(c, q.j, q.pp.b, 1, q.pp.b2, &q.table, &q.cnt2);
         if (e) return e;
         if (q.pp.b2) {
-            e = get_table(c, j, q.pp.b2, 1, 0, &q.table2);
+            e = get_table(c, q.j, q.pp.b2, 1, 0, &q.table2);
             if (e) return e;
         }
-        if (c->left_tables && left_table_fits(c, j, q.pp.a)) {
-            e = get_table(c, j, q.pp.a, 0, 0, &q.ltable);
+        if (c->left_tables && left_table_fits(c, q.j, q.pp.a)) {
+            e = get_table(c, q.j, q.pp.a, 0, 0, &q.ltable);
             if (e) return e;
         }
-        if (hipMemcpyAsync(c->d_groups + (size_t)buf * c->groups_cap, hg, sizeof(GroupEntry) * q.pp.ngroups,
-                           hipMemcpyHostToDevice, c->stream) != hipSuccess)
-            return fail(MINDIST_E_HIP, "group upload failed");
         return MINDIST_OK;
     };
     // the right-major order's prefix table is uploaded right before its launch
@@ -483,9 +542,9 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
             return fail(MINDIST_E_HIP, "chunk-order table upload failed");
         return MINDIST_OK;
     };
-    // wait for the mailbox of pair `pr` (the kernel's last wave fills it)
+    // wait for the mailbox of pair `pr` (the publish kernel behind it fills it)
     auto wait_mail = [&](int pr) -> int {
-        const uint32_t *seq = &c->h_mail[pr & 1].seq;
+        const uint32_t *seq = &c->h_mail[pr % kMailRing].seq;
         std::chrono::steady_clock::time_point idle_since{};
         bool idle = false;
         for (uint64_t spin = 1;; ++spin) {
@@ -514,7 +573,8 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
         }
     }
 
-    // Launch one prepared pair as pair index `idx` with bound L_prev.
+    // Launch one staged pair as pair index `idx` with bound L_prev, and the
+    // kernel that publishes its result behind it.
     auto launch = [&](const Prep &q, int idx, int L_prev) -> int {
         const GammaDev &g = c->gd[q.j];
         const PairPlan &pp = q.pp;
@@ -523,7 +583,7 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
         pa.table = q.table;
         pa.ltable = q.ltable;
         pa.binom = c->d_binom;
-        pa.groups = c->d_groups + (size_t)q.buf * c->groups_cap;
+        pa.groups = q.groups;
         pa.st = c->d_state;
         pa.n_items = pp.n_items;
         pa.total_chunks = pp.total_chunks;
@@ -548,14 +608,17 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
         const uint64_t want = ceil_div(pp.total_chunks, 4);
         const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->cus * c->blocks_per_cu));
         pa.waves = (uint32_t)blocks * 4u;
-        pa.mail = c->d_mail + (idx & 1);
-        __atomic_store_n(&c->h_mail[idx & 1].seq, 0u, __ATOMIC_RELEASE);
+        pa.parts = c->d_parts;
+        __atomic_store_n(&c->h_mail[idx % kMailRing].seq, 0u, __ATOMIC_RELEASE);
         if (c->profile && hipEventRecord(c->pair_ev[2 * idx], c->stream) != hipSuccess)
             return fail(MINDIST_E_HIP, "event record failed");
         if (launch_enum_pair(pa, g.D, c->items, c->verify, blocks, c->stream))
             return fail(MINDIST_E_HIP, "enumeration kernel launch failed");
         if (c->profile && hipEventRecord(c->pair_ev[2 * idx + 1], c->stream) != hipSuccess)
             return fail(MINDIST_E_HIP, "event record failed");
+        if (launch_publish_pair(c->d_parts, pa.waves, c->d_state, c->d_mail + idx % kMailRing,
+                                (uint32_t)idx, c->stream))
+            return fail(MINDIST_E_HIP, "publish kernel launch failed");
         ++launches;
         return MINDIST_OK;
     };
@@ -567,21 +630,33 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
         for (int i = 0; i < ng; ++i) sum += bound_f(i, w, P.m_full, k, P.k_m);
         return sum;
     };
+    auto beyond_limit = [&](int w) { return w > MINDIST_MAX_LEVEL || B(k, w) >= (1ull << 63); };
 
-    Prep cur, nxt;
-    int buf = 0;
-    bool cur_launched = false;   // cur was launched ahead (speculatively) as pair `pairs`
-    if (ng >= 1 && k >= 1) {
-        int e = prepare(cur, 0, 1, buf);
-        if (e) return e;
-    }
+    // Pairs run in Algorithm 1's order.  The pair Algorithm 1 visits next is
+    // launched once its test passes; behind it, further pairs are launched
+    // ahead of their results (with the bound they get if every pair before
+    // them completes) while the work already queued is small, so the device
+    // never waits for the host between short pairs.  If Algorithm 1 stops,
+    // the pairs launched ahead read U <= their bound and leave at once (with
+    // mid-pair exit on; otherwise only one pair of at most `speculate`
+    // combinations is launched ahead).
+    struct Flight { Prep q; int idx; };
+    std::deque<Flight> fl;          // launched, not read yet; front: next pair visited
+    int nj = 0, nw = 1;             // the next pair to launch
+    int L_pred = L;                 // the bound before it
+    int next_idx = 0;
+    PairMail last_mail{};
+    const bool free_exit = midpair && !c->deadline_ms;
+    constexpr uint64_t kAheadWork = 1ull << 30;   // queued combinations that stop a second launch ahead
+    auto advance = [&](int &j, int &w) { if (++j >= ng) { j = 0; ++w; } };
     for (bool more = ng >= 1 && k >= 1; more;) {
-        const int j = cur.j, w = cur.w;
+        const int j = fl.empty() ? nj : fl.front().q.j;
+        const int w = fl.empty() ? nw : fl.front().q.w;
         const int U = (int)std::min<uint32_t>(U_found, (uint32_t)singleton);
         // Algorithm 1's test: before every pair (per-pair rule) or before a
         // level (literal per-level rule)
         if (L >= U && (!c->term_per_level || j == 0)) break;
-        if (w > MINDIST_MAX_LEVEL || B(k, w) >= (1ull << 63)) {
+        if (beyond_limit(w)) {
             status = fail(MINDIST_E_LIMIT, "pair (" + std::to_string(j) + "," + std::to_string(w) +
                                                ") exceeds the rank-space limit");
             break;
@@ -593,39 +668,55 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
                 break;
             }
         }
-        if (c->order) {
-            // right-major order: plan again here (the staged plan's prefix
-            // table belongs to the last pair prepared)
-            int e = prepare(cur, j, w, cur.buf);
+        if (fl.empty()) {
+            Flight f;
+            int e = plan(f.q, nj, nw);
             if (e) return e;
-            e = upload_rprefix();
+            e = stage(f.q);
             if (e) return e;
-        }
-        if (!cur_launched) {
-            int e = launch(cur, pairs, L);
-            if (e) return e;
-        }
-        // stage the next pair while this one runs; a small one is launched
-        // at once (if the run ends here it finds nothing below U and exits)
-        int j2 = j + 1, w2 = w;
-        if (j2 >= ng) { j2 = 0; w2 = w + 1; }
-        const bool have_next = w2 <= k && w2 <= MINDIST_MAX_LEVEL && B(k, w2) < (1ull << 63) && !c->order &&
-                               pairs + 1 < c->max_pairs;
-        bool next_launched = false;
-        if (have_next) {
-            int e = prepare(nxt, j2, w2, buf ^ 1);
-            if (e) return e;
-            if (c->speculate && B(k, w2) <= c->speculate && !c->cancel_after) {
-                e = launch(nxt, pairs + 1, L_after_pair(j, w, L));
+            if (c->order) {
+                e = upload_rprefix();
                 if (e) return e;
-                next_launched = true;
             }
+            e = launch(f.q, next_idx, L);
+            if (e) return e;
+            f.idx = next_idx++;
+            L_pred = L_after_pair(nj, nw, L);
+            advance(nj, nw);
+            fl.push_back(f);
         }
-        int e = wait_mail(pairs);
+        // launch ahead
+        // (not once the U already known is at or below the pair's bound:
+        // Algorithm 1 certainly stops before it)
+        while (c->speculate && !c->cancel_after && !c->order && fl.size() < (size_t)kMailRing - 1 &&
+               nw <= k && !beyond_limit(nw) && next_idx < c->max_pairs &&
+               L_pred < (int)std::min<uint32_t>(U_found, (uint32_t)singleton)) {
+            uint64_t queued = 0;
+            for (const Flight &x : fl) queued += B(k, x.q.w);
+            // one pair ahead always; more only while the queued work is short
+            if (free_exit ? (fl.size() >= 2 && queued >= kAheadWork)
+                          : (fl.size() >= 2 || B(k, nw) > c->speculate))
+                break;
+            Flight f;
+            int e = plan(f.q, nj, nw);
+            if (e) return e;
+            e = stage(f.q);
+            if (e) return e;
+            e = launch(f.q, next_idx, L_pred);
+            if (e) return e;
+            f.idx = next_idx++;
+            L_pred = L_after_pair(nj, nw, L_pred);
+            advance(nj, nw);
+            fl.push_back(f);
+        }
+        const Flight f = fl.front();
+        fl.pop_front();
+        int e = wait_mail(f.idx);
         if (e) return e;
         const GammaDev &g = c->gd[j];
-        const PairPlan &pp = cur.pp;
-        const PairMail hm = c->h_mail[pairs & 1];
+        const PairPlan &pp = f.q.pp;
+        const PairMail hm = c->h_mail[f.idx % kMailRing];
+        last_mail = hm;
         U_found = std::min(U_found, hm.U_found);
         const int Lb = L;
         const bool cut = hm.exit_flag != 0 && hm.executed < B(k, w);
@@ -641,6 +732,7 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
         rec.split_a = pp.a;
         rec.split_b = pp.b;
         rec.split_b2 = pp.b2;
+        rec.dev_ms = hm.t_end > hm.t_begin ? (double)(hm.t_end - hm.t_begin) / c->wall_hz * 1e3 : 0.0;
         c->trace.push_back(rec);
         executed_total += hm.executed;
         canonical_total += rec.count;
@@ -650,30 +742,20 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
         if (hm.cancelled) { status = fail(MINDIST_E_CANCELLED, "cancelled after the chunk budget"); break; }
         if (cut) { exited = 1; break; }
         if (c->term_per_level && j == ng - 1) L = L_after_pair(j, w, L);
+        int j2 = j, w2 = w;
+        advance(j2, w2);
         if (w2 > k) break;
-        if (!have_next) {
-            if (w2 > MINDIST_MAX_LEVEL || B(k, w2) >= (1ull << 63)) {
-                status = fail(MINDIST_E_LIMIT, "pair (" + std::to_string(j2) + "," + std::to_string(w2) +
-                                                   ") exceeds the rank-space limit");
-                break;
-            }
-            cur.j = j2;         // right-major order: planned at its launch
-            cur.w = w2;
-            cur_launched = false;
-            continue;
-        }
-        buf ^= 1;
-        std::swap(cur, nxt);
-        cur_launched = next_launched;
     }
-    // a pair launched ahead of a stop still runs (it finds nothing below U
-    // and leaves at once): return with the stream idle
+    // pairs launched ahead of a stop still run (they find nothing below U
+    // and leave at once): return with the stream idle
     HIPCHK(hipStreamSynchronize(c->stream));
     if (c->profile && pairs) {
         for (int t = 0; t < pairs; ++t) {
-            float ms = 0;
+            float ms = 0, t_ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, c->pair_ev[2 * t], c->pair_ev[2 * t + 1]));
+            HIPCHK(hipEventElapsedTime(&t_ms, c->pair_ev[0], c->pair_ev[2 * t]));
             c->trace[t].ms = ms;
+            c->trace[t].t_start_ms = t_ms;
             enum_s += ms * 1e-3;
         }
     }
@@ -697,14 +779,11 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
         out->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         return status;
     }
-    // witness: slot[U_found] was written by the wave that lowered U_found to it
+    // witness: slot[U_found], written by the wave that lowered U_found to it,
+    // reaches the host in the mailbox of the last pair read
     if (U_found != kInf) {
-        Slot s;
-        HIPCHK(hipMemcpyAsync(c->h_read, state_slots(c->d_state) + U_found, sizeof(Slot),
-                              hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        std::memcpy(&s, c->h_read, sizeof(Slot));
-        if (s.pair >= (uint32_t)c->trace.size())
+        const Slot s = last_mail.witness;
+        if (last_mail.U_found != U_found || s.pair >= (uint32_t)c->trace.size())
             return fail(MINDIST_E_HIP, "witness slot holds an invalid pair index");
         const mindist_pair &pr = c->trace[s.pair];
         const std::vector<int> rows = witness_rows(k, pr.split_a, pr.split_b, pr.split_b2, s);

@@ -48,27 +48,15 @@ struct GroupEntry {
     uint32_t e;
 };
 
-struct PairStat {
-    uint32_t pair_min;     // least weight over the pair (kInf if none yet)
+// One wave's totals over the chunks it ran in a pair, written with plain
+// stores when the wave ends (no atomics on a shared line at the end of a
+// launch, when every wave finishes at about the same moment).
+struct WavePart {
+    uint32_t pair_min;     // least weight (kInf if none)
     uint32_t pad;
     uint64_t executed;     // combinations evaluated
     uint64_t wsum;         // sum of weights (verify mode)
-    uint64_t waves_done;   // waves of the pair's launch that have finished
-};
-
-// What the last wave of a pair's launch leaves in pinned host memory: the
-// run state and the pair's statistics, published by seq = pair + 1 once the
-// rest is written (the host waits on seq instead of synchronising and
-// copying back).
-struct PairMail {
-    uint32_t seq;
-    uint32_t U_found;
-    uint32_t exit_flag;
-    uint32_t cancelled;
-    uint32_t pair_min;
-    uint32_t pad;
-    uint64_t executed;
-    uint64_t wsum;
+    uint64_t t0, t1;       // device wall clock when the wave started and ended
 };
 
 struct Slot {              // witness of weight v: written once, by the wave
@@ -80,6 +68,29 @@ struct Slot {              // witness of weight v: written once, by the wave
     uint64_t pad2;
 };
 
+// What the publishing kernel behind a pair's launch leaves in pinned host
+// memory: the run state, the pair's statistics reduced over its waves and
+// the witness slot of the current U_found, published by seq = pair + 1 once
+// the rest is written (the host waits on seq instead of synchronising and
+// copying back).  Pair p uses mailbox p % kMailRing, so kMailRing - 1 pairs
+// can be launched ahead of the one being read.
+struct PairMail {
+    uint32_t seq;
+    uint32_t U_found;
+    uint32_t exit_flag;
+    uint32_t cancelled;
+    uint32_t pair_min;
+    uint32_t pad;
+    uint64_t executed;
+    uint64_t wsum;
+    uint64_t t_begin, t_end;   // device wall clock: first wave start, last wave end
+    uint64_t pad2;
+    Slot witness;          // slot[U_found] (unset while U_found = kInf)
+};
+constexpr int kMailRing = 8;
+constexpr uint32_t kMaxSlot = 512;    // witness slots 0..kMaxSlot, one per weight (n <= 512)
+
+
 struct DevState {
     uint32_t U_found;      // least weight found so far in the run (kInf = none)
     uint32_t exit_flag;    // set when U_found <= the bound before the pair
@@ -87,24 +98,22 @@ struct DevState {
     uint32_t pad;
     uint64_t claimed;      // chunks claimed in the run (for cancel_after)
     uint64_t pad2;
-    // followed by Slot slots[513], PairStat pairs[max_pairs] and the chunk
-    // dispensers: kCounters counters per pair, each on its own 128-byte line
+    // followed by Slot slots[kMaxSlot + 1] and the chunk dispensers: kCounters
+    // counters per pair, each on its own 128-byte line
 };
 
 constexpr int kCounters = 8;         // interleaved chunk dispensers per pair
 constexpr int kCounterStride = 16;   // uint64 words between two counters (128 B)
 
 MD_HD inline size_t state_bytes(int max_pairs) {
-    return sizeof(DevState) + sizeof(Slot) * 513 + sizeof(PairStat) * (size_t)max_pairs +
+    return sizeof(DevState) + sizeof(Slot) * (kMaxSlot + 1) +
            sizeof(uint64_t) * kCounters * kCounterStride * (size_t)max_pairs;
 }
 MD_HD inline Slot *state_slots(DevState *s) { return reinterpret_cast<Slot *>(s + 1); }
-MD_HD inline PairStat *state_pairs(DevState *s) {
-    return reinterpret_cast<PairStat *>(reinterpret_cast<Slot *>(s + 1) + 513);
-}
 // counter q of pair p
 MD_HD inline uint64_t *state_counter(DevState *s, int max_pairs, int p, int q) {
-    uint64_t *base = reinterpret_cast<uint64_t *>(state_pairs(s) + max_pairs);
+    (void)max_pairs;
+    uint64_t *base = reinterpret_cast<uint64_t *>(state_slots(s) + kMaxSlot + 1);
     return base + ((size_t)p * kCounters + q) * kCounterStride;
 }
 
@@ -134,8 +143,10 @@ struct PairArgs {
     uint32_t order;            // 0: chunk = (left tile, right tile) left-major, 1: right-major
     uint32_t n_rt;             // right tiles (order = 1)
     uint32_t counters;         // chunk dispensers in use (1 or kCounters)
-    uint32_t waves;            // waves of this launch (grid blocks x 4)
-    PairMail *mail;            // pinned host mailbox, or nullptr
+    uint32_t waves;            // waves of this launch (grid blocks x 4); wave v
+                               // runs chunk v first, the dispensers hand out
+                               // chunks waves, waves + 1, ...
+    WavePart *parts;           // waves entries: each wave's totals
 };
 
 // Saved sums of r-subsets: entry i is the sum of the rows of colex_unrank_r(i)
@@ -158,6 +169,10 @@ int launch_init_state(DevState *st, int max_pairs, void *stream);
 int launch_build_table(const TableArgs &ta, int D, void *stream);
 // items: lane items per chunk (2 or 4)
 int launch_enum_pair(const PairArgs &pa, int D, int items, int verify, int blocks, void *stream);
+// one block: reduce the waves' totals of pair `pair`, read the run state and
+// publish both to the mailbox (launched right behind the pair's kernel)
+int launch_publish_pair(const WavePart *parts, uint32_t waves, DevState *st, PairMail *mail,
+                        uint32_t pair, void *stream);
 int max_dwords();
 int launch_peak(const uint32_t *tab, uint32_t steps, uint32_t *out, int D, int blocks, void *stream);
 

@@ -12,24 +12,26 @@ namespace md {
 
 template <int D, int B, bool VERIFY>
 __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
+    const uint64_t t_begin = wall_clock64();
     const int lane = threadIdx.x & 63;
-    PairStat *ps = state_pairs(p.st) + p.pair;
     Slot *slots = state_slots(p.st);
     int gi = 0;
     // per-lane totals over all chunks of this wave, flushed once at the end
     // (per-chunk atomics on the pair record serialise in L2)
     uint32_t run_min = kInf;
     uint64_t run_cnt = 0, run_ws = 0;
-    // One chunk per claim, so the waves running at the same moment hold
-    // neighbouring chunks.  Chunk c is handed out by counter c % nq; a wave
-    // starts on counter (wave id % nq) and moves on, for good, once that
-    // counter is past the end.  Counters on separate lines take nq times
-    // the claim rate of one.
+    // Wave v runs chunk v first, without a claim; the chunks past the
+    // launch's waves go one per claim, so the waves running at the same
+    // moment hold neighbouring chunks.  Chunk waves + c is handed out by
+    // counter c % nq; a wave starts on counter (v % nq) and moves on, for
+    // good, once that counter is past the end.  Counters on separate lines
+    // take nq times the claim rate of one.  A pair with no more chunks than
+    // waves makes no claim at all.
     const uint32_t nq = p.counters;
     // (readfirstlane: the wave index is uniform, and everything derived from
     // the claimed chunk must stay in scalar registers for the table loads)
-    const uint32_t home =
-        uni32((uint32_t)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % nq));
+    const uint32_t wave = uni32((uint32_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const uint32_t home = wave % nq;
     // binomial columns C(x, a) and C(x, b), x <= k, for the per-lane lookups
     __shared__ uint64_t colA[kBinomX], colB[kBinomX];
     for (int x = threadIdx.x; x <= p.k; x += blockDim.x) {
@@ -40,25 +42,33 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
     const ItemSrc src{p.rows, p.table, p.ltable, p.binom, colA, colB, 1, 1,
                       p.n_items, p.k, p.a, p.b, p.b2, p.table2, p.cnt2};
     uint32_t rt_cur = 0;
-    uint32_t moved = 0;
+    uint32_t moved = (uint64_t)p.waves >= p.total_chunks ? nq : 0u;
+    bool first = true;
     uint32_t U_seen = kInf;
     for (;;) {
         uint64_t c = 0;
         bool have = false;
-        while (moved < nq) {
+        if (first) {
+            first = false;
+            c = wave;
+            have = c < p.total_chunks;
+        }
+        while (!have && moved < nq) {
             const uint32_t q = (home + moved) % nq;
             uint64_t idx = 0;
             if (lane == 0)
                 idx = atomicAdd((unsigned long long *)state_counter(p.st, p.max_pairs, p.pair, q), 1ull);
             idx = uni64((uint64_t)__shfl((long long)idx, 0));
-            c = idx * nq + q;
+            c = (uint64_t)p.waves + idx * nq + q;
             if (c < p.total_chunks) { have = true; break; }
             ++moved;
         }
         if (!have) break;
-        if (p.midpair_exit &&
-            __hip_atomic_load(&p.st->exit_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            break;
+        U_seen = uni32(__hip_atomic_load(&p.st->U_found, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT));
+        // U at or below the bound before this pair: cut short (a wave of this
+        // pair got there), or a pair launched ahead of a run that has ended
+        if (p.midpair_exit && U_seen <= p.L_prev) break;
         if (p.cancel_after) {
             uint64_t cl = 0;
             if (lane == 0) cl = atomicAdd((unsigned long long *)&p.st->claimed, 1ull);
@@ -68,8 +78,6 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
                 break;
             }
         }
-        U_seen = uni32(__hip_atomic_load(&p.st->U_found, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT));
         ChunkGeo g;
         if (p.order == 0) {
             // left-major: groups of left tiles by the largest element of their
@@ -135,30 +143,66 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
     const uint64_t wcnt = wave_sum_u64(run_cnt);
     const uint64_t wws = VERIFY ? wave_sum_u64(run_ws) : 0ull;
     if (lane == 0) {
-        if (wcnt) atomicAdd((unsigned long long *)&ps->executed, (unsigned long long)wcnt);
-        if (VERIFY && wcnt)
-            atomicAdd((unsigned long long *)&ps->wsum,
-                      (unsigned long long)(wws + (uint64_t)p.offset * wcnt));
-        if (wmin != kInf) atomicMin(&ps->pair_min, wmin + p.offset);
+        WavePart *wp = p.parts + wave;
+        wp->pair_min = wmin == kInf ? kInf : wmin + p.offset;
+        wp->executed = wcnt;
+        wp->wsum = VERIFY ? wws + (uint64_t)p.offset * wcnt : 0ull;
+        wp->t0 = t_begin;
+        wp->t1 = wall_clock64();
     }
-    if (p.mail) {
-        // the last wave to finish publishes the pair to the host
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        uint64_t prev = 0;
-        if (lane == 0) prev = atomicAdd((unsigned long long *)&ps->waves_done, 1ull);
-        prev = uni64((uint64_t)__shfl((long long)prev, 0));
-        if (prev + 1 == p.waves && lane == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            PairMail *m = p.mail;
-            m->U_found = __hip_atomic_load(&p.st->U_found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            m->exit_flag = __hip_atomic_load(&p.st->exit_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            m->cancelled = __hip_atomic_load(&p.st->cancelled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            m->pair_min = __hip_atomic_load(&ps->pair_min, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            m->executed = __hip_atomic_load(&ps->executed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            m->wsum = __hip_atomic_load(&ps->wsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence_system();
-            __hip_atomic_store(&m->seq, p.pair + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Runs right behind a pair's launch (stream order makes every wave's totals
+// and the run state visible): one block reduces the waves' totals and
+// publishes them with the run state to the pinned mailbox, seq last.
+__global__ __launch_bounds__(1024) void publish_pair_kernel(const WavePart *parts, uint32_t waves,
+                                                            DevState *st, PairMail *m,
+                                                            uint32_t pair) {
+    uint32_t mn = kInf;
+    uint64_t ex = 0, ws = 0, t0 = ~0ull, t1 = 0;
+    for (uint32_t v = threadIdx.x; v < waves; v += blockDim.x) {
+        mn = min(mn, parts[v].pair_min);
+        ex += parts[v].executed;
+        ws += parts[v].wsum;
+        t0 = min(t0, parts[v].t0);
+        t1 = max(t1, parts[v].t1);
+    }
+    mn = wave_min_u32(mn);
+    ex = wave_sum_u64(ex);
+    ws = wave_sum_u64(ws);
+    t0 = wave_min_u64(t0);
+    t1 = wave_max_u64(t1);
+    __shared__ uint32_t s_mn[16];
+    __shared__ uint64_t s_ex[16], s_ws[16], s_t0[16], s_t1[16];
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_mn[wv] = mn;
+        s_ex[wv] = ex;
+        s_ws[wv] = ws;
+        s_t0[wv] = t0;
+        s_t1[wv] = t1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+            mn = min(mn, s_mn[i]);
+            ex += s_ex[i];
+            ws += s_ws[i];
+            t0 = min(t0, s_t0[i]);
+            t1 = max(t1, s_t1[i]);
         }
+        m->t_begin = t0;
+        m->t_end = t1;
+        const uint32_t U = __hip_atomic_load(&st->U_found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        m->U_found = U;
+        if (U <= kMaxSlot) m->witness = state_slots(st)[U];
+        m->exit_flag = __hip_atomic_load(&st->exit_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        m->cancelled = __hip_atomic_load(&st->cancelled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        m->pair_min = mn;
+        m->executed = ex;
+        m->wsum = ws;
+        __threadfence_system();
+        __hip_atomic_store(&m->seq, pair + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -244,13 +288,6 @@ __global__ void init_state_kernel(DevState *st, int max_pairs) {
         st->cancelled = 0;
         st->claimed = 0;
     }
-    PairStat *ps = state_pairs(st);
-    for (int p = tid; p < max_pairs; p += gridDim.x * blockDim.x) {
-        ps[p].pair_min = kInf;
-        ps[p].executed = 0;
-        ps[p].wsum = 0;
-        ps[p].waves_done = 0;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -295,6 +332,13 @@ template <int D>
 static void enum_launch(const PairArgs &pa, int items, int verify, int blocks, hipStream_t s) {
     if (items == 4) enum_launch_b<D, 4>(pa, verify, blocks, s);
     else enum_launch_b<D, 2>(pa, verify, blocks, s);
+}
+
+int launch_publish_pair(const WavePart *parts, uint32_t waves, DevState *st, PairMail *mail,
+                        uint32_t pair, void *stream) {
+    hipLaunchKernelGGL(publish_pair_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, parts,
+                       waves, st, mail, pair);
+    return check(hipGetLastError());
 }
 
 int launch_enum_pair(const PairArgs &pa, int D, int items, int verify, int blocks, void *stream) {

@@ -3,6 +3,7 @@
 
 #include <map>
 #include <mutex>
+#include <string>
 #include <unordered_map>
 #include <vector>
 
@@ -12,6 +13,7 @@ namespace md {
 namespace {
 
 std::mutex g_mu;
+std::mutex &g_const_mu() { static std::mutex m; return m; }
 
 // sizes are rounded so repeated requests of nearby sizes share blocks
 size_t round_size(size_t b) {
@@ -33,6 +35,7 @@ size_t g_dev_cached = 0;
 std::vector<hipStream_t> g_streams[64];
 std::vector<hipEvent_t> g_events[64];
 const uint64_t *g_binom[64] = {nullptr};
+std::map<std::pair<int, std::string>, void *> g_const;   // (device, key) -> device copy
 
 int cur_dev() {
     int d = 0;
@@ -224,6 +227,25 @@ const uint64_t *device_binom_from(const uint64_t *host_table) {
     }
     g_binom[dev] = static_cast<const uint64_t *>(p);
     return g_binom[dev];
+}
+
+const void *device_const(const void *key, size_t key_bytes, const void *host, size_t bytes) {
+    const int dev = cur_dev();
+    const std::pair<int, std::string> k(dev, std::string(static_cast<const char *>(key), key_bytes));
+    std::lock_guard<std::mutex> lk(g_const_mu());
+    auto it = g_const.find(k);
+    if (it != g_const.end()) return it->second;
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) return nullptr;
+    // synchronous: once this returns, the copy is visible to kernels on
+    // every stream (the streams handed out here are non-blocking, so this
+    // does not wait for their work)
+    if (bytes && hipMemcpy(p, host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p);
+        return nullptr;
+    }
+    g_const.emplace(k, p);
+    return p;
 }
 
 size_t dev_cached_bytes() {

@@ -29,6 +29,11 @@ void event_put(hipEvent_t e);
 // the binomial table C(x, t), x < kBinomX, t < kBinomT, on the current
 // device (copied from host_table on the first call per device)
 const uint64_t *device_binom_from(const uint64_t *host_table);
+// a small immutable device array identified by `key` (key_bytes bytes): the
+// first call per device and key copies `bytes` bytes from `host` and waits
+// for the copy; later calls return the same device address.  Held until the
+// process ends.  nullptr if allocation or copy fails.
+const void *device_const(const void *key, size_t key_bytes, const void *host, size_t bytes);
 // bytes currently held in the device cache (not handed out)
 size_t dev_cached_bytes();
 

@@ -185,6 +185,26 @@ def test_determinism_repeated_runs():
             check_witness(G, w.n, w.k, r)
 
 
+def test_device_clock_pair_times_agree_with_events():
+    """Every pair reports its kernel's span on the device clock (first wave
+    start to last wave end); it is positive and no longer than the HIP-event
+    time around the same launch, which adds only the dispatch."""
+    w = WORKLOADS["rand150x75"]
+    G = w.matrix()
+    say("rand150x75 device clock vs events")
+    with md.MinDist(G, w.n, w.k, profile=1) as m:
+        m.run()
+        r = m.run()
+    big = 0
+    for p in r["pairs"]:
+        assert p["dev_ms"] > 0, p
+        assert p["dev_ms"] <= p["ms"] + 0.005, p
+        if p["ms"] > 1.0:
+            big += 1
+            assert p["dev_ms"] >= 0.95 * p["ms"], p
+    assert big >= 1
+
+
 # ---------------------------------------------------------------- random sweep
 def estimated_work(n, k):
     """Rough oracle work of a random [n,k] code: d from the expected weight

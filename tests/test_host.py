@@ -92,3 +92,35 @@ def test_bound_schedule_matches_printed_formula_at_level_ends():
 def test_bound_rejects_bad_queries():
     with pytest.raises(md.MindistError):
         md.bound_after(40, 6, 15, 1, 7, 3)
+
+
+def test_binding_structs_match_the_c_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    the C compiler gives the header's struct (a mismatch would corrupt every
+    result silently)."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not found")
+    pairs = [("mindist_result", md.Result), ("mindist_pair", md.Pair),
+             ("mindist_batch_opts", md.BatchOpts), ("mindist_server_opts", md.ServerOpts),
+             ("mindist_server_result", md.ServerResult), ("mindist_server_stats", md.ServerStats)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mindist.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "abi"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, f, v = line.split()
+        got[(cname, f)] = int(v)
+    for cname, py in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -23,7 +23,13 @@ constexpr int kBatchMaxSets = 32;     // information sets per code
 constexpr int kBatchMaxB = 6;         // right tables b = 0..6 per set
 constexpr int kBatchMaxPairs = 256;   // jobs per code (table job + pairs)
 constexpr int kBatchMaxD = 8;         // 32-bit words carried per row (n <= 256)
-constexpr int kBatchItems = 2;        // left subsets per lane
+// left subsets per lane: 4 up to 4 words per codeword (each scalar table
+// line then serves 256 codewords of the wave), 2 above (the 128-register
+// budget of the persistent kernel holds 4 x D words of left sums only up to
+// D = 4)
+constexpr int kBatchItemsMaxD4 = 4;
+constexpr int kBatchItemsWide = 2;
+MD_HD constexpr int batch_items(int D) { return D <= 4 ? kBatchItemsMaxD4 : kBatchItemsWide; }
 constexpr int kTableChunk = 4096;     // table entries per table-job chunk
 // tables of set j: right tables b = 0..bcap (shift 0) at t = j*kTabsPerSet + b,
 // outer tables b1 = 1..bcap over rows [0, k-bcap) (shift bcap, with inner

@@ -132,7 +132,7 @@ __device__ __noinline__ void finish_code(const BatchArgs &A, int c, int32_t stat
 }
 
 // Open pair (j, w) as job p of code c (whole wave).  Mirrors the host's
-// plan: b = min(w/2, bcap_j), a = w - b, left tiles of 64*kBatchItems
+// plan: b = min(w/2, bcap_j), a = w - b, left tiles of 64*batch_items(D_j)
 // subsets grouped by the largest element e of their first subset.
 __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32_t L_before) {
     BatchCode *cs = &A.codes[c];
@@ -143,7 +143,7 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
     // bcap, the shift the outer tables were built with
     int a, b, b2;
     split_rows(k, w, set.bcap, true, [&](int x, int r) { return binom(A.binom, x, r); }, a, b, b2);
-    const uint64_t TB = 64ull * kBatchItems;
+    const uint64_t TB = 64ull * batch_items(set.D);
     const uint64_t n_items = binom(A.binom, k - b - b2, a);
     const uint64_t tiles = (n_items + TB - 1) / TB;
     uint32_t T;
@@ -471,10 +471,11 @@ __device__ __forceinline__ void pair_chunk(const BatchArgs &A, JobView &v, uint6
                       nullptr, A.binom, A.binom + a, A.binom + b, kBinomT, kBinomT,
                       uni64(v.n_items), (int)uni32((uint32_t)v.k), a, b, (int)uni32((uint32_t)v.b2),
                       (const uint32_t *)uni64((uint64_t)v.tab2), (const uint32_t *)uni64((uint64_t)v.cnt2)};
-    uint32_t L[kBatchItems][D], nr[kBatchItems], lmin, ws;
+    constexpr int BI = batch_items(D);
+    uint32_t L[BI][D], nr[BI], lmin, ws;
     uint64_t cnt;
-    if (v.b2) run_chunk3<D, kBatchItems, false>(src, g, L, nr, lmin, cnt, ws);
-    else run_chunk<D, kBatchItems, false>(src, g, L, nr, lmin, cnt, ws);
+    if (v.b2) run_chunk3<D, BI, false>(src, g, L, nr, lmin, cnt, ws);
+    else run_chunk<D, BI, false>(src, g, L, nr, lmin, cnt, ws);
     const uint32_t wmin = uni32(wave_min_u32(lmin));
     exec += uni64(wave_sum_u64(cnt));
     if (wmin < wmin_out) wmin_out = wmin;
@@ -488,8 +489,8 @@ __device__ __forceinline__ void pair_chunk(const BatchArgs &A, JobView &v, uint6
         uint32_t hit_i, hit_i2 = 0;
         uint64_t hit_rho;
         const int first =
-            v.b2 ? find_witness3<D, kBatchItems>(src, g, L, nr, wmin, hit_i, hit_i2, hit_rho)
-                 : find_witness<D, kBatchItems>(src, g, L, nr, wmin, hit_i, hit_rho);
+            v.b2 ? find_witness3<D, BI>(src, g, L, nr, wmin, hit_i, hit_i2, hit_rho)
+                 : find_witness<D, BI>(src, g, L, nr, wmin, hit_i, hit_rho);
         if (lane == first) {
             cs->slots[val].pair = (uint32_t)v.p;
             cs->slots[val].i = hit_i;

@@ -216,10 +216,12 @@ def batch_leg(codes_total: int, stride: int):
             "codewords_per_s_kernel": info["executed_total"] / info["seconds_kernel"]}
 
 
-def serving_leg(rate: float, seconds: float, cap: float, max_requests: int = 4000):
+def serving_leg(rate: float, seconds: float, cap: float, max_requests: int = 4000, engine: int = 0):
     """Open-loop Poisson arrivals of the serving stream at `rate` per second
     for about `seconds`; requests whose estimated work exceeds `cap`
-    codewords are left out of the stream (counted in the report)."""
+    codewords are left out of the stream (counted in the report).  engine 0:
+    worker threads running the single-code path side by side; engine 1: the
+    persistent multi-code kernel in epochs."""
     import numpy as np
     import paper_1603_06757_amd as md
     from paper_1603_06757_amd.gen import serving_request, poisson_arrivals
@@ -233,7 +235,7 @@ def serving_leg(rate: float, seconds: float, cap: float, max_requests: int = 400
             continue
         kept.append((n, k, G))
     arr = poisson_arrivals(len(kept), rate)
-    with md.Server() as srv:
+    with md.Server(engine=engine) as srv:
         t_start = time.perf_counter()
         for tag, (t, (n, k, G)) in enumerate(zip(arr, kept)):
             dt = t - (time.perf_counter() - t_start)
@@ -253,7 +255,7 @@ def serving_leg(rate: float, seconds: float, cap: float, max_requests: int = 400
         st = srv.stats()
     lat = np.array([r["t_done"] - r["t_submit"] for r in got]) if got else np.zeros(1)
     ok = sum(1 for r in got if r["status"] == 0)
-    return {"rate_per_s": rate, "requests": len(kept), "completed_ok": ok,
+    return {"engine": engine, "rate_per_s": rate, "requests": len(kept), "completed_ok": ok,
             "skipped_over_cap": skipped, "work_cap_codewords": cap,
             "offered_s": float(arr[-1]), "wall_s": t_end - t_start,
             "codes_per_s": len(got) / (t_end - t_start),
@@ -304,9 +306,12 @@ def main():
         copy_probe(a.copy_probe_mib)
         return
     if a.serving_sweep:
-        for rate in (10, 30, 100, 300, 1000):
-            print(json.dumps({"serving": serving_leg(rate, 4.0 if rate >= 100 else 10.0,
-                                                     a.serving_cap)}), flush=True)
+        for engine in (0, 1):
+            for rate in (10, 30, 100, 300, 1000, 3000):
+                if engine == 1 and rate > 1000:
+                    continue           # already saturated at 1000/s
+                print(json.dumps({"serving": serving_leg(rate, 4.0 if rate >= 100 else 10.0,
+                                                         a.serving_cap, engine=engine)}), flush=True)
         return
     w, results, dt, events = single_code_leg(a.steps, a.warmup)
     ref = results[0]

@@ -267,7 +267,8 @@ int mindist_run_batch(const uint64_t *const *G, const int *n, const int *k, int 
 typedef struct mindist_server mindist_server;
 
 typedef struct mindist_server_opts {
-    int32_t max_active;       /* code slots resident on the device (0 = 256) */
+    int32_t max_active;       /* codes running at once: engine 0, worker threads (0 = 4);
+                                 engine 1, code slots resident on the device (0 = 256) */
     int32_t blocks_per_cu;    /* resident workgroups per CU (0 = 4) */
     int64_t device_bytes;     /* device memory for resident codes' rows, saved tables and
                                  witness slots, a code is admitted only when its share
@@ -278,7 +279,13 @@ typedef struct mindist_server_opts {
     int32_t jobs_per_code;    /* job records per slot (0 = 96); a code needing more ends
                                  with MINDIST_E_LIMIT */
     int32_t chunks_per_visit; /* as in mindist_batch_opts (0 = 4) */
-    int32_t reserved0;
+    int32_t engine;           /* 0 (default): each admitted code runs the single-code path
+                                 (mindist_create / run / destroy) on its own stream in one of
+                                 max_active worker threads; the device runs the kernels of
+                                 the codes in flight side by side.  1: the persistent
+                                 multi-code kernel in epochs (device_bytes, epoch_min_ms,
+                                 jobs_per_code, blocks_per_cu and chunks_per_visit apply to
+                                 this engine only) */
 } mindist_server_opts;
 
 #define MINDIST_SERVER_MAX_PAIRS 256
@@ -294,9 +301,10 @@ typedef struct mindist_server_result {
 
 typedef struct mindist_server_stats {
     uint64_t submitted, admitted, completed;
-    uint64_t epochs;          /* launches of the persistent kernel */
-    double   seconds_kernel;  /* summed launch time (HIP events) */
-    int32_t  resident;        /* codes on the device now */
+    uint64_t epochs;          /* launches of the persistent kernel (engine 1) */
+    double   seconds_kernel;  /* engine 1: summed launch time (HIP events); engine 0: summed
+                                 enumeration kernel time of the finished codes (device clock) */
+    int32_t  resident;        /* codes on the device (engine 1) or being run (engine 0) now */
     int32_t  pending;         /* codes waiting for admission now */
 } mindist_server_stats;
 
@@ -317,8 +325,9 @@ int mindist_server_wait(mindist_server *s, double timeout_s);
 /* seconds since the server started (the clock of t_submit/t_admit/t_done) */
 double mindist_server_clock(const mindist_server *s);
 int mindist_server_stats_get(const mindist_server *s, mindist_server_stats *out);
-/* Stop the kernel and the manager thread; unfinished codes are dropped.
- * NULL-safe. */
+/* Engine 1: stop the kernel and the manager thread; unfinished codes are
+ * dropped.  Engine 0: waiting codes are dropped, codes being run finish
+ * first, then the workers end.  NULL-safe. */
 void mindist_server_destroy(mindist_server *s);
 
 #ifdef __cplusplus

@@ -90,7 +90,7 @@ class ServerOpts(C.Structure):
     _fields_ = [("max_active", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("device_bytes", C.c_int64), ("epoch_min_ms", C.c_double),
                 ("table_kib", C.c_int32), ("jobs_per_code", C.c_int32),
-                ("chunks_per_visit", C.c_int32), ("reserved0", C.c_int32)]
+                ("chunks_per_visit", C.c_int32), ("engine", C.c_int32)]
 
 
 class ServerResult(C.Structure):
@@ -306,13 +306,15 @@ class Server:
     """Continuous batching of arriving codes on the current GPU (the
     mindist_server_* entry points).  submit() returns at once; poll()
     returns finished results as dicts with the request's tag, its result,
-    its visited pairs and t_submit / t_admit / t_done on the server clock."""
+    its visited pairs and t_submit / t_admit / t_done on the server clock.
+    engine 0: worker threads running the single-code path side by side;
+    engine 1: the persistent multi-code kernel in epochs."""
 
     def __init__(self, max_active: int = 0, blocks_per_cu: int = 0, device_bytes: int = 0,
                  epoch_min_ms: float = 0.0, table_kib: int = 0, jobs_per_code: int = 0,
-                 chunks_per_visit: int = 0):
+                 chunks_per_visit: int = 0, engine: int = 0):
         o = ServerOpts(max_active, blocks_per_cu, device_bytes, epoch_min_ms, table_kib,
-                       jobs_per_code, chunks_per_visit, 0)
+                       jobs_per_code, chunks_per_visit, engine)
         h = C.c_void_p()
         _check(lib().mindist_server_create(C.byref(o), C.byref(h)))
         self._h = h

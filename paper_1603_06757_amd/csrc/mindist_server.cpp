@@ -1,6 +1,15 @@
 // mindist_server.cpp -- continuous batching of arriving codes on one GPU.
 //
-// The persistent multi-code kernel runs in "epochs": one launch keeps every
+// Two engines serve the same queue.
+//
+// Engine 0 (default): worker threads, each taking the next waiting code and
+// running the single-code path on it (context, pair launches with the next
+// pairs queued ahead, mailbox reads) on its own stream.  The device runs the
+// kernels of the codes in flight side by side: short pairs of one code fill
+// the compute units another code's short pairs leave idle, and a code's
+// latency is that of the single-code path.
+//
+// Engine 1: the persistent multi-code kernel runs in "epochs": one launch keeps every
 // resident code moving (pair after pair, Algorithm 1's control on the
 // device) until the manager thread asks it to stop because codes are
 // waiting and room has freed up.  Waves finish the chunk they hold and add
@@ -82,7 +91,9 @@ private:
 
 struct Request {
     uint64_t tag = 0;
-    HostCode hc;
+    HostCode hc;                 // engine 1
+    std::vector<uint64_t> G;     // engine 0: the caller's matrix
+    int n = 0, k = 0;
     double t_submit = 0, t_admit = 0;
     size_t bytes = 0;            // rows + tables + witness slots
 };
@@ -129,6 +140,7 @@ struct mindist_server {
     uint64_t next_seq = 1;
     double wall_hz = 1e8;                   // device wall-clock rate
     std::thread mgr;
+    std::vector<std::thread> workers;       // engine 0
     std::string fatal;                      // first device error seen by the manager
 
     double clock() const {
@@ -345,6 +357,54 @@ void manager(mindist_server *S) {
     }
 }
 
+// Engine 0: one worker thread.  Codes are taken in submission order; the
+// single-code path allocates nothing per code after warm-up (process-wide
+// caches of device memory, streams and events).
+void direct_worker(mindist_server *S) {
+    (void)hipSetDevice(S->device);
+    const int table_mib = S->o.table_kib > 0 ? std::max(1, S->o.table_kib / 1024) : 0;
+    for (;;) {
+        std::unique_ptr<Request> req;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait(lk, [&] { return S->quit || !S->pending.empty(); });
+            if (S->quit) return;
+            req = std::move(S->pending.front());
+            S->pending.pop_front();
+            req->t_admit = S->clock();
+            ++S->resident;
+            ++S->st.admitted;
+        }
+        auto res = std::make_unique<mindist_server_result>();
+        std::memset(res.get(), 0, sizeof(*res));
+        res->tag = req->tag;
+        res->t_submit = req->t_submit;
+        res->t_admit = req->t_admit;
+        mindist_ctx *ctx = nullptr;
+        int status = mindist_create(req->G.data(), req->n, req->k, &ctx);
+        if (status == MINDIST_OK && table_mib) status = mindist_set_option(ctx, MINDIST_OPT_TABLE_MIB, table_mib);
+        if (status == MINDIST_OK) status = mindist_run(ctx, &res->result);
+        double kernel_s = 0;
+        if (ctx) {
+            int np = 0;
+            if (status == MINDIST_OK &&
+                mindist_get_pairs(ctx, res->pairs, MINDIST_SERVER_MAX_PAIRS, &np) == MINDIST_OK)
+                res->n_pairs = std::min(np, MINDIST_SERVER_MAX_PAIRS);
+            for (int t = 0; t < res->n_pairs; ++t) kernel_s += res->pairs[t].dev_ms * 1e-3;
+            mindist_destroy(ctx);
+        }
+        res->status = status;
+        if (status != MINDIST_OK && res->result.d >= 0) res->result.d = status;
+        res->t_done = S->clock();
+        std::lock_guard<std::mutex> lk(S->mu);
+        --S->resident;
+        ++S->st.completed;
+        S->st.seconds_kernel += kernel_s;
+        S->done.push_back(std::move(res));
+        S->cv.notify_all();
+    }
+}
+
 void release(mindist_server *S) {
     if (S->stream) (void)hipStreamSynchronize(S->stream);
     dev_free(S->d_codes);
@@ -371,6 +431,26 @@ extern "C" int mindist_server_create(const mindist_server_opts *opts, mindist_se
     *out = nullptr;
     auto S = std::make_unique<mindist_server>();
     if (opts) S->o = *opts;
+    if (S->o.engine != 0 && S->o.engine != 1) return fail(MINDIST_E_ARG, "engine must be 0 or 1");
+    if (S->o.engine == 0) {
+        const int workers = S->o.max_active > 0 ? S->o.max_active : 4;
+        if (workers > 256) return fail(MINDIST_E_ARG, "max_active too large for engine 0 (at most 256 workers)");
+        if (hipGetDevice(&S->device) != hipSuccess) return fail(MINDIST_E_HIP, "no HIP device");
+        // warm the process-wide caches the first codes would otherwise pay
+        // for: one stream per worker, the binomial table
+        {
+            std::vector<hipStream_t> ss;
+            for (int t = 0; t < workers; ++t) ss.push_back(stream_get());
+            for (hipStream_t st : ss)
+                if (st) stream_put(st);
+            if (!device_binom_from(BN().t.data())) return fail(MINDIST_E_NOMEM, "binomial table upload failed");
+        }
+        S->t0 = std::chrono::steady_clock::now();
+        mindist_server *raw = S.get();
+        for (int t = 0; t < workers; ++t) raw->workers.emplace_back(direct_worker, raw);
+        *out = S.release();
+        return MINDIST_OK;
+    }
     const int slots = S->o.max_active > 0 ? S->o.max_active : 256;
     if (slots > 65536) return fail(MINDIST_E_ARG, "max_active too large");
     const size_t pool_bytes = S->o.device_bytes > 0 ? (size_t)S->o.device_bytes : (size_t)8 << 30;
@@ -430,6 +510,21 @@ extern "C" int mindist_server_submit(mindist_server *S, const uint64_t *G, int n
     auto r = std::make_unique<Request>();
     r->tag = tag;
     r->t_submit = S->clock();
+    if (S->o.engine == 0) {
+        // validate here (the caller learns of a bad matrix at once); the
+        // worker plans again inside mindist_create
+        int e = mindist_plan(G, n, k, nullptr, nullptr, nullptr, nullptr);
+        if (e) return e;
+        r->n = n;
+        r->k = k;
+        r->G.assign(G, G + (size_t)k * ((n + 63) / 64));
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->quit) return fail(MINDIST_E_STATE, "server is shutting down");
+        S->pending.push_back(std::move(r));
+        ++S->st.submitted;
+        S->cv.notify_all();
+        return MINDIST_OK;
+    }
     const uint64_t table_cap = (uint64_t)(S->o.table_kib > 0 ? S->o.table_kib : 65536) << 10;
     int e = prepare_code(G, n, k, table_cap, r->hc);
     if (e) return e;
@@ -493,6 +588,8 @@ extern "C" void mindist_server_destroy(mindist_server *S) {
     }
     if (S->h_stop) __atomic_store_n(S->h_stop, 1u, __ATOMIC_RELEASE);
     if (S->mgr.joinable()) S->mgr.join();
+    for (auto &t : S->workers)
+        if (t.joinable()) t.join();   // a code being run finishes first
     release(S);
     delete S;
 }

@@ -185,6 +185,23 @@ def test_determinism_repeated_runs():
             check_witness(G, w.n, w.k, r)
 
 
+def test_launch_ahead_off_and_on_match_the_oracle():
+    """Pairs launched ahead of their results (several while the queued work
+    is short) change nothing a run reports: the same visited pairs, bounds,
+    minima and counts as with no pair launched ahead, and as the oracle."""
+    for i in range(12):
+        n = 40 + 8 * (i % 5)
+        k = n // 2 - (i % 3)
+        G = random_generator(n, k, 700 + i)
+        say("launch ahead", i, n, k)
+        off, _ = run_and_compare(G, n, k, verify=False, speculate=0)
+        on, _ = run_and_compare(G, n, k, verify=False)
+        key = lambda r: [(p["j"], p["w"], p["pair_min"], p["L_before"]) for p in r["pairs"]]
+        assert key(off) == key(on)
+        # executed differs only where mid-pair exit cut the last pair
+        assert [p["executed"] for p in off["pairs"][:-1]] == [p["executed"] for p in on["pairs"][:-1]]
+
+
 def test_device_clock_pair_times_agree_with_events():
     """Every pair reports its kernel's span on the device clock (first wave
     start to last wave end); it is positive and no longer than the HIP-event

@@ -1,4 +1,6 @@
-"""GPU tests of the serving loop (continuous batching of arriving codes).
+"""GPU tests of the serving loop (continuous batching of arriving codes),
+under both engines: worker threads running the single-code path side by
+side (engine 0) and the persistent multi-code kernel in epochs (engine 1).
 
 Each request's result in the mix must be exactly its result alone (d, the
 visited pairs, their bounds, counts and minima), with a valid witness; codes
@@ -10,9 +12,9 @@ import numpy as np
 import pytest
 
 import paper_1603_06757_amd as md
-from paper_1603_06757_amd.gen import batch_code, serving_request
+from paper_1603_06757_amd.gen import WORKLOADS, serving_request
 from tests.test_gpu_batch import light_codes, same_as_single
-from tests.test_gpu_parity import check_witness, estimated_work
+from tests.test_gpu_parity import check_witness
 
 pytestmark = pytest.mark.gpu
 
@@ -32,10 +34,11 @@ def collect(srv, count, timeout=120.0):
     return got
 
 
-def test_server_results_equal_alone_with_staggered_arrivals():
+@pytest.mark.parametrize("engine", [0, 1])
+def test_server_results_equal_alone_with_staggered_arrivals(engine):
     cs = light_codes(48, seed=91)
-    say("server: 48 light codes in 4 waves of arrivals, 16 slots")
-    with md.Server(max_active=16) as srv:
+    say("server: 48 light codes in 4 waves of arrivals, 16 slots, engine", engine)
+    with md.Server(max_active=16, engine=engine) as srv:
         for i, (n, k, G) in enumerate(cs):
             srv.submit(G, n, k, tag=i)
             if i % 12 == 11:
@@ -52,23 +55,21 @@ def test_server_results_equal_alone_with_staggered_arrivals():
         assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
 
 
-def test_server_admits_while_others_run():
+@pytest.mark.parametrize("engine", [0, 1])
+def test_server_admits_while_others_run(engine):
     """A heavier code is submitted first; light codes submitted while it runs
     are admitted into free slots after it started and finish before it ends
     (their work overlaps on the device), and every result equals the code's
     result alone."""
-    heavy = None
-    for i in range(2000):
-        n, k, G = batch_code(i)
-        if 5e10 <= estimated_work(n, k) <= 3e11:
-            heavy = (n, k, G)
-            break
-    assert heavy is not None
+    # the seeded [255,40] code: 78 pairs, 13-16 ms alone, long enough for the
+    # light codes to arrive while it runs under either engine
+    w = WORKLOADS["rand255x40"]
+    heavy = (w.n, w.k, w.matrix())
     light = light_codes(24, seed=92)
-    say("server: heavy", heavy[:2], "then 24 light codes while it runs")
-    with md.Server(max_active=8) as srv:
+    say("server: heavy", heavy[:2], "then 24 light codes while it runs, engine", engine)
+    with md.Server(max_active=8, engine=engine) as srv:
         srv.submit(heavy[2], heavy[0], heavy[1], tag=1000)
-        time.sleep(0.002)
+        time.sleep(0.001)
         for i, (n, k, G) in enumerate(light):
             srv.submit(G, n, k, tag=i)
         got = collect(srv, len(light) + 1)
@@ -83,7 +84,8 @@ def test_server_admits_while_others_run():
     overlap = [h["t_admit"] < got[i]["t_admit"] and got[i]["t_done"] < h["t_done"]
                for i in range(len(light))]
     assert sum(overlap) >= 7, "no light code ran while the heavy one was on the device"
-    assert st["epochs"] >= 2
+    if engine == 1:
+        assert st["epochs"] >= 2
     for i, (n, k, G) in enumerate(light):
         assert got[i]["status"] == 0
         same_as_single(got[i], md.min_distance(G, n, k))
@@ -94,8 +96,8 @@ def test_server_admission_by_device_memory():
     still completes with the result it has alone."""
     cs = [serving_request(i) for i in range(40)]
     cs = [(n, k, G) for n, k, G in cs if n <= 120][:16]
-    say("server: 16 serving-stream codes, 24 MiB of device memory")
-    with md.Server(max_active=64, device_bytes=24 << 20) as srv:
+    say("server: 16 serving-stream codes, 24 MiB of device memory (engine 1)")
+    with md.Server(max_active=64, device_bytes=24 << 20, engine=1) as srv:
         for i, (n, k, G) in enumerate(cs):
             srv.submit(G, n, k, tag=i)
         got = collect(srv, len(cs), timeout=300)
@@ -104,8 +106,9 @@ def test_server_admission_by_device_memory():
         same_as_single(got[i], md.min_distance(G, n, k))
 
 
-def test_server_submit_errors_and_wait():
-    with md.Server(max_active=4) as srv:
+@pytest.mark.parametrize("engine", [0, 1])
+def test_server_submit_errors_and_wait(engine):
+    with md.Server(max_active=4, engine=engine) as srv:
         G = np.zeros((3, 1), dtype=np.uint64)
         G[0, 0] = 0b0011
         G[1, 0] = 0b0110

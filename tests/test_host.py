@@ -124,3 +124,10 @@ def test_binding_structs_match_the_c_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_server_rejects_an_unknown_engine():
+    """Argument checks of mindist_server_create run before any device call."""
+    with pytest.raises(md.MindistError) as e:
+        md.Server(engine=2)
+    assert e.value.code == -1

@@ -252,27 +252,39 @@ int mindist_run_batch(const uint64_t *const *G, const int *n, const int *k, int 
 
 /* ---- serving: continuous batching of arriving codes ---------------------
  *
- * A server owns one GPU stream and a set of code slots on the device.  A
- * manager thread keeps the persistent multi-code kernel of mindist_run_batch
- * running over the resident codes; codes submitted while it runs wait in a
- * queue and are admitted, in submission order among those that fit, as
- * slots and device memory free up: the launch is stopped (every wave
- * finishes the chunk it holds, so no work is lost), the new codes' slots are
- * written and the kernel is launched again over old and new codes together.
- * A code's information sets, Gamma_j, saved tables, bounds and job records
- * stay on the device from admission to completion; finished codes are read
- * back while the others keep running.  A code's result equals
- * mindist_run's with default options (d, visited pairs, counts, pair
- * minima); witnesses may differ but have weight d. */
+ * Codes submitted to a server wait in a queue and are admitted, in
+ * submission order among those that fit, as slots and device memory free
+ * up; their work overlaps on the device with the codes already running.
+ *
+ * Engine 0 (default): max_active worker threads, each running one admitted
+ * code at a time through the single-code path (mindist_create / run /
+ * destroy) on its own stream; the device runs the kernels of all codes in
+ * flight side by side.  Engine 1: one stream and a set of code slots on the
+ * device; a manager thread keeps the persistent multi-code kernel of
+ * mindist_run_batch running over the resident codes; to admit waiting
+ * codes the launch is stopped (every wave finishes the chunk it holds, so
+ * no work is lost), the new codes' slots are written and the kernel is
+ * launched again over old and new codes together; a code's information
+ * sets, Gamma_j, saved tables, bounds and job records stay on the device
+ * from admission to completion, and finished codes are read back while the
+ * others keep running.
+ *
+ * Under either engine a code's result equals mindist_run's with default
+ * options (d, visited pairs, counts, pair minima); witnesses may differ but
+ * have weight d. */
 typedef struct mindist_server mindist_server;
 
 typedef struct mindist_server_opts {
     int32_t max_active;       /* codes running at once: engine 0, worker threads (0 = 4);
                                  engine 1, code slots resident on the device (0 = 256) */
     int32_t blocks_per_cu;    /* resident workgroups per CU (0 = 4) */
-    int64_t device_bytes;     /* device memory for resident codes' rows, saved tables and
-                                 witness slots, a code is admitted only when its share
-                                 fits (0 = 8 GiB) */
+    int64_t device_bytes;     /* device memory for the codes in flight: a code is admitted
+                                 only when its share fits beside theirs (0 = 8 GiB).  Engine
+                                 0: estimated rows, saved right and left tables up to half
+                                 the expected top level, run state; engine 1: rows,
+                                 saved tables and witness slots in a pool allocated at
+                                 creation.  Submit fails with MINDIST_E_NOMEM for a code
+                                 whose share exceeds it */
     double  epoch_min_ms;     /* least running time of a launch before waiting codes are
                                  admitted (0 = 0.5 ms) */
     int32_t table_kib;        /* cap on one saved table in KiB (0 = 65536) */
@@ -283,9 +295,9 @@ typedef struct mindist_server_opts {
                                  (mindist_create / run / destroy) on its own stream in one of
                                  max_active worker threads; the device runs the kernels of
                                  the codes in flight side by side.  1: the persistent
-                                 multi-code kernel in epochs (device_bytes, epoch_min_ms,
-                                 jobs_per_code, blocks_per_cu and chunks_per_visit apply to
-                                 this engine only) */
+                                 multi-code kernel in epochs (epoch_min_ms, jobs_per_code,
+                                 blocks_per_cu and chunks_per_visit apply to this engine
+                                 only) */
 } mindist_server_opts;
 
 #define MINDIST_SERVER_MAX_PAIRS 256

@@ -54,6 +54,31 @@ static int expected_top_level(const HostCode &hc) {
     return top;
 }
 
+int single_path_bytes(const uint64_t *G, int n, int k, uint64_t table_cap, size_t &bytes) {
+    HostCode hc;
+    hc.n = n;
+    hc.k = k;
+    int e = make_plan(G, n, k, hc.P);
+    if (e) return e;
+    hc.n_gamma = (int)hc.P.sets.size();
+    const Binom &B = BN();
+    // saved sums of s-subsets up to ceil(top / 2) for the expected top level
+    // (the balanced split's right and left sizes), each only if it fits the
+    // table cap
+    const int smax = (expected_top_level(hc) + 1) / 2;
+    bytes = (size_t)1 << 20;          // run state, per-wave totals, mailboxes
+    for (int j = 0; j < hc.n_gamma; ++j) {
+        const int dp = dp_of_host((int)((carried_columns(hc.P, j).size() + 31) / 32));
+        bytes += align256((size_t)k * dp * 4);
+        for (int sz = 1; sz <= smax && sz <= k; ++sz) {
+            const uint64_t tb = B(k, sz) * (uint64_t)dp * 4;
+            if (tb > table_cap) break;
+            bytes += 2 * align256(tb);
+        }
+    }
+    return MINDIST_OK;
+}
+
 int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &hc) {
     hc = HostCode();
     hc.n = n;

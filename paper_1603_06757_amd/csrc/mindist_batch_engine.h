@@ -30,6 +30,10 @@ struct SlotPlace {
 };
 
 int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &hc);
+// validate G and estimate the device bytes the single-code path holds for
+// it (rows, saved right and left tables up to half the expected top level,
+// rounded up, within the table cap; run state)
+int single_path_bytes(const uint64_t *G, int n, int k, uint64_t table_cap, size_t &bytes);
 // device bytes of a prepared code from its per-set table levels (bcap)
 void size_tables(HostCode &hc);
 // lower the table levels of the codes with the largest tables until all

@@ -141,6 +141,7 @@ struct mindist_server {
     double wall_hz = 1e8;                   // device wall-clock rate
     std::thread mgr;
     std::vector<std::thread> workers;       // engine 0
+    size_t bytes_budget = 0, bytes_in_flight = 0;   // engine 0: device footprint admission
     std::string fatal;                      // first device error seen by the manager
 
     double clock() const {
@@ -357,9 +358,11 @@ void manager(mindist_server *S) {
     }
 }
 
-// Engine 0: one worker thread.  Codes are taken in submission order; the
-// single-code path allocates nothing per code after warm-up (process-wide
-// caches of device memory, streams and events).
+// Engine 0: one worker thread.  A code is admitted when a worker is free
+// and its device footprint fits beside the codes in flight (submission
+// order among the codes that fit); the single-code path allocates nothing
+// per code after warm-up (process-wide caches of device memory, streams
+// and events).
 void direct_worker(mindist_server *S) {
     (void)hipSetDevice(S->device);
     const int table_mib = S->o.table_kib > 0 ? std::max(1, S->o.table_kib / 1024) : 0;
@@ -367,11 +370,19 @@ void direct_worker(mindist_server *S) {
         std::unique_ptr<Request> req;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv.wait(lk, [&] { return S->quit || !S->pending.empty(); });
+            auto fitting = S->pending.end();
+            S->cv.wait(lk, [&] {
+                if (S->quit) return true;
+                fitting = std::find_if(S->pending.begin(), S->pending.end(), [&](const auto &r) {
+                    return S->bytes_in_flight + r->bytes <= S->bytes_budget;
+                });
+                return fitting != S->pending.end();
+            });
             if (S->quit) return;
-            req = std::move(S->pending.front());
-            S->pending.pop_front();
+            req = std::move(*fitting);
+            S->pending.erase(fitting);
             req->t_admit = S->clock();
+            S->bytes_in_flight += req->bytes;
             ++S->resident;
             ++S->st.admitted;
         }
@@ -398,6 +409,7 @@ void direct_worker(mindist_server *S) {
         res->t_done = S->clock();
         std::lock_guard<std::mutex> lk(S->mu);
         --S->resident;
+        S->bytes_in_flight -= req->bytes;
         ++S->st.completed;
         S->st.seconds_kernel += kernel_s;
         S->done.push_back(std::move(res));
@@ -445,6 +457,7 @@ extern "C" int mindist_server_create(const mindist_server_opts *opts, mindist_se
                 if (st) stream_put(st);
             if (!device_binom_from(BN().t.data())) return fail(MINDIST_E_NOMEM, "binomial table upload failed");
         }
+        S->bytes_budget = S->o.device_bytes > 0 ? (size_t)S->o.device_bytes : (size_t)8 << 30;
         S->t0 = std::chrono::steady_clock::now();
         mindist_server *raw = S.get();
         for (int t = 0; t < workers; ++t) raw->workers.emplace_back(direct_worker, raw);
@@ -511,10 +524,14 @@ extern "C" int mindist_server_submit(mindist_server *S, const uint64_t *G, int n
     r->tag = tag;
     r->t_submit = S->clock();
     if (S->o.engine == 0) {
-        // validate here (the caller learns of a bad matrix at once); the
-        // worker plans again inside mindist_create
-        int e = mindist_plan(G, n, k, nullptr, nullptr, nullptr, nullptr);
+        // validate and size here (the caller learns of a bad matrix at
+        // once); the worker plans again inside mindist_create.  Footprint:
+        // rows, right and left saved tables up to the levels the estimated
+        // distance needs (within the table cap), and the run's state.
+        const uint64_t table_cap = (uint64_t)(S->o.table_kib > 0 ? S->o.table_kib : 262144) << 10;
+        int e = single_path_bytes(G, n, k, table_cap, r->bytes);
         if (e) return e;
+        if (r->bytes > S->bytes_budget) return fail(MINDIST_E_NOMEM, "code does not fit the server's device memory");
         r->n = n;
         r->k = k;
         r->G.assign(G, G + (size_t)k * ((n + 63) / 64));

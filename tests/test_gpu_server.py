@@ -91,13 +91,21 @@ def test_server_admits_while_others_run(engine):
         same_as_single(got[i], md.min_distance(G, n, k))
 
 
-def test_server_admission_by_device_memory():
-    """A small device budget keeps few codes resident at once; every code
-    still completes with the result it has alone."""
+@pytest.mark.parametrize("engine", [0, 1])
+def test_server_admission_by_device_memory(engine):
+    """A small device budget keeps few codes in flight at once; every code
+    still completes with the result it has alone, and a code whose share
+    exceeds the whole budget is refused at submit."""
     cs = [serving_request(i) for i in range(40)]
     cs = [(n, k, G) for n, k, G in cs if n <= 120][:16]
-    say("server: 16 serving-stream codes, 24 MiB of device memory (engine 1)")
-    with md.Server(max_active=64, device_bytes=24 << 20, engine=1) as srv:
+    with md.Server(max_active=4, device_bytes=1024, engine=engine) as srv:
+        with pytest.raises(md.MindistError) as e:
+            srv.submit(cs[0][2], cs[0][0], cs[0][1], tag=0)
+        assert e.value.code == -3
+    # 48 MiB: the largest of these codes needs about 29 MiB (engine 0's
+    # estimate), so only a few are in flight at once
+    say("server: 16 serving-stream codes, 48 MiB of device memory, engine", engine)
+    with md.Server(max_active=64, device_bytes=48 << 20, engine=engine) as srv:
         for i, (n, k, G) in enumerate(cs):
             srv.submit(G, n, k, tag=i)
         got = collect(srv, len(cs), timeout=300)

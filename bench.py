@@ -200,17 +200,27 @@ def batch_leg(codes_total: int, stride: int):
     res, info = md.run_batch(codes, pairs=False, deadline_s=600, **opts)
     tb = time.perf_counter() - t0
     print(f"[bench] batch of {len(codes)} codes: {tb:.2f}s", file=sys.stderr, flush=True)
+    # the same codes all in the persistent launch (no routing to the single path)
+    t0 = time.perf_counter()
+    res_p, info_p = md.run_batch(codes, pairs=False, deadline_s=600, direct_log2=-1, **opts)
+    tpers = time.perf_counter() - t0
+    print(f"[bench] batch of {len(codes)} codes, persistent launch only: {tpers:.2f}s",
+          file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     plain = [md.min_distance(G, n, k) for n, k, G in codes]
     tp = time.perf_counter() - t0
     print(f"[bench] one run per code: {tp:.2f}s", file=sys.stderr, flush=True)
     same = all(r.get("d") == p["d"] and r.get("canonical_total") == p["canonical_total"]
-               for r, p in zip(res, plain))
+               and q.get("d") == p["d"] and q.get("canonical_total") == p["canonical_total"]
+               for r, q, p in zip(res, res_p, plain))
     return {"codes": len(codes), "sample": f"codes 0,{stride},...,{codes_total - stride} of the "
                                             f"{codes_total}-code stream" if stride > 1 else
                                             f"all {codes_total} codes",
             "batched_s": tb, "plain_s": tp, "codes_per_s_batched": len(codes) / tb,
             "codes_per_s_plain": len(codes) / tp, "speedup": tp / tb, "identical": same,
+            "routing": "codes estimated at >= 2^30 combinations through the single path "
+                       "on 8 worker threads, the rest in one persistent launch",
+            "persistent_only_s": tpers, "speedup_persistent_only": tp / tpers,
             "kernel_s": info["seconds_kernel"], "autotuned": opts, "autotune_s": t_tune,
             "codewords": info["executed_total"],
             "codewords_per_s_kernel": info["executed_total"] / info["seconds_kernel"]}

@@ -214,14 +214,21 @@ typedef struct mindist_batch_opts {
     int32_t chunks_per_visit; /* chunks a wave runs on one code's job before it moves on to
                                  the next code with work (0 = 4; -1 = until the job is fully
                                  claimed): the share of waves each live code gets */
-    int32_t reserved0;
-    double  deadline_s;       /* wall-clock limit of the launch; waves leave after it and the
+    int32_t direct_log2;      /* routing: a code expected to enumerate at least 2^direct_log2
+                                 combinations (estimate: every pair while the bound is below a
+                                 Gilbert-Varshamov estimate of d), or beyond the persistent
+                                 kernel's limits, runs through the single-code path on one of
+                                 8 worker threads (own streams, side by side) after the
+                                 persistent launch; 0 = 30; -1 = every code in the persistent
+                                 launch (the tuning knobs above apply to that launch only) */
+    double  deadline_s;       /* wall-clock limit of the call; waves leave after it and the
                                  call returns MINDIST_E_TIMEOUT (0 = none) */
     int64_t stream;           /* hipStream_t, 0 = private */
     mindist_pair *pairs;      /* optional: visited pairs of every code (caller-owned) */
     int64_t pairs_cap;        /* capacity of pairs[] */
     int64_t *pairs_index;     /* optional: B+1 offsets into pairs[] (caller-owned) */
-    double  seconds_kernel;   /* out: device time of the launch (HIP events) */
+    double  seconds_kernel;   /* out: device time of the persistent launch (HIP events) plus
+                                 the wall time of the codes run through the single path */
     double  seconds_total;    /* out: wall clock of the call */
     double  seconds_prep;     /* out: host preprocessing (information sets, packing) */
     uint64_t executed_total;  /* out: codewords evaluated */
@@ -241,8 +248,11 @@ typedef struct mindist_batch_opts {
  * chunks of each code's current pair (Algorithm 1's inner minimum) and, when a
  * pair completes, applies Algorithm 1's bound and termination test for that
  * code and opens its next pair (one raise of L per Gamma_j, midpair exit).
- * G[i] points at code i's matrix (layout as above; n <= 256, at most 32
- * information sets); out has B caller-owned entries.  Results equal
+ * Codes expected to be long (see direct_log2) run through the single-code
+ * path instead, on worker threads after the launch.  G[i] points at code
+ * i's matrix (layout as above; in the persistent launch n <= 256 and at most
+ * 32 information sets, other codes are routed to the single path unless
+ * direct_log2 = -1); out has B caller-owned entries.  Results equal
  * mindist_run's with default options (d, visited pairs, counts, pair minima);
  * witnesses may differ but have weight d.  Per-code failures (rank, limits)
  * are reported as out[i].d = negative error code; the call returns

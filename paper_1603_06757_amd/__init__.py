@@ -74,7 +74,7 @@ class Pair(C.Structure):
 class BatchOpts(C.Structure):
     _fields_ = [("tile_min", C.c_int32), ("tile_max", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("use_graph", C.c_int32), ("table_kib", C.c_int32), ("jobs_per_code", C.c_int32),
-                ("chunks_per_visit", C.c_int32), ("reserved0", C.c_int32),
+                ("chunks_per_visit", C.c_int32), ("direct_log2", C.c_int32),
                 ("deadline_s", C.c_double), ("stream", C.c_int64), ("pairs", C.c_void_p), ("pairs_cap", C.c_int64),
                 ("pairs_index", C.c_void_p), ("seconds_kernel", C.c_double),
                 ("seconds_total", C.c_double), ("seconds_prep", C.c_double),
@@ -255,8 +255,11 @@ BATCH_MAX_PAIRS = 256
 
 def run_batch(codes, tile_min: int = 0, tile_max: int = 0, blocks_per_cu: int = 0,
               use_graph: int = 1, table_kib: int = 0, jobs_per_code: int = 0,
-              pairs: bool = True, deadline_s: float = 60.0, chunks_per_visit: int = 0):
-    """Solve many codes in one persistent launch.
+              pairs: bool = True, deadline_s: float = 60.0, chunks_per_visit: int = 0,
+              direct_log2: int = 0):
+    """Solve many codes in one call: short codes in one persistent launch,
+    codes expected to enumerate at least 2^direct_log2 combinations (0 =
+    2^30; -1 = none) through the single-code path on worker threads.
 
     codes: iterable of (n, k, G).  Returns (results, info): results[i] is the
     dict of mindist_run for code i (with "pairs" when requested) or
@@ -274,6 +277,7 @@ def run_batch(codes, tile_min: int = 0, tile_max: int = 0, blocks_per_cu: int = 
     o.use_graph, o.table_kib, o.jobs_per_code = use_graph, table_kib, jobs_per_code
     o.deadline_s = deadline_s
     o.chunks_per_visit = chunks_per_visit
+    o.direct_log2 = direct_log2
     done = (C.c_double * B)()
     o.done_s = C.cast(done, C.c_void_p)
     if pairs:
@@ -291,7 +295,7 @@ def run_batch(codes, tile_min: int = 0, tile_max: int = 0, blocks_per_cu: int = 
             continue
         r = out[i].to_dict()
         if pairs:
-            r["pairs"] = [parr[t].to_dict() for t in range(idx[i], idx[i + 1])]
+            r["pairs"] = [parr[t].to_dict() for t in range(idx[i], min(idx[i + 1], cap))]
         results.append(r)
     info = {"seconds_kernel": o.seconds_kernel, "seconds_total": o.seconds_total,
             "seconds_prep": o.seconds_prep, "executed_total": o.executed_total,

@@ -14,9 +14,9 @@ columns need (identity columns of full sets stripped), and more words only
 add work.
 
 ``tune`` runs a coordinate search over these parameters on a seeded sample
-of the workload, keeps only configurations whose results equal the first
-run's (d and the canonical count of every code), and returns the fastest by
-kernel time.  ``tuned_options`` caches the result per device and workload
+of the workload (every code in the persistent launch), keeps only
+configurations whose results equal the first run's (d and the canonical
+count of every code), and returns the fastest by kernel time.  ``tuned_options`` caches the result per device and workload
 key in a JSON file.
 """
 from __future__ import annotations
@@ -51,7 +51,7 @@ def tune(codes, repeats: int = 1, log=None) -> dict:
         nonlocal ref
         t = None
         for _ in range(repeats):
-            res, info = run_batch(codes, pairs=False, **opts)
+            res, info = run_batch(codes, pairs=False, direct_log2=-1, **opts)
             key = _key(res)
             if ref is None:
                 ref = key

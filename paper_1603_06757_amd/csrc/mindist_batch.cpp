@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <thread>
 
 #include "../../include/mindist.h"
@@ -52,6 +53,32 @@ static int expected_top_level(const HostCode &hc) {
             L = bound_after(k, hc.P.m_full, hc.P.k_m, hc.n_gamma, j, w);
         }
     return top;
+}
+
+// Combinations Algorithm 1 is expected to enumerate: every pair in order
+// while the bound is below a Gilbert-Varshamov estimate of d (the least w
+// with sum_{i<=w} C(n,i) >= 2^(n-k)).
+static double estimated_work(const HostCode &hc) {
+    const int n = hc.n, k = hc.k;
+    auto log2c = [](int a, int b) {
+        return (std::lgamma(a + 1.0) - std::lgamma(b + 1.0) - std::lgamma(a - b + 1.0)) / std::log(2.0);
+    };
+    double acc = -1e300;
+    int d = n - k + 1;
+    for (int i = 0; i <= n; ++i) {
+        const double t = log2c(n, i);
+        acc = acc > t ? acc + std::log2(1.0 + std::exp2(t - acc)) : t + std::log2(1.0 + std::exp2(acc - t));
+        if (acc >= n - k) { d = i; break; }
+    }
+    double work = 0;
+    int L = 1;
+    for (int w = 1; w <= k; ++w)
+        for (int j = 0; j < hc.n_gamma; ++j) {
+            if (L >= d) return work;
+            work += std::exp2(log2c(k, w));
+            L = bound_after(k, hc.P.m_full, hc.P.k_m, hc.n_gamma, j, w);
+        }
+    return work;
 }
 
 int single_path_bytes(const uint64_t *G, int n, int k, uint64_t table_cap, size_t &bytes) {
@@ -338,9 +365,19 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
         status[i] = prepare_code(G[i], n[i], k[i], table_cap, hc[i]);
     });
     const auto t_prep = std::chrono::steady_clock::now();
-    std::vector<int> live;
-    for (int i = 0; i < B; ++i)
-        if (status[i] == MINDIST_OK) live.push_back(i);
+    // routing: a code expected to enumerate at least 2^direct_log2
+    // combinations (or beyond the persistent kernel's limits) runs through
+    // the single-code path on a worker thread, where its pairs fill the GPU
+    // on their own; the others share the persistent launch, which saves
+    // them the per-pair launches and host round trips that dominate short
+    // codes
+    const bool direct_on = o.direct_log2 >= 0;
+    const double direct_min = std::exp2(o.direct_log2 > 0 ? o.direct_log2 : 30);
+    std::vector<int> live, direct;
+    for (int i = 0; i < B; ++i) {
+        if (status[i] == MINDIST_OK && !(direct_on && estimated_work(hc[i]) >= direct_min)) live.push_back(i);
+        else if (direct_on && (status[i] == MINDIST_OK || status[i] == MINDIST_E_LIMIT)) direct.push_back(i);
+    }
     for (int i = 0; i < B; ++i)
         if (status[i] != MINDIST_OK) {
             std::memset(&out[i], 0, sizeof(out[i]));
@@ -348,7 +385,102 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
             out[i].n = n[i];
             out[i].k = k[i];
         }
-    if (live.empty()) return fail(MINDIST_E_ARG, "no valid code in the batch");
+    if (live.empty() && direct.empty()) return fail(MINDIST_E_ARG, "no valid code in the batch");
+    std::vector<std::vector<mindist_pair>> direct_traces(direct.size());
+    double direct_s = 0;
+    bool direct_timed_out = false;
+    auto run_direct = [&](double t_offset) -> int {
+        // worker threads, each running whole codes through the single path
+        // on its own stream; the device runs their kernels side by side
+        if (direct.empty()) return MINDIST_OK;
+        const auto td = std::chrono::steady_clock::now();
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        std::atomic<int> next{0};
+        std::atomic<int> hard{MINDIST_OK};
+        std::string hard_msg;
+        std::mutex mu;
+        auto worker = [&]() {
+            (void)hipSetDevice(dev);
+            for (int t; (t = next.fetch_add(1)) < (int)direct.size();) {
+                const int i = direct[t];
+                mindist_ctx *ctx = nullptr;
+                int st = mindist_create(G[i], n[i], k[i], &ctx);
+                if (st == MINDIST_OK && o.deadline_s > 0) {
+                    const double left = o.deadline_s -
+                        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                    st = left > 0 ? mindist_set_option(ctx, MINDIST_OPT_DEADLINE_MS, std::max<int64_t>(1, (int64_t)(left * 1e3)))
+                                  : MINDIST_E_TIMEOUT;
+                }
+                if (st == MINDIST_OK) st = mindist_run(ctx, &out[i]);
+                if (st == MINDIST_OK) {
+                    int np = 0;
+                    mindist_get_pairs(ctx, nullptr, 0, &np);
+                    direct_traces[t].resize(np);
+                    if (np) mindist_get_pairs(ctx, direct_traces[t].data(), np, &np);
+                } else {
+                    const std::string msg = last_error_text();
+                    std::memset(&out[i], 0, sizeof(out[i]));
+                    out[i].d = st;
+                    out[i].n = n[i];
+                    out[i].k = k[i];
+                    if (st == MINDIST_E_TIMEOUT) direct_timed_out = true;
+                    if (st == MINDIST_E_HIP) {
+                        std::lock_guard<std::mutex> lk(mu);
+                        hard = st;
+                        hard_msg = msg;
+                    }
+                }
+                if (ctx) mindist_destroy(ctx);
+                if (o.done_s)
+                    o.done_s[i] = t_offset + std::chrono::duration<double>(std::chrono::steady_clock::now() - td).count();
+            }
+        };
+        const int nw = std::min<int>(kBatchDirectWorkers, (int)direct.size());
+        std::vector<std::thread> ths;
+        for (int w = 1; w < nw; ++w) ths.emplace_back(worker);
+        worker();
+        for (auto &th : ths) th.join();
+        direct_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - td).count();
+        if (hard != MINDIST_OK) return fail(hard, hard_msg);
+        return MINDIST_OK;
+    };
+    if (o.done_s)
+        for (int i = 0; i < B; ++i) o.done_s[i] = -1.0;
+    auto write_pairs = [&](const std::vector<std::vector<mindist_pair>> *persist_traces) {
+        if (!o.pairs_index) return;
+        int64_t pos = 0;
+        std::vector<const std::vector<mindist_pair> *> by_code(B, nullptr);
+        if (persist_traces)
+            for (size_t s = 0; s < live.size(); ++s) by_code[live[s]] = &(*persist_traces)[s];
+        for (size_t t = 0; t < direct.size(); ++t) by_code[direct[t]] = &direct_traces[t];
+        for (int i = 0; i < B; ++i) {
+            o.pairs_index[i] = pos;
+            if (by_code[i])
+                for (const auto &r : *by_code[i]) {
+                    if (o.pairs && pos < o.pairs_cap) o.pairs[pos] = r;
+                    ++pos;
+                }
+        }
+        o.pairs_index[B] = pos;
+    };
+    if (live.empty()) {
+        // every code runs through the single path
+        int e = run_direct(0.0);
+        if (e) return e;
+        uint64_t executed = 0;
+        for (int i : direct) if (out[i].d > 0) executed += out[i].executed_total;
+        write_pairs(nullptr);
+        o.seconds_kernel = direct_s;
+        o.wave_s_table = o.wave_s_pair = o.wave_s_flush = 0;
+        o.waves = 0;
+        o.chunks_table = o.chunks_pair = 0;
+        o.seconds_prep = std::chrono::duration<double>(t_prep - t0).count();
+        o.executed_total = executed;
+        o.seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (direct_timed_out) return fail(MINDIST_E_TIMEOUT, "batch deadline reached before every code finished");
+        return MINDIST_OK;
+    }
     const int L = (int)live.size();
     {
         // all saved tables of the batch within half of the free device memory
@@ -405,22 +537,14 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
         executed += out[live[s]].executed_total;
         if (drc[s] == MINDIST_E_HIP) return fail(MINDIST_E_HIP, derr[s]);
     }
-    if (o.pairs_index) {
-        int64_t pos = 0;
-        std::vector<const std::vector<mindist_pair> *> by_code(B, nullptr);
-        for (int s = 0; s < L; ++s) by_code[live[s]] = &traces[s];
-        for (int i = 0; i < B; ++i) {
-            o.pairs_index[i] = pos;
-            if (by_code[i])
-                for (const auto &r : *by_code[i]) {
-                    if (o.pairs && pos < o.pairs_cap) o.pairs[pos] = r;
-                    ++pos;
-                }
-        }
-        o.pairs_index[B] = pos;
-    }
-    if (timed_out) return fail(MINDIST_E_TIMEOUT, "batch deadline reached before every code finished");
-    o.seconds_kernel = eng.kernel_seconds;
+    // the codes routed to the single path, after the persistent launch
+    e = run_direct(eng.kernel_seconds);
+    if (e) return e;
+    for (int i : direct) if (out[i].d > 0) executed += out[i].executed_total;
+    write_pairs(&traces);
+    if (timed_out || direct_timed_out)
+        return fail(MINDIST_E_TIMEOUT, "batch deadline reached before every code finished");
+    o.seconds_kernel = eng.kernel_seconds + direct_s;
     o.wave_s_table = (double)eng.h_g->ticks_table / eng.wall_hz;
     o.wave_s_pair = (double)eng.h_g->ticks_pair / eng.wall_hz;
     o.wave_s_flush = (double)eng.h_g->ticks_flush / eng.wall_hz;
@@ -431,7 +555,6 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
         uint64_t t0 = ~0ull;
         for (int s = 0; s < L; ++s)
             if (eng.h_codes[s].t_open) t0 = std::min<uint64_t>(t0, eng.h_codes[s].t_open);
-        for (int i = 0; i < B; ++i) o.done_s[i] = -1.0;
         for (int s = 0; s < L; ++s) {
             const BatchCode &bc = eng.h_codes[s];
             if (bc.t_done && t0 != ~0ull) o.done_s[live[s]] = (double)(bc.t_done - t0) / eng.wall_hz;

@@ -55,6 +55,7 @@ struct BatchSet {
 };
 
 constexpr int kJobCounters = 8;       // chunk dispensers per job (one cache line each)
+constexpr int kBatchDirectWorkers = 8;   // threads running a batch's codes routed to the single path
 
 // one job of a code; GroupEntry groups[ngroups] follow the struct.
 // Chunks are handed out by nctr counters: counter r hands out chunks

@@ -1,4 +1,5 @@
-"""GPU parity of the persistent multi-code path.
+"""GPU parity of the multi-code path: the persistent launch, and the single
+path for the long codes a batch routes there.
 
 Every code of a batch must give exactly what the single-code path gives with
 default options (d, the visited pairs, every pair minimum, the counts C(k,w),
@@ -71,7 +72,10 @@ def test_batch_matches_oracle_small_codes():
         check_witness(G, n, k, r)
 
 
-def test_batch_workloads_and_textbook_golden():
+@pytest.mark.parametrize("direct_log2", [0, -1])
+def test_batch_workloads_and_textbook_golden(direct_log2):
+    """The long codes go through the single path by default (direct_log2 = 0)
+    and through the persistent launch with -1; both match the goldens."""
     names = ["rand48x24", "rand150x75", "rand255x40", "golay24", "rm_2_7", "rm_3_7",
              "rm_2_8", "rm_2_8_punct"]
     ctors = {"golay24": codes.golay24, "rm_2_7": lambda: codes.reed_muller(2, 7),
@@ -85,8 +89,8 @@ def test_batch_workloads_and_textbook_golden():
         else:
             G, n, k = ctors[nm]()
             cs.append((n, k, G))
-    say("batch of workloads + textbook codes")
-    res, info = md.run_batch(cs)
+    say("batch of workloads + textbook codes, direct_log2", direct_log2)
+    res, info = md.run_batch(cs, direct_log2=direct_log2)
     for nm, (n, k, G), r in zip(names, cs, res):
         gold = json.load(open(os.path.join(GOLDEN, f"{nm}.json")))
         assert r["d"] == gold["d"], nm
@@ -115,7 +119,8 @@ def test_batch_equals_single_on_batch_stream():
 def test_batch_launch_shapes(graph, tmin, tmax, bpc):
     cs = light_codes(48, seed=5)
     say("launch shape", graph, tmin, tmax, bpc)
-    res, info = md.run_batch(cs, use_graph=graph, tile_min=tmin, tile_max=tmax, blocks_per_cu=bpc)
+    res, info = md.run_batch(cs, use_graph=graph, tile_min=tmin, tile_max=tmax, blocks_per_cu=bpc,
+                             direct_log2=-1)
     for (n, k, G), r in zip(cs, res):
         ref = oracle.bz(G, n, k, threads=4)
         assert r["d"] == ref["d"]
@@ -135,21 +140,26 @@ def test_batch_errors_reported_per_code():
 
 
 def test_batch_limits_reported():
-    """More than 32 information sets is beyond the batch layout: E_LIMIT for
-    that code, the others unaffected."""
+    """More than 32 information sets is beyond the persistent launch's
+    layout: E_LIMIT for that code when every code must run there, the
+    single path's answer when routing is on; the others unaffected."""
     G = random_generator(200, 3, 1, 2)
     good = light_codes(2, seed=13)
-    res, info = md.run_batch([(200, 3, G)] + good)
+    res, info = md.run_batch([(200, 3, G)] + good, direct_log2=-1)
     assert res[0]["error"] == -5
     for (n, k, G2), r in zip(good, res[1:]):
         assert r["d"] == oracle.bz(G2, n, k)["d"]
+    res, info = md.run_batch([(200, 3, G)] + good)
+    assert res[0]["d"] == oracle.bz(G, 200, 3)["d"]
+    same_as_single(res[0], md.min_distance(G, 200, 3))
 
 
-def test_batch_single_code_and_repeat():
+@pytest.mark.parametrize("direct_log2", [0, -1])
+def test_batch_single_code_and_repeat(direct_log2):
     w = WORKLOADS["rand150x75"]
     gold = json.load(open(os.path.join(GOLDEN, "rand150x75.json")))
     for _ in range(3):
-        res, info = md.run_batch([(w.n, w.k, w.matrix())])
+        res, info = md.run_batch([(w.n, w.k, w.matrix())], direct_log2=direct_log2)
         assert res[0]["d"] == gold["d"]
         compare_with_trace(res[0], gold["trace"], gold["counts"], gold["pair_min"], None, w.k)
 
@@ -159,6 +169,24 @@ def test_batch_kernel_keeps_four_blocks_per_cu():
     most 128 VGPRs): a larger register budget silently drops a quarter of
     the resident waves."""
     cs = light_codes(4, seed=95)
-    res, info = md.run_batch(cs)
+    res, info = md.run_batch(cs, direct_log2=-1)
     say("waves", info["waves"])
     assert info["waves"] == 256 * 4 * 4      # MI355X: 256 CUs, 4 blocks of 4 waves
+
+
+def test_batch_routes_long_codes_to_the_single_path():
+    """A mixed batch: short codes share the persistent launch, long ones (and
+    one beyond the launch's limits) run through the single path on worker
+    threads; every result equals the code's single run, in input order."""
+    light = light_codes(40, seed=96)
+    w150, w255 = WORKLOADS["rand150x75"], WORKLOADS["rand255x40"]
+    wide = random_generator(200, 3, 1, 2)
+    cs = light[:20] + [(w150.n, w150.k, w150.matrix())] + light[20:] + \
+        [(w255.n, w255.k, w255.matrix()), (200, 3, wide)]
+    say("mixed batch", len(cs))
+    res, info = md.run_batch(cs)
+    assert info["waves"] > 0                 # the persistent launch ran
+    for (n, k, G), r in zip(cs, res):
+        same_as_single(r, md.min_distance(G, n, k))
+        check_witness(G, n, k, r)
+    assert all(x >= 0 for x in info["done_s"])

@@ -163,6 +163,13 @@ static int get_table(mindist_ctx *c, int j, int r, int kind, int shift, uint32_t
         if (cnt_out) *cnt_out = it->second.second;
         return MINDIST_OK;
     }
+    // a plain table of level r >= 2 is extended from level r - 1 (built
+    // first if missing): one row per entry instead of r
+    uint32_t *prev = nullptr;
+    if (shift == 0 && r >= 2) {
+        int e = get_table(c, j, r - 1, kind, 0, &prev);
+        if (e) return e;
+    }
     const uint64_t ent = BN()(c->P.k - shift, r);
     uint32_t *t = static_cast<uint32_t *>(dev_alloc(ent * g.DP * 4));
     uint32_t *cn = shift ? static_cast<uint32_t *>(dev_alloc(ent * 4)) : nullptr;
@@ -171,7 +178,7 @@ static int get_table(mindist_ctx *c, int j, int r, int kind, int shift, uint32_t
         dev_free(cn);
         return fail(MINDIST_E_NOMEM, "saved-sum table allocation failed");
     }
-    TableArgs ta{g.rows, c->d_binom, t, cn, ent, c->P.k, r, g.DP, kind ? 1 : 0, shift};
+    TableArgs ta{g.rows, c->d_binom, t, cn, ent, c->P.k, r, g.DP, kind ? 1 : 0, shift, prev};
     if (launch_build_table(ta, g.D, c->stream)) {
         dev_free(t);
         dev_free(cn);

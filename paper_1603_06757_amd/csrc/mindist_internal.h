@@ -162,6 +162,12 @@ struct TableArgs {
     int32_t k, b, dp;
     int32_t reflect;
     int32_t shift;
+    // the same kind of table one level down (shift 0, b >= 2), or nullptr.
+    // In colex order the b-subsets with largest element m are the entries
+    // [C(m,b), C(m+1,b)), and entry C(m,b) + r is {m} with the (b-1)-subset
+    // of rank r (r < C(m,b-1)), so entry C(m,b) + r = row(m) + prev[r]
+    // (row k-1-m for the reflected right tables)
+    const uint32_t *prev;
 };
 
 // kernel launchers (mindist_kernels.hip)

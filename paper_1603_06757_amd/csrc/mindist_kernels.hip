@@ -278,6 +278,28 @@ __global__ __launch_bounds__(256) void build_table_kernel(TableArgs ta) {
     if (ta.cnt2) ta.cnt2[i] = (uint32_t)binom(ta.binom, ta.shift + zmin, ta.shift);
 }
 
+// Level b from level b-1 (TableArgs::prev): one search of the block of
+// the entry's largest element in LDS, one row and one lower-level entry.
+template <int D>
+__global__ __launch_bounds__(256) void extend_table_kernel(TableArgs ta) {
+    __shared__ uint64_t start[kBinomX];      // start[m] = C(m, b): first entry of block m
+    for (int x = threadIdx.x; x <= ta.k; x += blockDim.x) start[x] = binom(ta.binom, x, ta.b);
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ta.entries) return;
+    int lo = ta.b - 1, hi = ta.k - 1;          // largest m with C(m, b) <= i
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    const uint64_t r = i - start[lo];
+    const int row = ta.reflect ? (ta.k - 1 - lo) : lo;
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+        ta.table[i * ta.dp + d] = ta.rows[(size_t)row * ta.dp + d] ^ ta.prev[r * ta.dp + d];
+    for (int d = D; d < ta.dp; ++d) ta.table[i * ta.dp + d] = 0;
+}
+
 __global__ void init_state_kernel(DevState *st, int max_pairs) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     for (int q = tid; q < max_pairs * kCounters; q += gridDim.x * blockDim.x)
@@ -304,7 +326,10 @@ int launch_init_state(DevState *st, int max_pairs, void *stream) {
 template <int D>
 static void table_launch(const TableArgs &ta, hipStream_t s) {
     const uint64_t blocks = (ta.entries + 255) / 256;
-    hipLaunchKernelGGL(build_table_kernel<D>, dim3((unsigned)blocks), dim3(256), 0, s, ta);
+    if (ta.prev)
+        hipLaunchKernelGGL(extend_table_kernel<D>, dim3((unsigned)blocks), dim3(256), 0, s, ta);
+    else
+        hipLaunchKernelGGL(build_table_kernel<D>, dim3((unsigned)blocks), dim3(256), 0, s, ta);
 }
 
 int launch_build_table(const TableArgs &ta, int D, void *stream) {

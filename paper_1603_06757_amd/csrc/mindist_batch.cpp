@@ -388,7 +388,7 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
     if (live.empty() && direct.empty()) return fail(MINDIST_E_ARG, "no valid code in the batch");
     std::vector<std::vector<mindist_pair>> direct_traces(direct.size());
     double direct_s = 0;
-    bool direct_timed_out = false;
+    std::atomic<bool> direct_timed_out{false};
     auto run_direct = [&](double t_offset) -> int {
         // worker threads, each running whole codes through the single path
         // on its own stream; the device runs their kernels side by side

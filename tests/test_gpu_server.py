@@ -130,3 +130,17 @@ def test_server_submit_errors_and_wait(engine):
         got = srv.poll()
         assert [r["tag"] for r in got] == [7] and got[0]["status"] == 0
         assert srv.poll() == []
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+def test_server_destroy_with_waiting_codes(engine):
+    """Destroying a server with a long queue returns promptly: waiting codes
+    are dropped, the ones being run finish or stop first."""
+    cs = light_codes(120, seed=97)
+    srv = md.Server(max_active=2, engine=engine)
+    for i, (n, k, G) in enumerate(cs):
+        srv.submit(G, n, k, tag=i)
+    t0 = time.time()
+    srv.close()
+    say("destroy with", len(cs), "queued codes took", round(time.time() - t0, 3), "s, engine", engine)
+    assert time.time() - t0 < 10.0

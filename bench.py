@@ -95,12 +95,19 @@ def roofline(results, events):
     # kernel's first wave start to its last wave end, published with each
     # pair); HIP events on the kernel's stream in untimed runs cross-check them.
     def per_dwords(runs, field):
+        # per launch (short consecutive pairs share one): its pairs start
+        # together, so its time is the longest of theirs; codewords add up
         per_d = {}
         for r in runs:
+            launches = {}
             for p in r["pairs"]:
-                t = per_d.setdefault(p["dwords"], [0.0, 0, 0])
-                t[0] += p[field] * 1e-3
-                t[1] += p["executed"]
+                t = launches.setdefault(p["launch"], [p["dwords"], 0.0, 0])
+                t[1] = max(t[1], p[field] * 1e-3)
+                t[2] += p["executed"]
+            for D, sec, cw in launches.values():
+                t = per_d.setdefault(D, [0.0, 0, 0])
+                t[0] += sec
+                t[1] += cw
                 t[2] += 1
         return per_d
     per_d = per_dwords(results, "dev_ms")

@@ -138,18 +138,20 @@ typedef struct mindist_pair {
     uint64_t count;           /* C(k,w): combinations the pair covers */
     uint64_t executed;        /* combinations evaluated (< count only if cut short) */
     uint64_t wsum;            /* sum of weights (VERIFY=1 only, else 0) */
-    double   ms;              /* kernel time of the pair (PROFILE=1 only) */
+    double   ms;              /* kernel time of the pair's launch (PROFILE=1 only) */
     int32_t  dwords;          /* 32-bit words carried per codeword by the kernel */
     int32_t  split_a;         /* rows per lane subset */
     int32_t  split_b;         /* rows from the (outer) right table */
     int32_t  split_b2;        /* rows from the inner table (0: two-level split) */
-    int32_t  reserved;
+    int32_t  launch;          /* single path: index of the first pair of the launch this pair
+                                 ran in (short consecutive pairs share one launch; 0 in batch
+                                 and serving records) */
     double   t_start_ms;      /* PROFILE=1: when the pair's kernel started, ms after the first
                                  pair's; batch and serving: when the pair's job opened, ms after
                                  the code's first job opened (ms is then the open-to-close time) */
-    double   dev_ms;          /* single path, always: the pair's enumeration kernel on the device
-                                 clock, from its first wave's start to its last wave's end (no
-                                 dispatch latency); 0 in batch and serving records */
+    double   dev_ms;          /* single path, always: the pair's part of its enumeration launch
+                                 on the device clock, from its first wave's start to its last
+                                 wave's end (no dispatch latency); 0 in batch and serving */
 } mindist_pair;
 
 /* Section 2 and Algorithm 1 preprocessing: validate and copy G, greedy

@@ -64,7 +64,7 @@ class Pair(C.Structure):
                 ("L_after", C.c_int32), ("U_after", C.c_int32), ("pair_min", C.c_int32),
                 ("count", C.c_uint64), ("executed", C.c_uint64), ("wsum", C.c_uint64),
                 ("ms", C.c_double), ("dwords", C.c_int32), ("split_a", C.c_int32),
-                ("split_b", C.c_int32), ("split_b2", C.c_int32), ("reserved", C.c_int32),
+                ("split_b", C.c_int32), ("split_b2", C.c_int32), ("launch", C.c_int32),
                 ("t_start_ms", C.c_double), ("dev_ms", C.c_double)]
 
     def to_dict(self):

@@ -580,51 +580,71 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
         }
     }
 
-    // Launch one staged pair as pair index `idx` with bound L_prev, and the
-    // kernel that publishes its result behind it.
-    auto launch = [&](const Prep &q, int idx, int L_prev) -> int {
-        const GammaDev &g = c->gd[q.j];
-        const PairPlan &pp = q.pp;
-        PairArgs pa{};
-        pa.rows = g.rows;
-        pa.table = q.table;
-        pa.ltable = q.ltable;
-        pa.binom = c->d_binom;
-        pa.groups = q.groups;
-        pa.st = c->d_state;
-        pa.n_items = pp.n_items;
-        pa.total_chunks = pp.total_chunks;
-        pa.cancel_after = c->cancel_after;
-        pa.ngroups = pp.ngroups;
-        pa.k = k;
-        pa.a = pp.a;
-        pa.b = pp.b;
-        pa.b2 = pp.b2;
-        pa.table2 = q.table2;
-        pa.cnt2 = q.cnt2;
-        pa.T = pp.T;
-        pa.offset = g.stripped ? (uint32_t)q.w : 0u;
-        pa.L_prev = (uint32_t)L_prev;
-        pa.pair = (uint32_t)idx;
-        pa.midpair_exit = (uint32_t)midpair;
-        pa.max_pairs = c->max_pairs;
-        pa.rprefix = c->d_rprefix;
-        pa.order = (uint32_t)c->order;
-        pa.n_rt = pp.n_rt;
-        pa.counters = (uint32_t)c->counters;
+    // A pair ready to run as pair index idx with bound L_prev.
+    struct Flight { Prep q; int idx = 0; int L_prev = 0; int blocks = 0; };
+    auto blocks_of = [&](const PairPlan &pp) {
         const uint64_t want = ceil_div(pp.total_chunks, 4);
-        const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->cus * c->blocks_per_cu));
-        pa.waves = (uint32_t)blocks * 4u;
-        pa.parts = c->d_parts;
-        __atomic_store_n(&c->h_mail[idx % kMailRing].seq, 0u, __ATOMIC_RELEASE);
-        if (c->profile && hipEventRecord(c->pair_ev[2 * idx], c->stream) != hipSuccess)
+        return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->cus * c->blocks_per_cu));
+    };
+    // the plan of every pair launched in this run (a witness may come from a
+    // pair launched but not visited, in a launch shared with visited ones)
+    std::vector<Flight> launched_pairs;
+    std::vector<int> leader;          // profile: the first pair of each pair's launch
+    // Launch staged pairs (consecutive indices, same D) as one kernel, and
+    // the kernel that publishes their results behind it.
+    auto launch = [&](const std::vector<Flight> &grp) -> int {
+        GroupArgs ga{};
+        ga.n = (uint32_t)grp.size();
+        uint32_t bs = 0;
+        for (size_t t = 0; t < grp.size(); ++t) {
+            const Prep &q = grp[t].q;
+            const GammaDev &g = c->gd[q.j];
+            const PairPlan &pp = q.pp;
+            PairArgs &pa = ga.p[t];
+            pa.rows = g.rows;
+            pa.table = q.table;
+            pa.ltable = q.ltable;
+            pa.binom = c->d_binom;
+            pa.groups = q.groups;
+            pa.st = c->d_state;
+            pa.n_items = pp.n_items;
+            pa.total_chunks = pp.total_chunks;
+            pa.cancel_after = c->cancel_after;
+            pa.ngroups = pp.ngroups;
+            pa.k = k;
+            pa.a = pp.a;
+            pa.b = pp.b;
+            pa.b2 = pp.b2;
+            pa.table2 = q.table2;
+            pa.cnt2 = q.cnt2;
+            pa.T = pp.T;
+            pa.offset = g.stripped ? (uint32_t)q.w : 0u;
+            pa.L_prev = (uint32_t)grp[t].L_prev;
+            pa.pair = (uint32_t)grp[t].idx;
+            pa.midpair_exit = (uint32_t)midpair;
+            pa.max_pairs = c->max_pairs;
+            pa.rprefix = c->d_rprefix;
+            pa.order = (uint32_t)c->order;
+            pa.n_rt = pp.n_rt;
+            pa.counters = (uint32_t)c->counters;
+            pa.waves = (uint32_t)grp[t].blocks * 4u;
+            pa.parts = c->d_parts + (size_t)bs * 4;
+            ga.block_start[t] = bs;
+            bs += (uint32_t)grp[t].blocks;
+            __atomic_store_n(&c->h_mail[grp[t].idx % kMailRing].seq, 0u, __ATOMIC_RELEASE);
+            launched_pairs.push_back(grp[t]);
+            leader.push_back(grp[0].idx);
+        }
+        ga.block_start[grp.size()] = bs;
+        if ((uint64_t)bs * 4 > c->parts_cap) return fail(MINDIST_E_HIP, "launch exceeds the per-wave buffer");
+        const int idx0 = grp[0].idx;
+        if (c->profile && hipEventRecord(c->pair_ev[2 * idx0], c->stream) != hipSuccess)
             return fail(MINDIST_E_HIP, "event record failed");
-        if (launch_enum_pair(pa, g.D, c->items, c->verify, blocks, c->stream))
+        if (launch_enum_pair(ga, c->gd[grp[0].q.j].D, c->items, c->verify, c->stream))
             return fail(MINDIST_E_HIP, "enumeration kernel launch failed");
-        if (c->profile && hipEventRecord(c->pair_ev[2 * idx + 1], c->stream) != hipSuccess)
+        if (c->profile && hipEventRecord(c->pair_ev[2 * idx0 + 1], c->stream) != hipSuccess)
             return fail(MINDIST_E_HIP, "event record failed");
-        if (launch_publish_pair(c->d_parts, pa.waves, c->d_state, c->d_mail + idx % kMailRing,
-                                (uint32_t)idx, c->stream))
+        if (launch_publish_pair(ga, c->d_mail, c->stream))
             return fail(MINDIST_E_HIP, "publish kernel launch failed");
         ++launches;
         return MINDIST_OK;
@@ -643,19 +663,66 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
     // launched once its test passes; behind it, further pairs are launched
     // ahead of their results (with the bound they get if every pair before
     // them completes) while the work already queued is small, so the device
-    // never waits for the host between short pairs.  If Algorithm 1 stops,
-    // the pairs launched ahead read U <= their bound and leave at once (with
-    // mid-pair exit on; otherwise only one pair of at most `speculate`
-    // combinations is launched ahead).
-    struct Flight { Prep q; int idx; };
+    // never waits for the host between short pairs.  Short consecutive pairs
+    // of the same width share one launch (block ranges per pair), as long as
+    // all their blocks fit one round of the resident ones.  If Algorithm 1
+    // stops, the pairs launched ahead read U <= their bound and leave at once
+    // (with mid-pair exit on; otherwise only one pair of at most `speculate`
+    // combinations is launched ahead, and no launch is shared).
     std::deque<Flight> fl;          // launched, not read yet; front: next pair visited
     int nj = 0, nw = 1;             // the next pair to launch
     int L_pred = L;                 // the bound before it
     int next_idx = 0;
     PairMail last_mail{};
     const bool free_exit = midpair && !c->deadline_ms;
+    const bool grouping = free_exit && c->speculate && !c->order && !c->cancel_after;
+    const int resident_blocks = c->cus * c->blocks_per_cu;
     constexpr uint64_t kAheadWork = 1ull << 30;   // queued combinations that stop a second launch ahead
     auto advance = [&](int &j, int &w) { if (++j >= ng) { j = 0; ++w; } };
+    // Stage pair (nj, nw) as index next_idx with bound L0, extend the launch
+    // with the following short pairs when allowed, launch, and queue them.
+    auto launch_from_next = [&](int L0, bool may_group) -> int {
+        std::vector<Flight> grp;
+        int L_cur = L0;
+        int blocks = 0;
+        for (;;) {
+            Flight f;
+            int e = plan(f.q, nj, nw);
+            if (e) return e;
+            f.blocks = blocks_of(f.q.pp);
+            if (!grp.empty()) {
+                // joins the launch only if it is short and of the same width
+                const bool ok = f.q.pp.b2 == 0 && grp[0].q.pp.b2 == 0 &&
+                                c->gd[nj].D == c->gd[grp[0].q.j].D &&
+                                (uint64_t)f.q.pp.total_chunks <= 4ull * (uint64_t)f.blocks &&
+                                blocks + f.blocks <= resident_blocks;
+                if (!ok) break;
+            }
+            e = stage(f.q);
+            if (e) return e;
+            if (grp.empty() && c->order) {
+                e = upload_rprefix();
+                if (e) return e;
+            }
+            f.idx = next_idx++;
+            f.L_prev = L_cur;
+            blocks += f.blocks;
+            grp.push_back(f);
+            L_cur = L_after_pair(nj, nw, L_cur);
+            L_pred = L_cur;
+            advance(nj, nw);
+            const bool first_short = (uint64_t)grp[0].q.pp.total_chunks <= 4ull * (uint64_t)grp[0].blocks;
+            if (!may_group || !grouping || !first_short || (int)grp.size() >= kGroupMax ||
+                fl.size() + grp.size() >= (size_t)kMailRing - 1 || nw > k || beyond_limit(nw) ||
+                next_idx >= c->max_pairs ||
+                L_cur >= (int)std::min<uint32_t>(U_found, (uint32_t)singleton))
+                break;
+        }
+        int e = launch(grp);
+        if (e) return e;
+        for (auto &f : grp) fl.push_back(f);
+        return MINDIST_OK;
+    };
     for (bool more = ng >= 1 && k >= 1; more;) {
         const int j = fl.empty() ? nj : fl.front().q.j;
         const int w = fl.empty() ? nw : fl.front().q.w;
@@ -676,21 +743,8 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
             }
         }
         if (fl.empty()) {
-            Flight f;
-            int e = plan(f.q, nj, nw);
+            int e = launch_from_next(L, true);
             if (e) return e;
-            e = stage(f.q);
-            if (e) return e;
-            if (c->order) {
-                e = upload_rprefix();
-                if (e) return e;
-            }
-            e = launch(f.q, next_idx, L);
-            if (e) return e;
-            f.idx = next_idx++;
-            L_pred = L_after_pair(nj, nw, L);
-            advance(nj, nw);
-            fl.push_back(f);
         }
         // launch ahead
         // (not once the U already known is at or below the pair's bound:
@@ -704,17 +758,8 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
             if (free_exit ? (fl.size() >= 2 && queued >= kAheadWork)
                           : (fl.size() >= 2 || B(k, nw) > c->speculate))
                 break;
-            Flight f;
-            int e = plan(f.q, nj, nw);
+            int e = launch_from_next(L_pred, true);
             if (e) return e;
-            e = stage(f.q);
-            if (e) return e;
-            e = launch(f.q, next_idx, L_pred);
-            if (e) return e;
-            f.idx = next_idx++;
-            L_pred = L_after_pair(nj, nw, L_pred);
-            advance(nj, nw);
-            fl.push_back(f);
         }
         const Flight f = fl.front();
         fl.pop_front();
@@ -724,9 +769,11 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
         const PairPlan &pp = f.q.pp;
         const PairMail hm = c->h_mail[f.idx % kMailRing];
         last_mail = hm;
-        U_found = std::min(U_found, hm.U_found);
+        // U after this pair: the least weight of the pairs visited so far (the
+        // device's U_found may already hold a later pair of a shared launch)
+        U_found = std::min(U_found, hm.pair_min);
         const int Lb = L;
-        const bool cut = hm.exit_flag != 0 && hm.executed < B(k, w);
+        const bool cut = midpair && hm.executed < B(k, w) && !hm.cancelled;
         if (!c->term_per_level && !cut) L = bound_after(k, P.m_full, P.k_m, ng, j, w);
         mindist_pair rec{};
         rec.j = j; rec.w = w; rec.L_before = Lb; rec.L_after = L;
@@ -740,6 +787,7 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
         rec.split_b = pp.b;
         rec.split_b2 = pp.b2;
         rec.dev_ms = hm.t_end > hm.t_begin ? (double)(hm.t_end - hm.t_begin) / c->wall_hz * 1e3 : 0.0;
+        rec.launch = leader[f.idx];
         c->trace.push_back(rec);
         executed_total += hm.executed;
         canonical_total += rec.count;
@@ -758,12 +806,14 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
     HIPCHK(hipStreamSynchronize(c->stream));
     if (c->profile && pairs) {
         for (int t = 0; t < pairs; ++t) {
+            // pairs of a shared launch report that launch's time
             float ms = 0, t_ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, c->pair_ev[2 * t], c->pair_ev[2 * t + 1]));
-            HIPCHK(hipEventElapsedTime(&t_ms, c->pair_ev[0], c->pair_ev[2 * t]));
+            const int l = leader[t];
+            HIPCHK(hipEventElapsedTime(&ms, c->pair_ev[2 * l], c->pair_ev[2 * l + 1]));
+            HIPCHK(hipEventElapsedTime(&t_ms, c->pair_ev[0], c->pair_ev[2 * l]));
             c->trace[t].ms = ms;
             c->trace[t].t_start_ms = t_ms;
-            enum_s += ms * 1e-3;
+            if (l == t) enum_s += ms * 1e-3;
         }
     }
     out->n = n;
@@ -786,19 +836,34 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
         out->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         return status;
     }
-    // witness: slot[U_found], written by the wave that lowered U_found to it,
-    // reaches the host in the mailbox of the last pair read
+    // witness: slot[U_found], written by the wave that first lowered the
+    // device's U_found to it, normally reaches the host in the mailbox of the
+    // last pair read; it may come from a pair launched with the visited ones
+    // but not visited itself (any codeword of weight U_found will do)
     if (U_found != kInf) {
-        const Slot s = last_mail.witness;
-        if (last_mail.U_found != U_found || s.pair >= (uint32_t)c->trace.size())
+        Slot s = last_mail.witness;
+        if (last_mail.U_found != U_found) {
+            // a pair launched but not visited found a lower weight (possible
+            // only when the Singleton bound ends the run): read slot[U_found]
+            Slot *h = static_cast<Slot *>(pinned_alloc(sizeof(Slot)));
+            if (!h) return fail(MINDIST_E_NOMEM, "witness readback allocation failed");
+            const bool ok = hipMemcpyAsync(h, state_slots(c->d_state) + U_found, sizeof(Slot),
+                                           hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
+                            hipStreamSynchronize(c->stream) == hipSuccess;
+            s = *h;
+            pinned_free(h);
+            if (!ok) return fail(MINDIST_E_HIP, "witness readback failed");
+        }
+        if (s.pair >= (uint32_t)launched_pairs.size())
             return fail(MINDIST_E_HIP, "witness slot holds an invalid pair index");
-        const mindist_pair &pr = c->trace[s.pair];
-        const std::vector<int> rows = witness_rows(k, pr.split_a, pr.split_b, pr.split_b2, s);
-        if ((int)rows.size() != pr.w)
+        const Flight &lp = launched_pairs[s.pair];
+        const int wj = lp.q.j, ww = lp.q.w;
+        const std::vector<int> rows = witness_rows(k, lp.q.pp.a, lp.q.pp.b, lp.q.pp.b2, s);
+        if ((int)rows.size() != ww)
             return fail(MINDIST_E_HIP, "witness slot decodes to an invalid combination");
         uint64_t word[MINDIST_MAX_WORDS] = {0};
         for (int r : rows) {
-            for (int t = 0; t < P.W; ++t) word[t] ^= P.gamma[pr.j][(size_t)r * P.W + t];
+            for (int t = 0; t < P.W; ++t) word[t] ^= P.gamma[wj][(size_t)r * P.W + t];
             out->witness_rows[r >> 6] |= 1ull << (r & 63);
         }
         int wt = 0;
@@ -807,8 +872,8 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
             return fail(MINDIST_E_HIP, "witness weight " + std::to_string(wt) +
                                            " differs from the found weight " + std::to_string(U_found));
         std::memcpy(out->witness, word, sizeof(uint64_t) * P.W);
-        out->witness_j = pr.j;
-        out->witness_w = pr.w;
+        out->witness_j = wj;
+        out->witness_w = ww;
     }
     out->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     c->have_run = true;

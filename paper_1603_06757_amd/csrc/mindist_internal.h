@@ -87,7 +87,8 @@ struct PairMail {
     uint64_t pad2;
     Slot witness;          // slot[U_found] (unset while U_found = kInf)
 };
-constexpr int kMailRing = 8;
+constexpr int kMailRing = 16;
+constexpr int kGroupMax = 8;          // pairs of one launch at most
 constexpr uint32_t kMaxSlot = 512;    // witness slots 0..kMaxSlot, one per weight (n <= 512)
 
 
@@ -95,11 +96,13 @@ struct DevState {
     uint32_t U_found;      // least weight found so far in the run (kInf = none)
     uint32_t exit_flag;    // set when U_found <= the bound before the pair
     uint32_t cancelled;
-    uint32_t pad;
+    uint32_t U_base;       // U_found after the previous launch (its publish kernel
+                           // writes it; kInf before the first)
     uint64_t claimed;      // chunks claimed in the run (for cancel_after)
     uint64_t pad2;
-    // followed by Slot slots[kMaxSlot + 1] and the chunk dispensers: kCounters
-    // counters per pair, each on its own 128-byte line
+    // followed by Slot slots[kMaxSlot + 1], the chunk dispensers (kCounters
+    // counters per pair, each on its own 128-byte line) and, per pair, the
+    // least weight found by that pair and the pairs before it in its launch
 };
 
 constexpr int kCounters = 8;         // interleaved chunk dispensers per pair
@@ -107,7 +110,8 @@ constexpr int kCounterStride = 16;   // uint64 words between two counters (128 B
 
 MD_HD inline size_t state_bytes(int max_pairs) {
     return sizeof(DevState) + sizeof(Slot) * (kMaxSlot + 1) +
-           sizeof(uint64_t) * kCounters * kCounterStride * (size_t)max_pairs;
+           sizeof(uint64_t) * kCounters * kCounterStride * (size_t)max_pairs +
+           sizeof(uint32_t) * (size_t)max_pairs;
 }
 MD_HD inline Slot *state_slots(DevState *s) { return reinterpret_cast<Slot *>(s + 1); }
 // counter q of pair p
@@ -115,6 +119,10 @@ MD_HD inline uint64_t *state_counter(DevState *s, int max_pairs, int p, int q) {
     (void)max_pairs;
     uint64_t *base = reinterpret_cast<uint64_t *>(state_slots(s) + kMaxSlot + 1);
     return base + ((size_t)p * kCounters + q) * kCounterStride;
+}
+// least weight found by pair p and the pairs before it in its launch
+MD_HD inline uint32_t *state_prefix_min(DevState *s, int max_pairs) {
+    return reinterpret_cast<uint32_t *>(state_counter(s, max_pairs, max_pairs, 0));
 }
 
 struct PairArgs {
@@ -149,6 +157,18 @@ struct PairArgs {
     WavePart *parts;           // waves entries: each wave's totals
 };
 
+// One launch: up to kGroupMax consecutive pairs of Algorithm 1, pair g on
+// blocks [block_start[g], block_start[g+1]) (its own chunks, counters,
+// per-wave totals and mailbox).  Pair g is cut once the least weight of the
+// previous launches (U_base) or of pairs 0..g of this launch reaches its
+// bound: Algorithm 1 would then stop at or before pair g, so the pairs it
+// visits are enumerated exactly as one launch per pair would.
+struct GroupArgs {
+    PairArgs p[kGroupMax];
+    uint32_t block_start[kGroupMax + 1];
+    uint32_t n;                // pairs in this launch
+};
+
 // Saved sums of r-subsets: entry i is the sum of the rows of colex_unrank_r(i)
 // (left table, reflect = 0) or of the rows {k-1-shift-z} (right tables,
 // reflect = 1; shift = b2 > 0 builds the outer table of a three-level split
@@ -174,11 +194,13 @@ struct TableArgs {
 int launch_init_state(DevState *st, int max_pairs, void *stream);
 int launch_build_table(const TableArgs &ta, int D, void *stream);
 // items: lane items per chunk (2 or 4)
-int launch_enum_pair(const PairArgs &pa, int D, int items, int verify, int blocks, void *stream);
-// one block: reduce the waves' totals of pair `pair`, read the run state and
-// publish both to the mailbox (launched right behind the pair's kernel)
-int launch_publish_pair(const WavePart *parts, uint32_t waves, DevState *st, PairMail *mail,
-                        uint32_t pair, void *stream);
+// all pairs of one launch share D and the lane items
+int launch_enum_pair(const GroupArgs &ga, int D, int items, int verify, void *stream);
+// one block: reduce the waves' totals of every pair of the launch, read the
+// run state and publish them to the pairs' mailboxes (mail[pair %
+// kMailRing]), then record U_found as the next launch's U_base (launched
+// right behind the enumeration kernel)
+int launch_publish_pair(const GroupArgs &ga, PairMail *mail, void *stream);
 int max_dwords();
 int launch_peak(const uint32_t *tab, uint32_t steps, uint32_t *out, int D, int blocks, void *stream);
 

@@ -10,11 +10,24 @@
 
 namespace md {
 
+static_assert(sizeof(GroupArgs) <= 4096, "launch arguments exceed the kernel argument space");
+
 template <int D, int B, bool VERIFY>
-__global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
+__global__ __launch_bounds__(256) void enum_pair_kernel(GroupArgs ga) {
     const uint64_t t_begin = wall_clock64();
     const int lane = threadIdx.x & 63;
+    // this block's pair (blocks of a launch are laid out pair after pair)
+    uint32_t g = 0;
+    while (g + 1 < ga.n && ga.block_start[g + 1] <= blockIdx.x) ++g;
+    g = uni32(g);
+    const PairArgs &p = ga.p[g];
     Slot *slots = state_slots(p.st);
+    // the least weight this pair may be cut by: the previous launches' and
+    // that of pairs 0..g of this launch
+    uint32_t *pref = state_prefix_min(p.st, p.max_pairs);
+    const uint32_t U_base = uni32(__hip_atomic_load(&p.st->U_base, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT));
+    const uint32_t pair_end = ga.p[0].pair + ga.n;
     int gi = 0;
     // per-lane totals over all chunks of this wave, flushed once at the end
     // (per-chunk atomics on the pair record serialise in L2)
@@ -30,7 +43,8 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
     const uint32_t nq = p.counters;
     // (readfirstlane: the wave index is uniform, and everything derived from
     // the claimed chunk must stay in scalar registers for the table loads)
-    const uint32_t wave = uni32((uint32_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const uint32_t wave = uni32((uint32_t)((blockIdx.x - ga.block_start[g]) * (blockDim.x >> 6) +
+                                           (threadIdx.x >> 6)));
     const uint32_t home = wave % nq;
     // binomial columns C(x, a) and C(x, b), x <= k, for the per-lane lookups
     __shared__ uint64_t colA[kBinomX], colB[kBinomX];
@@ -64,10 +78,11 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
             ++moved;
         }
         if (!have) break;
-        U_seen = uni32(__hip_atomic_load(&p.st->U_found, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT));
+        U_seen = min(U_base, uni32(__hip_atomic_load(&pref[p.pair], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)));
         // U at or below the bound before this pair: cut short (a wave of this
-        // pair got there), or a pair launched ahead of a run that has ended
+        // pair or of an earlier pair of the launch got there), or a pair
+        // launched ahead of a run that has ended
         if (p.midpair_exit && U_seen <= p.L_prev) break;
         if (p.cancel_after) {
             uint64_t cl = 0;
@@ -120,9 +135,12 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
         const uint32_t wmin = wave_min_u32(lmin);
         const uint32_t val = wmin + p.offset;
         uint32_t old = 0;
-        if (lane == 0) old = atomicMin(&p.st->U_found, val);
+        if (lane == 0) {
+            old = atomicMin(&p.st->U_found, val);
+            for (uint32_t q = p.pair; q < pair_end; ++q) atomicMin(&pref[q], val);
+        }
         old = uni32((uint32_t)__shfl((int)old, 0));
-        U_seen = min(old, val);
+        U_seen = min(U_seen, val);
         if (old > val) {
             // this wave moved U_found to val: it alone writes slot[val]
             uint32_t hit_i, hit_i2 = 0;
@@ -152,58 +170,92 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(PairArgs p) {
     }
 }
 
-// Runs right behind a pair's launch (stream order makes every wave's totals
-// and the run state visible): one block reduces the waves' totals and
-// publishes them with the run state to the pinned mailbox, seq last.
-__global__ __launch_bounds__(1024) void publish_pair_kernel(const WavePart *parts, uint32_t waves,
-                                                            DevState *st, PairMail *m,
-                                                            uint32_t pair) {
-    uint32_t mn = kInf;
-    uint64_t ex = 0, ws = 0, t0 = ~0ull, t1 = 0;
-    for (uint32_t v = threadIdx.x; v < waves; v += blockDim.x) {
-        mn = min(mn, parts[v].pair_min);
-        ex += parts[v].executed;
-        ws += parts[v].wsum;
-        t0 = min(t0, parts[v].t0);
-        t1 = max(t1, parts[v].t1);
-    }
-    mn = wave_min_u32(mn);
-    ex = wave_sum_u64(ex);
-    ws = wave_sum_u64(ws);
-    t0 = wave_min_u64(t0);
-    t1 = wave_max_u64(t1);
+// Runs right behind a launch (stream order makes every wave's totals and the
+// run state visible): one block reduces each pair's waves' totals and
+// publishes them with the run state to the pair's pinned mailbox, sequence
+// word last; then records U_found as the next launch's U_base.
+__global__ __launch_bounds__(1024) void publish_pair_kernel(GroupArgs ga, PairMail *mails) {
     __shared__ uint32_t s_mn[16];
     __shared__ uint64_t s_ex[16], s_ws[16], s_t0[16], s_t1[16];
-    const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        s_mn[wv] = mn;
-        s_ex[wv] = ex;
-        s_ws[wv] = ws;
-        s_t0[wv] = t0;
-        s_t1[wv] = t1;
+    __shared__ uint32_t r_mn[kGroupMax];
+    __shared__ uint64_t r_ex[kGroupMax], r_ws[kGroupMax], r_t0[kGroupMax], r_t1[kGroupMax];
+    DevState *st = ga.p[0].st;
+    const int lane = threadIdx.x & 63;
+    const uint32_t nwv = blockDim.x >> 6, wv = threadIdx.x >> 6, n = ga.n;
+    // wave wv reduces pair wv % n (every pair gets nwv / n waves or one more,
+    // all pairs at once), over its entries lane + 64 * (wv / n + k * per)
+    {
+        const uint32_t g = wv % n;
+        const uint32_t per = (nwv - g + n - 1) / n;    // waves on pair g
+        const PairArgs &p = ga.p[g];
+        uint32_t mn = kInf;
+        uint64_t ex = 0, ws = 0, t0 = ~0ull, t1 = 0;
+        for (uint32_t v = lane + 64u * (wv / n); v < p.waves; v += 64u * per) {
+            mn = min(mn, p.parts[v].pair_min);
+            ex += p.parts[v].executed;
+            ws += p.parts[v].wsum;
+            t0 = min(t0, p.parts[v].t0);
+            t1 = max(t1, p.parts[v].t1);
+        }
+        mn = wave_min_u32(mn);
+        ex = wave_sum_u64(ex);
+        ws = wave_sum_u64(ws);
+        t0 = wave_min_u64(t0);
+        t1 = wave_max_u64(t1);
+        if (lane == 0) {
+            s_mn[wv] = mn;
+            s_ex[wv] = ex;
+            s_ws[wv] = ws;
+            s_t0[wv] = t0;
+            s_t1[wv] = t1;
+        }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
-            mn = min(mn, s_mn[i]);
-            ex += s_ex[i];
-            ws += s_ws[i];
-            t0 = min(t0, s_t0[i]);
-            t1 = max(t1, s_t1[i]);
+    if (threadIdx.x < n) {
+        const uint32_t g = threadIdx.x;
+        uint32_t mn = kInf;
+        uint64_t ex = 0, ws = 0, t0 = ~0ull, t1 = 0;
+        for (uint32_t w = g; w < nwv; w += n) {
+            mn = min(mn, s_mn[w]);
+            ex += s_ex[w];
+            ws += s_ws[w];
+            t0 = min(t0, s_t0[w]);
+            t1 = max(t1, s_t1[w]);
         }
-        m->t_begin = t0;
-        m->t_end = t1;
-        const uint32_t U = __hip_atomic_load(&st->U_found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        m->U_found = U;
-        if (U <= kMaxSlot) m->witness = state_slots(st)[U];
-        m->exit_flag = __hip_atomic_load(&st->exit_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        m->cancelled = __hip_atomic_load(&st->cancelled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        m->pair_min = mn;
-        m->executed = ex;
-        m->wsum = ws;
-        __threadfence_system();
-        __hip_atomic_store(&m->seq, pair + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        r_mn[g] = mn;
+        r_ex[g] = ex;
+        r_ws[g] = ws;
+        r_t0[g] = t0;
+        r_t1[g] = t1;
     }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    // the run state, the same for every pair of the launch
+    const uint32_t U = __hip_atomic_load(&st->U_found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t exit_flag = __hip_atomic_load(&st->exit_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t cancelled = __hip_atomic_load(&st->cancelled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    Slot wit{};
+    if (U <= kMaxSlot) wit = state_slots(st)[U];
+    for (uint32_t g = 0; g < ga.n; ++g) {
+        PairMail *m = mails + ga.p[g].pair % kMailRing;
+        m->t_begin = r_t0[g];
+        m->t_end = r_t1[g];
+        m->U_found = U;
+        if (U <= kMaxSlot) m->witness = wit;
+        m->exit_flag = exit_flag;
+        m->cancelled = cancelled;
+        m->pair_min = r_mn[g];
+        m->executed = r_ex[g];
+        m->wsum = r_ws[g];
+    }
+    // every mailbox's contents before any sequence word: one system fence,
+    // then relaxed stores (a release store would repeat the L2 write-back
+    // of the fence for every mailbox)
+    __threadfence_system();
+    for (uint32_t g = 0; g < ga.n; ++g)
+        __hip_atomic_store(&mails[ga.p[g].pair % kMailRing].seq, ga.p[g].pair + 1, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&st->U_base, U, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Calibration: the hot loop of enum_pair_kernel with nothing around it.
@@ -308,8 +360,11 @@ __global__ void init_state_kernel(DevState *st, int max_pairs) {
         st->U_found = kInf;
         st->exit_flag = 0;
         st->cancelled = 0;
+        st->U_base = kInf;
         st->claimed = 0;
     }
+    uint32_t *pref = state_prefix_min(st, max_pairs);
+    for (int q = tid; q < max_pairs; q += gridDim.x * blockDim.x) pref[q] = kInf;
 }
 
 // ---------------------------------------------------------------------------
@@ -346,30 +401,34 @@ int launch_build_table(const TableArgs &ta, int D, void *stream) {
 }
 
 template <int D, int B>
-static void enum_launch_b(const PairArgs &pa, int verify, int blocks, hipStream_t s) {
+static void enum_launch_b(const GroupArgs &ga, int verify, int blocks, hipStream_t s) {
     if (verify)
-        hipLaunchKernelGGL((enum_pair_kernel<D, B, true>), dim3(blocks), dim3(256), 0, s, pa);
+        hipLaunchKernelGGL((enum_pair_kernel<D, B, true>), dim3(blocks), dim3(256), 0, s, ga);
     else
-        hipLaunchKernelGGL((enum_pair_kernel<D, B, false>), dim3(blocks), dim3(256), 0, s, pa);
+        hipLaunchKernelGGL((enum_pair_kernel<D, B, false>), dim3(blocks), dim3(256), 0, s, ga);
 }
 
 template <int D>
-static void enum_launch(const PairArgs &pa, int items, int verify, int blocks, hipStream_t s) {
-    if (items == 4) enum_launch_b<D, 4>(pa, verify, blocks, s);
-    else enum_launch_b<D, 2>(pa, verify, blocks, s);
+static void enum_launch(const GroupArgs &ga, int items, int verify, int blocks, hipStream_t s) {
+    if (items == 4) enum_launch_b<D, 4>(ga, verify, blocks, s);
+    else enum_launch_b<D, 2>(ga, verify, blocks, s);
 }
 
-int launch_publish_pair(const WavePart *parts, uint32_t waves, DevState *st, PairMail *mail,
-                        uint32_t pair, void *stream) {
-    hipLaunchKernelGGL(publish_pair_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, parts,
-                       waves, st, mail, pair);
+int launch_publish_pair(const GroupArgs &ga, PairMail *mail, void *stream) {
+    hipLaunchKernelGGL(publish_pair_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, ga, mail);
     return check(hipGetLastError());
 }
 
-int launch_enum_pair(const PairArgs &pa, int D, int items, int verify, int blocks, void *stream) {
+int launch_enum_pair(const GroupArgs &ga, int D, int items, int verify, void *stream) {
     hipStream_t s = (hipStream_t)stream;
+    if (ga.n < 1 || ga.n > (uint32_t)kGroupMax || ga.block_start[0] != 0) return -1;
+    for (uint32_t g = 0; g < ga.n; ++g)
+        if (ga.block_start[g + 1] <= ga.block_start[g] || ga.p[g].pair != ga.p[0].pair + g ||
+            ga.p[g].waves != 4u * (ga.block_start[g + 1] - ga.block_start[g]))
+            return -1;
+    const int blocks = (int)ga.block_start[ga.n];
     switch (D) {
-#define MD_CASE(X) case X: enum_launch<X>(pa, items, verify, blocks, s); break;
+#define MD_CASE(X) case X: enum_launch<X>(ga, items, verify, blocks, s); break;
         MD_CASE(1) MD_CASE(2) MD_CASE(3) MD_CASE(4) MD_CASE(5) MD_CASE(6) MD_CASE(7) MD_CASE(8)
         MD_CASE(9) MD_CASE(10) MD_CASE(11) MD_CASE(12) MD_CASE(13) MD_CASE(14) MD_CASE(15)
         MD_CASE(16)

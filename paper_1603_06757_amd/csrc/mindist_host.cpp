@@ -42,6 +42,7 @@ struct GammaDev {
     int D = 0, DP = 0;         // dwords carried / stored per row
     bool stripped = false;     // identity columns removed (weight offset w)
     uint32_t *rows = nullptr;  // device, k x DP
+    uint32_t *h_rows = nullptr;   // pinned staging of rows (source of the upload)
     // saved-sum tables keyed by (kind, size, shift): kind 0 left, 1 right
     // (shift 0) or outer (shift = b2, with inner counts)
     std::map<std::tuple<int, int, int>, std::pair<uint32_t *, uint32_t *>> tabs;
@@ -109,6 +110,7 @@ static void free_ctx(mindist_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto &g : c->gd) {
         dev_free(g.rows);
+        pinned_free(g.h_rows);
         for (auto &kv : g.tabs) {
             dev_free(kv.second.first);
             dev_free(kv.second.second);
@@ -134,12 +136,16 @@ static int upload_gamma(mindist_ctx *c, int j) {
     g.stripped = full;
     g.D = (int)((cols.size() + 31) / 32);
     g.DP = dp_of_host(g.D);
-    std::vector<uint32_t> h((size_t)P.k * g.DP);
-    for (int r = 0; r < P.k; ++r) pack_row(&P.gamma[j][(size_t)r * P.W], cols, &h[(size_t)r * g.DP], g.DP);
-    g.rows = static_cast<uint32_t *>(dev_alloc(h.size() * 4));
-    if (!g.rows) return fail(MINDIST_E_NOMEM, "device allocation of Gamma rows failed");
-    HIPCHK(hipMemcpyAsync(g.rows, h.data(), h.size() * 4, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    // packed rows staged in pinned memory the context keeps, so the copy is
+    // asynchronous and creation never waits for it (kernels that read the
+    // rows follow it in stream order)
+    const size_t words = (size_t)P.k * g.DP;
+    g.h_rows = static_cast<uint32_t *>(pinned_alloc(words * 4));
+    g.rows = static_cast<uint32_t *>(dev_alloc(words * 4));
+    if (!g.rows || !g.h_rows) return fail(MINDIST_E_NOMEM, "allocation of Gamma rows failed");
+    std::memset(g.h_rows, 0, words * 4);
+    for (int r = 0; r < P.k; ++r) pack_row(&P.gamma[j][(size_t)r * P.W], cols, &g.h_rows[(size_t)r * g.DP], g.DP);
+    HIPCHK(hipMemcpyAsync(g.rows, g.h_rows, words * 4, hipMemcpyHostToDevice, c->stream));
     const Binom &B = BN();
     g.bcap = 0;
     for (int b = 1; b <= 16 && b <= P.k; ++b) {

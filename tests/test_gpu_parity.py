@@ -202,6 +202,26 @@ def test_launch_ahead_off_and_on_match_the_oracle():
         assert [p["executed"] for p in off["pairs"][:-1]] == [p["executed"] for p in on["pairs"][:-1]]
 
 
+def test_short_pairs_share_launches():
+    """Short consecutive pairs run in one launch: each record names the
+    first pair of its launch, launches hold consecutive pairs, at least one
+    holds several on [150,75]; with nothing launched ahead every pair has
+    its own launch.  The visited pairs are the same either way."""
+    w = WORKLOADS["rand150x75"]
+    G = w.matrix()
+    say("rand150x75 launches")
+    r = md.min_distance(G, w.n, w.k)
+    launch = [p["launch"] for p in r["pairs"]]
+    assert launch[0] == 0
+    for i, l in enumerate(launch):
+        assert l <= i and (i == 0 or l in (launch[i - 1], i))
+    assert len(set(launch)) < len(launch)
+    off = md.min_distance(G, w.n, w.k, speculate=0)
+    assert [p["launch"] for p in off["pairs"]] == list(range(len(off["pairs"])))
+    key = lambda x: [(p["j"], p["w"], p["pair_min"], p["L_before"], p["L_after"]) for p in x["pairs"]]
+    assert key(r) == key(off) and r["d"] == off["d"]
+
+
 def test_device_clock_pair_times_agree_with_events():
     """Every pair reports its kernel's span on the device clock (first wave
     start to last wave end); it is positive and no longer than the HIP-event

@@ -287,7 +287,7 @@ int mindist_run_batch(const uint64_t *const *G, const int *n, const int *k, int 
 typedef struct mindist_server mindist_server;
 
 typedef struct mindist_server_opts {
-    int32_t max_active;       /* codes running at once: engine 0, worker threads (0 = 4);
+    int32_t max_active;       /* codes running at once: engine 0, worker threads (0 = 8);
                                  engine 1, code slots resident on the device (0 = 256) */
     int32_t blocks_per_cu;    /* resident workgroups per CU (0 = 4) */
     int64_t device_bytes;     /* device memory for the codes in flight: a code is admitted

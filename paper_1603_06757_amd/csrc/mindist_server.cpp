@@ -445,7 +445,7 @@ extern "C" int mindist_server_create(const mindist_server_opts *opts, mindist_se
     if (opts) S->o = *opts;
     if (S->o.engine != 0 && S->o.engine != 1) return fail(MINDIST_E_ARG, "engine must be 0 or 1");
     if (S->o.engine == 0) {
-        const int workers = S->o.max_active > 0 ? S->o.max_active : 4;
+        const int workers = S->o.max_active > 0 ? S->o.max_active : 8;
         if (workers > 256) return fail(MINDIST_E_ARG, "max_active too large for engine 0 (at most 256 workers)");
         if (hipGetDevice(&S->device) != hipSuccess) return fail(MINDIST_E_HIP, "no HIP device");
         // warm the process-wide caches the first codes would otherwise pay

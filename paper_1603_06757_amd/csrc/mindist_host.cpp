@@ -451,7 +451,7 @@ PairPlan plan_pair(const mindist_ctx *c, int j, int w, GroupEntry *groups,
 
 }  // namespace
 
-extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
+static int run_impl(mindist_ctx *c, mindist_result *out) {
     if (!c || !out) return fail(MINDIST_E_ARG, "NULL argument");
     const auto t0 = std::chrono::steady_clock::now();
     const Plan &P = c->P;
@@ -884,6 +884,14 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
     out->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     c->have_run = true;
     return MINDIST_OK;
+}
+
+extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
+    const int e = run_impl(c, out);
+    // no launch of a run may outlive it: the next run reuses its mailboxes
+    // (a stale publish could otherwise land in one it waits on)
+    if (e != MINDIST_OK && c && c->stream) (void)hipStreamSynchronize(c->stream);
+    return e;
 }
 
 extern "C" int mindist_get_pairs(const mindist_ctx *c, mindist_pair *out, int cap, int *n_out) {

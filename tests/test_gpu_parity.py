@@ -376,3 +376,12 @@ def test_cancel_and_deadline():
         with pytest.raises(md.MindistError) as e:
             m.run()
         assert e.value.code == -7
+        # a run that stopped with pairs queued leaves nothing behind: the
+        # next runs on the context (pairs launched ahead and shared launches
+        # reusing its mailboxes) give the full result
+        m.set_option("deadline_ms", 0)
+        gold = json.load(open(os.path.join(GOLDEN, "rand150x75.json")))
+        for _ in range(2):
+            r = m.run()
+            assert r["d"] == gold["d"]
+            compare_with_trace(r, gold["trace"], gold["counts"], gold["pair_min"], None, w.k)

@@ -207,7 +207,8 @@ int mindist_bound_after(int k, int m_full, int k_partial, int include_partial,
 
 /* ---- batches: many codes in one persistent launch ---------------------- */
 typedef struct mindist_batch_opts {
-    int32_t tile_min;         /* right-tile length bounds (0 = 256 / 2048) */
+    int32_t tile_min;         /* right-tile length bounds (0 = 2048 / 4096; the maximum is raised
+                                 to the minimum if below it) */
     int32_t tile_max;
     int32_t blocks_per_cu;    /* resident workgroups per CU (0 = 4) */
     int32_t use_graph;        /* 1 = run as one captured hipGraph (default), 0 = plain launch */

@@ -6,7 +6,9 @@ depend on the mix of codes:
 * ``chunks_per_visit`` -- chunks a wave runs on one code's job before it
   moves on to the next code with work: the share of waves each live code
   gets (small = fair to short codes, large = fewer completions);
-* ``tile_max`` -- the longest right tile of a chunk (chunk size);
+* ``tile_min``, ``tile_max`` -- the shortest and longest right tile of a
+  chunk (chunk size; short codes want long minimum tiles, their per-chunk
+  set-up otherwise dominates);
 * ``blocks_per_cu`` -- resident workgroups per CU (occupancy).
 
 Words per row are not tuned: each code carries the fewest 32-bit words its
@@ -28,11 +30,12 @@ import time
 from . import run_batch
 
 SEARCH = [
+    ("tile_min", [256, 1024, 2048, 4096]),
     ("chunks_per_visit", [1, 2, 4, 8, -1]),
-    ("tile_max", [1024, 2048, 4096, 8192]),
+    ("tile_max", [2048, 4096, 8192]),
     ("blocks_per_cu", [2, 3, 4]),
 ]
-DEFAULT = {"chunks_per_visit": 4, "tile_max": 2048, "blocks_per_cu": 4}
+DEFAULT = {"chunks_per_visit": 4, "tile_min": 2048, "tile_max": 4096, "blocks_per_cu": 4}
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1603_06757_amd", "autotune.json")
 
 
@@ -70,6 +73,8 @@ def tune(codes, repeats: int = 1, log=None) -> dict:
                 continue
             cand = dict(best)
             cand[name] = v
+            if cand["tile_min"] > cand["tile_max"]:
+                continue
             t = measure(cand)
             if t is not None and t < best_t:
                 best, best_t = cand, t

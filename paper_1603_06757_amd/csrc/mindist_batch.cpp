@@ -350,8 +350,11 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
     if (!G || !n || !k || !out || B < 1) return fail(MINDIST_E_ARG, "bad batch arguments");
     mindist_batch_opts dflt{};
     mindist_batch_opts &o = opts ? *opts : dflt;
-    const uint32_t tile_min = o.tile_min > 0 ? (uint32_t)o.tile_min : 256u;
-    const uint32_t tile_max = o.tile_max > 0 ? (uint32_t)o.tile_max : 2048u;
+    // right-tile bounds: at least 2048 entries, so a short pair's left tile
+    // is one chunk (per-chunk set-up -- claim, left-subset unranking,
+    // reductions -- dominated short codes at 256)
+    const uint32_t tile_min = o.tile_min > 0 ? (uint32_t)o.tile_min : 2048u;
+    const uint32_t tile_max = std::max(tile_min, o.tile_max > 0 ? (uint32_t)o.tile_max : 4096u);
     const int bpc = o.blocks_per_cu > 0 ? o.blocks_per_cu : 4;
     const uint64_t table_cap = (uint64_t)(o.table_kib > 0 ? o.table_kib : 65536) << 10;
     const int jobs_per_code = o.jobs_per_code > 0 ? o.jobs_per_code : 96;

@@ -246,7 +246,7 @@ int upload_fresh(mindist_server *S, const uint32_t tile_max) {
 
 void manager(mindist_server *S) {
     (void)hipSetDevice(S->device);
-    const uint32_t tile_min = 256, tile_max = 2048;
+    const uint32_t tile_min = 2048, tile_max = 4096;   // as the batch defaults
     const int bpc_req = S->o.blocks_per_cu > 0 ? S->o.blocks_per_cu : 4;
     const int resident_bpc = persistent_resident_blocks_per_cu();
     const int blocks = S->cus * (resident_bpc > 0 && bpc_req > resident_bpc ? resident_bpc : bpc_req);

@@ -19,6 +19,7 @@ Prints one JSON line:
   serving    open-loop Poisson arrivals of the serving stream at one rate:
              p50/p99 latency and codes/s (requests above a work cap are left
              out and counted); --serving-sweep runs the whole rate sweep
+--new-codes certifies the codes of Section 6 instead (one line per code).
 """
 from __future__ import annotations
 
@@ -281,6 +282,46 @@ def serving_leg(rate: float, seconds: float, cap: float, max_requests: int = 400
             "epochs": st["epochs"], "kernel_s": st["seconds_kernel"]}
 
 
+# Section 6's timings of its best CPU implementation (vectorised saved
+# additions) on its own machine, seconds on 1 core and on 6 cores: context
+# for the GPU times, not a target measured here.
+PAPER_CPU_S = {
+    "mp235x51": (234890.8, 38428.5),
+    "mp236x51": (231345.5, 38497.1),
+    "mp233x51": (159470.8, 26725.6),
+    "mp233x52": (225141.2, 37660.1),
+    "mp232x51": (125695.6, 20691.6),
+}
+
+
+def new_codes_leg(names):
+    """Section 6's codes through the single-code path, one fresh context
+    each: d against the claimed distance, time, codewords and the share of
+    the VALU peak (every pair's codewords times its 32-bit words)."""
+    import paper_1603_06757_amd as md
+    from paper_1603_06757_amd.newcodes import NEW_CODES
+    out = []
+    for name in names or list(NEW_CODES):
+        c = NEW_CODES[name]
+        G = c.matrix()
+        print(f"[bench] section 6 code {name} [{c.n},{c.k}]", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        r = md.min_distance(G, c.n, c.k)
+        dt = time.perf_counter() - t0
+        ops = sum(p["executed"] * p["dwords"] for p in r["pairs"])
+        rec = {"new_code": name, "n": c.n, "k": c.k, "d": r["d"], "d_claimed": c.d,
+               "d_previously_known": c.d_before, "certified": r["d"] == c.d,
+               "seconds": dt, "pairs": r["pairs_visited"], "codewords": r["executed_total"],
+               "codewords_per_s": r["executed_total"] / dt,
+               "valu_frac": ops / dt / PEAK_DWORD_OPS}
+        if name in PAPER_CPU_S:
+            one, six = PAPER_CPU_S[name]
+            rec["paper_cpu_s"] = {"1_core": one, "6_cores": six}
+        out.append(rec)
+        print(json.dumps(rec), flush=True)
+    return out
+
+
 def copy_probe(mib: int):
     """Plain device-to-device copies of a known size: the reference reading
     for the FETCH_SIZE / WRITE_SIZE counters (each copy reads and writes
@@ -314,6 +355,9 @@ def main():
                     help="only run the serving sweep (one JSON line per arrival rate) and exit")
     ap.add_argument("--serving-cap", type=float, default=2e10,
                     help="serving: leave out requests above this many estimated codewords")
+    ap.add_argument("--new-codes", nargs="*", default=None,
+                    help="only certify Section 6's codes (all, or the names given; "
+                         "one JSON line per code) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
         print("this benchmark runs on one GPU only (single-GPU build); use --gpus 1",
@@ -321,6 +365,9 @@ def main():
         sys.exit(2)
     if a.copy_probe_mib:
         copy_probe(a.copy_probe_mib)
+        return
+    if a.new_codes is not None:
+        new_codes_leg(a.new_codes)
         return
     if a.serving_sweep:
         for engine in (0, 1):

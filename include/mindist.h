@@ -78,7 +78,7 @@ extern "C" {
  * have been claimed; 0 = off. */
 #define MINDIST_OPT_CANCEL_AFTER_CHUNKS 10
 /* cap on the saved right-sum table of one (Gamma_j, size) in MiB
- * (default 256). */
+ * (default 1024). */
 #define MINDIST_OPT_TABLE_MIB        11
 /* kernel shape: left subsets held per lane in one chunk (2 or 4, default 4). */
 #define MINDIST_OPT_LANE_ITEMS       12
@@ -300,7 +300,8 @@ typedef struct mindist_server_opts {
                                  whose share exceeds it */
     double  epoch_min_ms;     /* least running time of a launch before waiting codes are
                                  admitted (0 = 0.5 ms) */
-    int32_t table_kib;        /* cap on one saved table in KiB (0 = 65536) */
+    int32_t table_kib;        /* cap on one saved table in KiB (0 = the single-code path's
+                                 1 GiB for engine 0, 65536 for engine 1) */
     int32_t jobs_per_code;    /* job records per slot (0 = 96); a code needing more ends
                                  with MINDIST_E_LIMIT */
     int32_t chunks_per_visit; /* as in mindist_batch_opts (0 = 4) */

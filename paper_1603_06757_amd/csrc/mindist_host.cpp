@@ -74,7 +74,7 @@ struct mindist_ctx {
     int order = 0;             // chunk order: 0 left-tile-major, 1 right-tile-major
     int counters = kCounters;  // chunk dispensers (1 or kCounters)
     int left_tables = 1;       // read left subsets from saved tables when they fit
-    uint64_t table_cap = 256ull << 20;
+    uint64_t table_cap = kTableCapDefault;
     uint64_t min_items = 0;    // left subsets a pair's split should give (0 = balanced split)
     uint64_t speculate = 1ull << 28;   // launch the next pair before the current one's result
                                        // is read when it has at most this many combinations

@@ -31,6 +31,11 @@ struct Binom {
 };
 const Binom &BN();
 
+// default cap on one saved-sum table of the single-code path: 1 GiB keeps
+// six-row right tables of k ~ 51 (576 MB at 8 words per entry), whose longer
+// right runs lift the w >= 12 pairs of such codes by 4-12 %
+constexpr uint64_t kTableCapDefault = 1ull << 30;
+
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline int bit_of(const uint64_t *row, int c) { return (int)((row[c >> 6] >> (c & 63)) & 1u); }
 inline int dp_of_host(int D) { return D <= 1 ? 1 : D <= 2 ? 2 : D <= 4 ? 4 : D <= 8 ? 8 : 16; }

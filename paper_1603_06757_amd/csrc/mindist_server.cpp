@@ -528,7 +528,7 @@ extern "C" int mindist_server_submit(mindist_server *S, const uint64_t *G, int n
         // once); the worker plans again inside mindist_create.  Footprint:
         // rows, right and left saved tables up to the levels the estimated
         // distance needs (within the table cap), and the run's state.
-        const uint64_t table_cap = (uint64_t)(S->o.table_kib > 0 ? S->o.table_kib : 262144) << 10;
+        const uint64_t table_cap = S->o.table_kib > 0 ? (uint64_t)S->o.table_kib << 10 : kTableCapDefault;
         int e = single_path_bytes(G, n, k, table_cap, r->bytes);
         if (e) return e;
         if (r->bytes > S->bytes_budget) return fail(MINDIST_E_NOMEM, "code does not fit the server's device memory");

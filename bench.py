@@ -19,7 +19,8 @@ Prints one JSON line:
   serving    open-loop Poisson arrivals of the serving stream at one rate:
              p50/p99 latency and codes/s (requests above a work cap are left
              out and counted); --serving-sweep runs the whole rate sweep
---new-codes certifies the codes of Section 6 instead (one line per code).
+--new-codes certifies the codes of Section 6 instead (one line per code);
+--paper-random runs seeded codes of the random sizes the paper times.
 """
 from __future__ import annotations
 
@@ -322,6 +323,62 @@ def new_codes_leg(names):
     return out
 
 
+# The paper's times for its random codes on one AMD Opteron 6128 (2.0 GHz)
+# machine, seconds: vectorised saved additions on 1 core (Table 2) and on 6
+# cores (Table 4), Magma on 6 cores (Table 4).  Context only: its matrices
+# are unpublished, the codes run here are seeded stand-ins of the same size.
+PAPER_RANDOM_S = {
+    (150, 50): (38.9, 7.8, 29.3),
+    (130, 67): (331.3, 64.9, 345.3),
+    (115, 63): (755.1, 134.2, 860.5),
+    (102, 62): (3047.5, 525.1, 3659.8),
+    (150, 77): (10245.4, 1763.1, 9562.8),
+}
+
+
+def paper_random_leg(repeats: int = 3, attempts: int = 64):
+    """Seeded random codes of the sizes the paper times, whole single-code
+    path (fresh context each run, best of `repeats`), next to its times.
+    Work grows steeply with d, so of the first `attempts` seeded matrices of
+    each size the first whose distance equals the paper's code is timed (the
+    closest one if none does)."""
+    import paper_1603_06757_amd as md
+    from paper_1603_06757_amd.gen import PAPER_RANDOM_SIZES, paper_random_code
+    out = []
+    for n, k, d_paper in PAPER_RANDOM_SIZES:
+        pick = None                               # (|d - d_paper|, attempt, G)
+        for attempt in range(attempts):
+            G = paper_random_code(n, k, attempt)
+            try:
+                d = md.min_distance(G, n, k)["d"]
+            except md.MindistError as e:
+                if e.code != -2:                  # rank-deficient draws are skipped
+                    raise
+                continue
+            if pick is None or abs(d - d_paper) < pick[0]:
+                pick = (abs(d - d_paper), attempt, G)
+            if d == d_paper:
+                break
+        _, attempt, G = pick
+        best, r = None, None
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            r = md.min_distance(G, n, k)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        one, six, magma6 = PAPER_RANDOM_S[(n, k)]
+        rec = {"paper_random": f"[{n},{k}]", "seed": 6, "stream": 1000 * n + k, "attempt": attempt,
+               "d": r["d"], "d_paper_code": d_paper,
+               "seconds": best, "codewords": r["executed_total"],
+               "codewords_per_s": r["executed_total"] / best,
+               "paper_s": {"vector_saved_1_core": one, "vector_saved_6_cores": six,
+                           "magma_6_cores": magma6,
+                           "machine": "AMD Opteron 6128, 2.0 GHz (cplex)"}}
+        out.append(rec)
+        print(json.dumps(rec), flush=True)
+    return out
+
+
 def copy_probe(mib: int):
     """Plain device-to-device copies of a known size: the reference reading
     for the FETCH_SIZE / WRITE_SIZE counters (each copy reads and writes
@@ -355,6 +412,9 @@ def main():
                     help="only run the serving sweep (one JSON line per arrival rate) and exit")
     ap.add_argument("--serving-cap", type=float, default=2e10,
                     help="serving: leave out requests above this many estimated codewords")
+    ap.add_argument("--paper-random", action="store_true",
+                    help="only run seeded random codes of the sizes the paper times "
+                         "(one JSON line per size, with the paper's CPU times) and exit")
     ap.add_argument("--new-codes", nargs="*", default=None,
                     help="only certify Section 6's codes (all, or the names given; "
                          "one JSON line per code) and exit")
@@ -365,6 +425,9 @@ def main():
         sys.exit(2)
     if a.copy_probe_mib:
         copy_probe(a.copy_probe_mib)
+        return
+    if a.paper_random:
+        paper_random_leg()
         return
     if a.new_codes is not None:
         new_codes_leg(a.new_codes)

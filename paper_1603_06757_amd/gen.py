@@ -155,6 +155,17 @@ WORKLOADS = {
 }
 
 
+# Sizes of the random codes the paper times (Tables 1, 2 and 4), with the
+# distance it reports.  Their matrices are not published; paper_random_code
+# draws a seeded stand-in of the same [n, k] (seed 6, stream 1000 n + k).
+PAPER_RANDOM_SIZES = ((150, 50, 28), (130, 67, 15), (115, 63, 11), (102, 62, 12), (150, 77, 17))
+
+
+def paper_random_code(n: int, k: int, attempt: int = 0) -> np.ndarray:
+    """Attempt `attempt` of the seeded stand-in for the paper's random [n, k]."""
+    return random_generator(n, k, 6, 1000 * n + k, attempt)
+
+
 def batch_code(index: int, seed: int = 4, n_lo: int = 64, n_hi: int = 160):
     """Code `index` of the batch stream: n ~ U{n_lo..n_hi},
     k ~ U{ceil(n/4)..floor(n/2)}, then the k x n matrix (stream = index)."""

@@ -20,7 +20,8 @@ Prints one JSON line:
              p50/p99 latency and codes/s (requests above a work cap are left
              out and counted); --serving-sweep runs the whole rate sweep
 --new-codes certifies the codes of Section 6 instead (one line per code);
---paper-random runs seeded codes of the random sizes the paper times.
+--paper-random runs seeded codes of the random sizes the paper times;
+--compare-walk measures the saved-sums kernel against the direct walk.
 """
 from __future__ import annotations
 
@@ -379,6 +380,38 @@ def paper_random_leg(repeats: int = 3, attempts: int = 64):
     return out
 
 
+def walk_compare_leg(repeats: int = 3):
+    """The saved-sums kernel against the per-lane lexicographic walk
+    (mindist_walk_pair) on the same pairs of [150,75]: codewords/s of each,
+    the walk's best of `repeats` launches, the saved-sums kernel's pair time
+    from the device clock in a full run."""
+    import paper_1603_06757_amd as md
+    from paper_1603_06757_amd.gen import WORKLOADS
+    w = WORKLOADS["rand150x75"]
+    out = []
+    with md.MinDist(w.matrix(), w.n, w.k) as m:
+        m.run()                                   # tables and shapes built
+        res = m.run()
+        for p in res["pairs"]:
+            if p["w"] < 6 or p["executed"] != p["count"]:
+                continue
+            best = None
+            for _ in range(repeats):
+                r = m.walk_pair(p["j"], p["w"])
+                assert r["pair_min"] == p["pair_min"] and r["executed"] == p["count"]
+                best = r["seconds"] if best is None else min(best, r["seconds"])
+            saved = p["count"] / (p["dev_ms"] * 1e-3)
+            walk = p["count"] / best
+            rec = {"walk_compare": f"[{w.n},{w.k}] pair (j={p['j']}, w={p['w']})",
+                   "combinations": p["count"], "dwords": p["dwords"],
+                   "saved_sums_codewords_per_s": saved, "walk_codewords_per_s": walk,
+                   "saved_over_walk": saved / walk,
+                   "walk_frac_of_peak": walk * p["dwords"] / PEAK_DWORD_OPS}
+            out.append(rec)
+            print(json.dumps(rec), flush=True)
+    return out
+
+
 def copy_probe(mib: int):
     """Plain device-to-device copies of a known size: the reference reading
     for the FETCH_SIZE / WRITE_SIZE counters (each copy reads and writes
@@ -412,6 +445,9 @@ def main():
                     help="only run the serving sweep (one JSON line per arrival rate) and exit")
     ap.add_argument("--serving-cap", type=float, default=2e10,
                     help="serving: leave out requests above this many estimated codewords")
+    ap.add_argument("--compare-walk", action="store_true",
+                    help="only compare the saved-sums kernel with the lexicographic walk "
+                         "kernel on the pairs of [150,75] with w >= 6, and exit")
     ap.add_argument("--paper-random", action="store_true",
                     help="only run seeded random codes of the sizes the paper times "
                          "(one JSON line per size, with the paper's CPU times) and exit")
@@ -425,6 +461,9 @@ def main():
         sys.exit(2)
     if a.copy_probe_mib:
         copy_probe(a.copy_probe_mib)
+        return
+    if a.compare_walk:
+        walk_compare_leg()
         return
     if a.paper_random:
         paper_random_leg()

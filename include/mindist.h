@@ -183,9 +183,26 @@ const char *mindist_last_error(void);
  * 32-bit XOR + popcount per carried word and a min per codeword, right sums
  * from scalar loads) over registers and a 64-entry table, on every CU, with
  * no setup, tails or atomics.  Reports codewords/s for `dwords` carried
- * words per codeword (1, 2, 3, 4, 7 or 8): the measured ceiling that the
- * enumeration's achieved rate is compared against. */
+ * words per codeword (1, 2, 3, 4, 7 or 8).  A reference for the instruction
+ * mix, not a ceiling: on gfx950 the enumeration kernel itself runs 5-10 %
+ * faster (its right runs are longer than the table walked here). */
 int mindist_calibrate(int dwords, int blocks_per_cu, double *codewords_per_s, double *seconds);
+
+/* Comparison kernel for one pair (Gamma_j, w) of a created context (Section
+ * 3.3, the stack-based enumeration of Algorithm 4, as a GPU walk): every
+ * lane unranks its own start in lexicographic order (combinatorial number
+ * system) and walks consecutive w-subsets, the last element moving fastest
+ * over rows held in LDS, one row addition per codeword plus the partial
+ * sums rebuilt at each carry.  It only measures that direct walk against
+ * the saved-sums kernel that mindist_run uses; it changes no state of the
+ * context.  j indexes the enumerated sets (full sets in order, then the
+ * partial set), 1 <= w <= 12, k <= 128 and at most 4 carried 32-bit words
+ * per row (n - k <= 128 for a full set, n <= 128 for the partial set), else
+ * MINDIST_E_LIMIT.  blocks_per_cu 0 = 4 (at most 16).  Outputs: the least
+ * weight of the pair, the combinations evaluated (C(k, w)) and the kernel
+ * time from HIP events; executed and seconds may be NULL.  Blocking. */
+int mindist_walk_pair(mindist_ctx *ctx, int j, int w, int blocks_per_cu, int32_t *pair_min,
+                      uint64_t *executed, double *seconds);
 
 /* The current HIP device: its architecture name (e.g. "gfx950", written to
  * name with at most cap bytes including the terminator) and its compute

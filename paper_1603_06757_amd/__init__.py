@@ -130,6 +130,8 @@ def lib():
         L.mindist_calibrate.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
         L.mindist_device.argtypes = [C.c_char_p, C.c_int, ip]
+        L.mindist_walk_pair.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int32),
+                                        u64p, C.POINTER(C.c_double)]
         if hasattr(L, "mindist_run_batch"):
             L.mindist_run_batch.argtypes = [C.POINTER(u64p), ip, ip, C.c_int,
                                             C.POINTER(Result), C.POINTER(BatchOpts)]
@@ -224,6 +226,13 @@ class MinDist:
         out = r.to_dict()
         out["pairs"] = self.pairs()
         return out
+
+    def walk_pair(self, j: int, w: int, blocks_per_cu: int = 0) -> dict:
+        """Pair (Gamma_j, w) by the lexicographic walk kernel (comparison only)."""
+        pm, ex, sec = C.c_int32(), C.c_uint64(), C.c_double()
+        _check(lib().mindist_walk_pair(self._h, j, w, blocks_per_cu, C.byref(pm), C.byref(ex),
+                                       C.byref(sec)))
+        return {"pair_min": pm.value, "executed": ex.value, "seconds": sec.value}
 
     def pairs(self):
         cnt = C.c_int()

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmindist.so")
 
-SOURCES = ["mindist_kernels.hip", "mindist_batch.hip", "mindist_plan.cpp", "mindist_host.cpp",
+SOURCES = ["mindist_kernels.hip", "mindist_batch.hip", "mindist_walk.hip", "mindist_plan.cpp", "mindist_host.cpp",
            "mindist_pool.cpp", "mindist_batch.cpp", "mindist_server.cpp"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.

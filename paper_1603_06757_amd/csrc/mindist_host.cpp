@@ -20,6 +20,7 @@
 #include "mindist_internal.h"
 #include "mindist_plan.h"
 #include "mindist_pool.h"
+#include "mindist_walk.h"
 
 using namespace md;
 
@@ -942,6 +943,53 @@ extern "C" int mindist_calibrate(int dwords, int blocks_per_cu, double *codeword
     event_put(e0);
     event_put(e1);
     return rc;
+}
+
+extern "C" int mindist_walk_pair(mindist_ctx *c, int j, int w, int blocks_per_cu, int32_t *pair_min,
+                                 uint64_t *executed, double *seconds) {
+    if (!c || !pair_min) return fail(MINDIST_E_ARG, "NULL argument");
+    if (j < 0 || j >= c->n_gamma) return fail(MINDIST_E_ARG, "walk: no such information set");
+    const GammaDev &g = c->gd[j];
+    const int k = c->P.k;
+    if (w < 1 || w > k) return fail(MINDIST_E_ARG, "walk: need 1 <= w <= k");
+    if (w > kWalkMaxW || k > kWalkMaxK || g.D > kWalkMaxD)
+        return fail(MINDIST_E_LIMIT, "walk: needs w <= 12, k <= 128 and at most 4 carried words");
+    if (blocks_per_cu < 0 || blocks_per_cu > 16) return fail(MINDIST_E_ARG, "walk: blocks_per_cu in 0..16");
+    const int bpc = blocks_per_cu > 0 ? blocks_per_cu : 4;
+    const uint64_t total = BN()(k, w);
+    const uint64_t threads = (uint64_t)c->cus * bpc * 256;
+    WalkArgs a{};
+    a.rows = g.rows;
+    a.binom = c->d_binom;
+    a.total = total;
+    a.per_thread = ceil_div(total, threads);
+    a.k = k;
+    a.w = w;
+    a.offset = g.stripped ? (uint32_t)w : 0u;
+    a.out = static_cast<WalkOut *>(dev_alloc(sizeof(WalkOut)));
+    hipEvent_t e0 = event_get(), e1 = event_get();
+    WalkOut res{kInf, 0, 0};
+    int rc = MINDIST_OK;
+    float ms = 0;
+    if (!a.out || !e0 || !e1) rc = fail(MINDIST_E_NOMEM, "walk: allocation failed");
+    if (rc == MINDIST_OK &&
+        (hipMemcpyAsync(a.out, &res, sizeof(res), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+         hipEventRecord(e0, c->stream) != hipSuccess ||
+         launch_walk_pair(a, g.D, c->cus * bpc, c->stream) != 0 ||
+         hipEventRecord(e1, c->stream) != hipSuccess ||
+         hipMemcpyAsync(&res, a.out, sizeof(res), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+         hipStreamSynchronize(c->stream) != hipSuccess ||
+         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(MINDIST_E_HIP, "walk: kernel failed");
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    dev_free(a.out);
+    event_put(e0);
+    event_put(e1);
+    if (rc) return rc;
+    *pair_min = res.min_weight == kInf ? -1 : (int32_t)res.min_weight;
+    if (executed) *executed = res.executed;
+    if (seconds) *seconds = ms * 1e-3;
+    return MINDIST_OK;
 }
 
 extern "C" int mindist_device(char *name, int cap, int *compute_units) {

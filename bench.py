@@ -21,7 +21,8 @@ Prints one JSON line:
              out and counted); --serving-sweep runs the whole rate sweep
 --new-codes certifies the codes of Section 6 instead (one line per code);
 --paper-random runs seeded codes of the random sizes the paper times;
---compare-walk measures the saved-sums kernel against the direct walk.
+--compare-walk measures the saved-sums kernel against the direct walk;
+--cpu-family times the paper's CPU algorithms on the host (Table 1's code size).
 """
 from __future__ import annotations
 
@@ -412,6 +413,56 @@ def walk_compare_leg(repeats: int = 3):
     return out
 
 
+# Table 1: the whole run on the paper's random [150,50,28], one core, seconds
+PAPER_TABLE1_S = {
+    "basic": (511.5, 273.1), "optimized": (191.0, 105.3), "stack": (144.5, 84.6),
+    "saved": (89.8, 44.7), "saved_unroll2": (74.0, 44.6),
+}
+
+
+def cpu_family_leg(threads: int = 0):
+    """The paper's CPU algorithms (libmindist_cpu.so) over the pairs that
+    Algorithm 1 visits on the seeded [150,50] stand-in with d = 28 (the GPU
+    run gives the pair list and the minima they must reproduce), on the
+    host's cores, next to Table 1's one-core times."""
+    import paper_1603_06757_amd as md
+    from paper_1603_06757_amd import cpu
+    from paper_1603_06757_amd.gen import paper_random_code
+    n, k, attempt = 150, 50, 4
+    G = paper_random_code(n, k, attempt)
+    md.min_distance(G, n, k)
+    t0 = time.perf_counter()
+    r = md.min_distance(G, n, k)
+    t_gpu = time.perf_counter() - t0
+    full, part, gam = md.plan(G, n, k)
+    threads = threads or min(16, os.cpu_count() or 1)
+    out, t_basic = [], None
+    for alg in cpu.ALGORITHMS:
+        t0 = time.perf_counter()
+        tables = adds = combos = 0
+        for p in r["pairs"]:
+            c = cpu.cpu_pair(gam[p["j"]], k, p["w"], alg, s=5, threads=threads)
+            if p["executed"] == p["count"]:
+                assert c["pair_min"] == p["pair_min"], (alg, p)
+            assert c["pair_min"] >= r["d"]
+            tables += c["table_seconds"]
+            adds += c["additions"]
+            combos += c["combinations"]
+        dt = time.perf_counter() - t0
+        t_basic = t_basic or dt
+        rec = {"cpu_family": alg, "code": f"[{n},{k}] d={r['d']} (seed 6, stream {1000 * n + k}, attempt {attempt})",
+               "pairs": len(r["pairs"]), "threads": threads, "seconds": dt,
+               "table_seconds": tables, "combinations": combos, "additions": adds,
+               "codewords_per_s": combos / dt, "speedup_vs_basic": t_basic / dt,
+               "paper_table1_1_core_s": {"cplex_opteron_6128": PAPER_TABLE1_S[alg][0],
+                                         "marbore_xeon_e5_2695v3": PAPER_TABLE1_S[alg][1]},
+               "paper_speedup_vs_basic_cplex": PAPER_TABLE1_S["basic"][0] / PAPER_TABLE1_S[alg][0],
+               "gpu_seconds_same_code": t_gpu}
+        out.append(rec)
+        print(json.dumps(rec), flush=True)
+    return out
+
+
 def copy_probe(mib: int):
     """Plain device-to-device copies of a known size: the reference reading
     for the FETCH_SIZE / WRITE_SIZE counters (each copy reads and writes
@@ -445,6 +496,9 @@ def main():
                     help="only run the serving sweep (one JSON line per arrival rate) and exit")
     ap.add_argument("--serving-cap", type=float, default=2e10,
                     help="serving: leave out requests above this many estimated codewords")
+    ap.add_argument("--cpu-family", action="store_true",
+                    help="only time the paper's CPU algorithms (libmindist_cpu.so) on the "
+                         "seeded [150,50,28] code's pairs, next to Table 1, and exit")
     ap.add_argument("--compare-walk", action="store_true",
                     help="only compare the saved-sums kernel with the lexicographic walk "
                          "kernel on the pairs of [150,75] with w >= 6, and exit")
@@ -461,6 +515,9 @@ def main():
         sys.exit(2)
     if a.copy_probe_mib:
         copy_probe(a.copy_probe_mib)
+        return
+    if a.cpu_family:
+        cpu_family_leg()
         return
     if a.compare_walk:
         walk_compare_leg()

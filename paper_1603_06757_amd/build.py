@@ -1,4 +1,6 @@
-"""Build libmindist.so (HIP kernels for gfx950 + host scheduler + C ABI).
+"""Build libmindist.so (HIP kernels for gfx950 + host scheduler + C ABI)
+and libmindist_cpu.so (the paper's CPU algorithms as host baselines, plain C
+with OpenMP; the GPU library does not link or call it).
 
     python -m paper_1603_06757_amd.build
 """
@@ -12,6 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmindist.so")
+CPU_LIB = os.path.join(HERE, "libmindist_cpu.so")
+# x86-64 with POPCNT: the library runs on whichever host drives the GPU
+CPU_FLAGS = ["-O3", "-fPIC", "-shared", "-fopenmp", "-mpopcnt", "-std=c11"]
 
 SOURCES = ["mindist_kernels.hip", "mindist_batch.hip", "mindist_walk.hip", "mindist_plan.cpp", "mindist_host.cpp",
            "mindist_pool.cpp", "mindist_batch.cpp", "mindist_server.cpp"]
@@ -35,7 +40,22 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libmindist.so")
     os.replace(tmp, LIB)
+    build_cpu(verbose)
     return LIB
+
+
+def build_cpu(verbose: bool = False) -> str:
+    tmp = CPU_LIB + ".tmp"
+    cmd = ["gcc", *CPU_FLAGS, "-I", os.path.join(ROOT, "include"),
+           os.path.join(CSRC, "mindist_cpu.c"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("gcc failed building libmindist_cpu.so")
+    os.replace(tmp, CPU_LIB)
+    return CPU_LIB
 
 
 if __name__ == "__main__":

@@ -21,10 +21,22 @@ from tests import codes
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_symbols():
-    text = open(os.path.join(ROOT, "include", "mindist.h")).read()
+def declared_symbols(header="mindist.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mindist_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(mindist_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_cpu_library_exports_its_symbols_and_stays_separate():
+    """libmindist_cpu.so (the paper's CPU algorithms) exports what
+    mindist_cpu.h declares; the GPU library holds none of it."""
+    from paper_1603_06757_amd import cpu
+    syms = declared_symbols("mindist_cpu.h")
+    assert syms == ["mindist_cpu_pair"]
+    L = ctypes.CDLL(cpu.LIB_PATH)
+    for s in syms:
+        assert hasattr(L, s), s
+    assert not hasattr(ctypes.CDLL(md.LIB_PATH), "mindist_cpu_pair")
 
 
 def test_library_exports_every_declared_symbol():

@@ -695,12 +695,37 @@ int Engine::fetch_all() {
         hipMemcpyAsync(h_slots, d_slots, slot_bytes, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
         return fail(MINDIST_E_HIP, "batch: readback failed");
-    const uint64_t used = std::min<uint64_t>(h_g->arena_next, arena_units) * 128;
-    arena_host.resize(std::max<uint64_t>(used, 128));
-    if (used && hipMemcpy(arena_host.data(), d_arena, used, hipMemcpyDeviceToHost) != hipSuccess)
-        return fail(MINDIST_E_HIP, "batch: job readback failed");
-    h_arena = arena_host.data();
-    return MINDIST_OK;
+    // the job records' first lines only (the rest -- chunk counters and
+    // groups -- is never read back): ~1/10 of the used arena
+    const uint64_t used_units = std::min<uint64_t>(h_g->arena_next, arena_units);
+    std::vector<uint32_t> src;
+    for (int s = 0; s < slots; ++s) {
+        BatchCode &bc = h_codes[s];
+        const int nj = std::max(0, std::min<int>(bc.njobs, (int)kBatchMaxPairs));
+        for (int p = 0; p < nj; ++p) {
+            if (bc.job[p] >= used_units) return fail(MINDIST_E_HIP, "batch: job offset outside the arena");
+            src.push_back(bc.job[p]);
+            bc.job[p] = (uint32_t)(src.size() - 1);
+        }
+    }
+    const uint32_t n = (uint32_t)src.size();
+    pinned_free(h_lines);
+    h_lines = static_cast<unsigned char *>(pinned_alloc((size_t)std::max<uint32_t>(n, 1) * 128));
+    uint32_t *d_src = static_cast<uint32_t *>(dev_alloc((size_t)std::max<uint32_t>(n, 1) * 4));
+    unsigned char *d_lines = static_cast<unsigned char *>(dev_alloc((size_t)std::max<uint32_t>(n, 1) * 128));
+    int rc = MINDIST_OK;
+    if (!h_lines || !d_src || !d_lines) rc = fail(MINDIST_E_NOMEM, "batch: readback buffers");
+    if (rc == MINDIST_OK && n &&
+        (hipMemcpyAsync(d_src, src.data(), (size_t)n * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+         launch_gather_lines(d_arena, d_src, n, d_lines, stream) != 0 ||
+         hipMemcpyAsync(h_lines, d_lines, (size_t)n * 128, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+         hipStreamSynchronize(stream) != hipSuccess))
+        rc = fail(MINDIST_E_HIP, "batch: job readback failed");
+    (void)hipStreamSynchronize(stream);
+    dev_free(d_src);
+    dev_free(d_lines);
+    h_arena = h_lines;
+    return rc;
 }
 
 Engine::~Engine() {
@@ -715,6 +740,7 @@ Engine::~Engine() {
     pinned_free(h_g);
     pinned_free(h_rows);
     pinned_free(h_slots);
+    pinned_free(h_lines);
     if (h_done) (void)hipHostFree(h_done);
     if (h_stop) (void)hipHostFree(h_stop);
     event_put(e0);

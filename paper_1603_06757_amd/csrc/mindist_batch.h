@@ -146,6 +146,11 @@ struct BatchArgs {
 };
 
 int launch_persistent(const BatchArgs &a, int blocks, void *stream);
+// copy the 128-byte arena lines src[0..n) (arena offsets in 128-byte units)
+// to dst[0..n): the first line of each job record holds every field the
+// host decodes
+int launch_gather_lines(const unsigned char *arena, const uint32_t *src, uint32_t n, unsigned char *dst,
+                        void *stream);
 // blocks of 256 threads of the persistent kernel that fit on one CU at once
 // (0 if the runtime cannot tell)
 int persistent_resident_blocks_per_cu();

@@ -755,6 +755,26 @@ int persistent_resident_blocks_per_cu() {
     return n;
 }
 
+// eight threads per 128-byte line, 16 bytes each
+__global__ __launch_bounds__(256) void gather_lines_kernel(const unsigned char *arena, const uint32_t *src,
+                                                           uint32_t n, unsigned char *dst) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t line = t >> 3, part = t & 7;
+    if (line >= n) return;
+    const uint4 *from = reinterpret_cast<const uint4 *>(arena + (size_t)src[line] * 128) + part;
+    uint4 *to = reinterpret_cast<uint4 *>(dst + line * 128) + part;
+    *to = *from;
+}
+
+int launch_gather_lines(const unsigned char *arena, const uint32_t *src, uint32_t n, unsigned char *dst,
+                        void *stream) {
+    if (n == 0) return 0;
+    const uint64_t threads = (uint64_t)n * 8;
+    hipLaunchKernelGGL(gather_lines_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, arena, src, n, dst);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_persistent(const BatchArgs &a, int blocks, void *stream) {
     hipLaunchKernelGGL(persistent_batch_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -68,7 +68,7 @@ struct Engine {
     double kernel_seconds = 0;
     double wall_hz = 1e8;               // device wall-clock rate
     int waves = 0;                      // waves of the last launch
-    std::vector<unsigned char> arena_host;
+    unsigned char *h_lines = nullptr;   // pinned: first line of every job, gathered
 
     int init(int slots, size_t rows_bytes, size_t tab_bytes, size_t slot_bytes,
              uint64_t arena_units, int64_t user_stream, bool serving = false);
@@ -77,7 +77,10 @@ struct Engine {
     // wait for it
     int run(int blocks_per_cu, uint32_t tile_min, uint32_t tile_max, bool graph,
             double deadline_s = 0, uint32_t quantum = 4);
-    // read back the descriptors, the used part of the job arena and the slots
+    // read back the descriptors, the slots and the first line of every job
+    // the codes opened (gathered on the device into one dense array; each
+    // code's job offsets are rewritten to indices into it, so h_arena reads
+    // like the arena with 128-byte lines)
     int fetch_all();
     ~Engine();
 };

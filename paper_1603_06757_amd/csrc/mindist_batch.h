@@ -31,6 +31,9 @@ constexpr int kBatchItemsMaxD4 = 4;
 constexpr int kBatchItemsWide = 2;
 MD_HD constexpr int batch_items(int D) { return D <= 4 ? kBatchItemsMaxD4 : kBatchItemsWide; }
 constexpr int kTableChunk = 4096;     // table entries per table-job chunk
+// LDS words per wave for the rows of the set a table chunk builds: k <= 256
+// rows of at most 8 words (4 waves x 8 KB per block, 4 blocks in 128 KB)
+constexpr int kRowsLds = 2048;
 // tables of set j: right tables b = 0..bcap (shift 0) at t = j*kTabsPerSet + b,
 // outer tables b1 = 1..bcap over rows [0, k-bcap) (shift bcap, with inner
 // counts) at t = j*kTabsPerSet + (kBatchMaxB+1) + b1

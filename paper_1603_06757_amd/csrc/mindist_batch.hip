@@ -352,20 +352,44 @@ __device__ __noinline__ void table_run(const uint64_t *bt, const uint32_t *rows,
     }
 }
 
+// the table (index into tab_off) holding flattened entry x
+__device__ __forceinline__ int table_of(const BatchCode *cs, uint64_t x) {
+    int lo = 0, hi = kBatchTabs - 1;       // last table t with tab_off[t] <= x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cs->tab_off[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Chunk ch of the table job: entries [ch*4096, ...) of the flattened list
-// of the code's tables; lane l fills 64 consecutive entries.
-__device__ void table_chunk(const BatchArgs &A, BatchCode *cs, uint64_t ch) {
+// of the code's tables; lane l fills 64 consecutive entries.  When the whole
+// chunk lies in one set's tables (the usual case: a set's tables are
+// contiguous), the wave first copies that set's rows into its own LDS slice
+// (k x dp <= kRowsLds words), so that the successor walk's row reads -- a
+// few dependent reads per entry -- come from LDS instead of L2.
+__device__ void table_chunk(const BatchArgs &A, BatchCode *cs, uint64_t ch, uint32_t *lds) {
     const int lane = threadIdx.x & 63;
     const uint64_t E = cs->tab_off[kBatchTabs];
     const int k = cs->k;
-    uint64_t idx = ch * kTableChunk + (uint64_t)lane * (kTableChunk / 64);
+    const uint64_t first = ch * kTableChunk;
+    const uint64_t last = (first + kTableChunk < E ? first + kTableChunk : E) - 1;
+    const int j0 = table_of(cs, first) / kTabsPerSet;
+    const bool staged = j0 == table_of(cs, last) / kTabsPerSet &&
+                        k * cs->sets[j0].dp <= kRowsLds;
+    if (staged) {
+        const uint32_t *src = cs->sets[j0].rows;
+        const int words = k * cs->sets[j0].dp;
+        __builtin_amdgcn_wave_barrier();
+        for (int w = lane; w < words; w += 64) lds[w] = src[w];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    uint64_t idx = first + (uint64_t)lane * (kTableChunk / 64);
     uint64_t left = kTableChunk / 64;
     while (left > 0 && idx < E) {
-        int lo = 0, hi = kBatchTabs - 1;   // last table t with tab_off[t] <= idx
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (cs->tab_off[mid] <= idx) lo = mid; else hi = mid - 1;
-        }
+        const int lo = table_of(cs, idx);
         const int j = lo / kTabsPerSet, r0 = lo % kTabsPerSet;
         const BatchSet &set = cs->sets[j];
         const bool outer = r0 > kBatchMaxB;
@@ -377,14 +401,15 @@ __device__ void table_chunk(const BatchArgs &A, BatchCode *cs, uint64_t ch) {
         uint32_t *out = outer ? set.otab[b] : set.rtab[b];
         uint32_t *cnt = outer ? set.ocnt[b] : nullptr;
         const int kk = k - shift;
+        const uint32_t *rows = staged ? lds : set.rows;   // staged: j == j0 for every entry
         switch (b) {
-            case 0: table_run<0>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
-            case 1: table_run<1>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
-            case 2: table_run<2>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
-            case 3: table_run<3>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
-            case 4: table_run<4>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
-            case 5: table_run<5>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
-            default: table_run<6>(A.binom, set.rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            case 0: table_run<0>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            case 1: table_run<1>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            case 2: table_run<2>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            case 3: table_run<3>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            case 4: table_run<4>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            case 5: table_run<5>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+            default: table_run<6>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
         }
         left -= n;
         idx += n;
@@ -605,6 +630,9 @@ __device__ __noinline__ void flush(const BatchArgs &A, int c, int p, BatchJob *j
 // At most 128 VGPRs (4 waves per SIMD, 4 blocks of 256 per CU): the few
 // values this spills live outside the enumeration loops.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void persistent_batch_kernel(BatchArgs A) {
+    // one slice per wave for the rows of the set whose tables it builds
+    __shared__ uint32_t s_rows[4 * kRowsLds];
+    uint32_t *const my_rows = s_rows + (threadIdx.x >> 6) * kRowsLds;
     const int lane = threadIdx.x & 63;
     const uint32_t wave = uni32(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const int nc = A.n_codes;
@@ -655,7 +683,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
             if (ch != ~0ull) {
                 const uint64_t t0 = wall_clock64();
                 if (v.kind == 0) {
-                    table_chunk(A, &A.codes[v.c], ch);
+                    table_chunk(A, &A.codes[v.c], ch, my_rows);
                     tk_table += wall_clock64() - t0;
                     n_table += 1;
                 } else {

@@ -39,6 +39,10 @@ extern "C" {
 #define MINDIST_E_CANCELLED  -6   /* stopped by MINDIST_OPT_CANCEL_AFTER_CHUNKS */
 #define MINDIST_E_TIMEOUT    -7   /* MINDIST_OPT_DEADLINE_MS elapsed */
 #define MINDIST_E_STATE      -8   /* call out of order (e.g. results before a run) */
+#define MINDIST_E_CERT       -9   /* the result failed its certificate: a pair stopped
+                                     early although the least weight found was above the
+                                     bound before it, or the witness slot does not decode
+                                     to a codeword of the found weight */
 
 #define MINDIST_MAX_N      512
 #define MINDIST_MAX_WORDS  8
@@ -105,6 +109,13 @@ extern "C" {
  * bound after the current pair reaches the Singleton bound, nor with a
  * chunk budget. */
 #define MINDIST_OPT_SPECULATE        17
+/* testing: seed the device's least weight found with this value (and no
+ * witness) before the first pair; 0 (default) = off.  A value below the true
+ * distance makes the kernels stop a pair early (they see U <= L before it)
+ * while the host's U, the least pair minimum, is higher: the run must fail
+ * with MINDIST_E_CERT instead of returning a result whose enumeration
+ * stopped short.  A value above the true distance changes nothing. */
+#define MINDIST_OPT_INJECT_U         18
 
 typedef struct mindist_ctx mindist_ctx;
 
@@ -221,6 +232,12 @@ int mindist_plan(const uint64_t *G, int n, int k, int *sets, int *m_full,
  * f_full(h) = h+1, f_partial(h) = max(0, h+1-(k-k_m)). */
 int mindist_bound_after(int k, int m_full, int k_partial, int include_partial,
                         int j, int w);
+
+/* Host-only: the r-subset {x_1 < ... < x_r} of [0, hi) whose colex rank
+ * sum_t C(x_t, t) is `rank` (the combinatorial number system the kernels
+ * and the witness decoding use), written to out[0..r) ascending.
+ * 0 <= r <= 64, r <= hi <= 512, rank < C(hi, r); else MINDIST_E_ARG. */
+int mindist_colex_unrank(uint64_t rank, int r, int hi, int *out);
 
 /* ---- batches: many codes in one persistent launch ---------------------- */
 typedef struct mindist_batch_opts {

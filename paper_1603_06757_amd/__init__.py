@@ -15,12 +15,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmindist.so")
 
 E_NAMES = {0: "OK", -1: "E_ARG", -2: "E_RANK", -3: "E_NOMEM", -4: "E_HIP", -5: "E_LIMIT",
-           -6: "E_CANCELLED", -7: "E_TIMEOUT", -8: "E_STATE"}
+           -6: "E_CANCELLED", -7: "E_TIMEOUT", -8: "E_STATE", -9: "E_CERT"}
 
 OPT = {"term": 1, "midpair_exit": 2, "partial": 3, "verify": 4, "stream": 5,
        "deadline_ms": 6, "tile_t": 7, "blocks_per_cu": 8, "profile": 9,
        "cancel_after_chunks": 10, "table_mib": 11, "lane_items": 12,
-       "left_tables": 13, "chunk_order": 14, "counters": 15, "min_items": 16, "speculate": 17}
+       "left_tables": 13, "chunk_order": 14, "counters": 15, "min_items": 16, "speculate": 17,
+       "inject_u": 18}
 
 MAX_WORDS = 8
 
@@ -127,6 +128,7 @@ def lib():
         L.mindist_last_error.restype = C.c_char_p
         L.mindist_plan.argtypes = [u64p, C.c_int, C.c_int, ip, ip, ip, u64p]
         L.mindist_bound_after.argtypes = [C.c_int] * 6
+        L.mindist_colex_unrank.argtypes = [C.c_uint64, C.c_int, C.c_int, ip]
         L.mindist_calibrate.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
         L.mindist_device.argtypes = [C.c_char_p, C.c_int, ip]
@@ -194,6 +196,13 @@ def device() -> dict:
     cus = C.c_int(0)
     _check(lib().mindist_device(buf, 64, C.byref(cus)))
     return {"arch": buf.value.decode(), "compute_units": cus.value}
+
+
+def colex_unrank(rank: int, r: int, hi: int) -> list:
+    """Host-only: the r-subset of [0, hi) with colex rank `rank`, ascending."""
+    out = (C.c_int * max(r, 1))()
+    _check(lib().mindist_colex_unrank(rank, r, hi, out))
+    return list(out[:r])
 
 
 def bound_after(k, m_full, k_partial, include_partial, j, w) -> int:

@@ -77,6 +77,7 @@ struct mindist_ctx {
     int left_tables = 1;       // read left subsets from saved tables when they fit
     uint64_t table_cap = kTableCapDefault;
     uint64_t min_items = 0;    // left subsets a pair's split should give (0 = balanced split)
+    uint32_t inject_u = 0;             // testing: initial least weight on the device (0 = off)
     uint64_t speculate = 1ull << 28;   // launch the next pair before the current one's result
                                        // is read when it has at most this many combinations
     hipStream_t stream = nullptr;
@@ -228,6 +229,13 @@ extern "C" int mindist_bound_after(int k, int m_full, int k_partial, int include
     return bound_after(k, m_full, k_partial, ng, j, w);
 }
 
+extern "C" int mindist_colex_unrank(uint64_t rank, int r, int hi, int *out) {
+    if (!out || r < 0 || r > 64 || hi < r || hi > 512) return fail(MINDIST_E_ARG, "bad unrank query");
+    if (rank >= BN()(hi, r)) return fail(MINDIST_E_ARG, "rank out of range");
+    colex_unrank(rank, r, hi, out);
+    return MINDIST_OK;
+}
+
 extern "C" int mindist_create(const uint64_t *G, int n, int k, mindist_ctx **out) {
     if (!out) return fail(MINDIST_E_ARG, "out is NULL");
     *out = nullptr;
@@ -312,6 +320,9 @@ extern "C" int mindist_set_option(mindist_ctx *c, int key, int64_t v) {
         case MINDIST_OPT_SPECULATE:
             if (v < 0) return fail(MINDIST_E_ARG, "speculate must be >= 0");
             c->speculate = (uint64_t)v; break;
+        case MINDIST_OPT_INJECT_U:
+            if (v < 0 || v > c->P.n) return fail(MINDIST_E_ARG, "inject_u must be in 0..n");
+            c->inject_u = (uint32_t)v; break;
         case MINDIST_OPT_MIN_ITEMS:
             if (v < 0 || v > (int64_t)1 << 40) return fail(MINDIST_E_ARG, "min_items out of range");
             c->min_items = (uint64_t)v; break;
@@ -464,6 +475,18 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
     c->have_run = false;
     if (launch_init_state(c->d_state, c->max_pairs, c->stream))
         return fail(MINDIST_E_HIP, "init kernel launch failed");
+    if (c->inject_u) {
+        // testing: the device starts from a least weight it never found
+        uint32_t *h = static_cast<uint32_t *>(pinned_alloc(sizeof(uint32_t)));
+        if (!h) return fail(MINDIST_E_NOMEM, "inject_u staging");
+        *h = c->inject_u;
+        const bool ok =
+            hipMemcpyAsync(&c->d_state->U_found, h, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+            hipMemcpyAsync(&c->d_state->U_base, h, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+            hipStreamSynchronize(c->stream) == hipSuccess;
+        pinned_free(h);
+        if (!ok) return fail(MINDIST_E_HIP, "inject_u copy failed");
+    }
 
     const int singleton = n - k + 1;
     int L = 1;
@@ -802,7 +825,20 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         last_j = j;
         last_w = w;
         if (hm.cancelled) { status = fail(MINDIST_E_CANCELLED, "cancelled after the chunk budget"); break; }
-        if (cut) { exited = 1; break; }
+        if (cut) {
+            // the kernels stop a pair only once the least weight they know
+            // (from earlier launches and earlier pairs of this one) is at or
+            // below the bound before it, and the host's U -- the least pair
+            // minimum up to this pair -- is never above theirs: a cut the
+            // host's own U does not justify leaves the enumeration short
+            if ((int)std::min<uint32_t>(U_found, (uint32_t)singleton) > Lb) {
+                status = fail(MINDIST_E_CERT, "pair (" + std::to_string(j) + "," + std::to_string(w) +
+                                                  ") stopped early although U > L before it");
+                break;
+            }
+            exited = 1;
+            break;
+        }
         if (c->term_per_level && j == ng - 1) L = L_after_pair(j, w, L);
         int j2 = j, w2 = w;
         advance(j2, w2);
@@ -862,12 +898,12 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
             if (!ok) return fail(MINDIST_E_HIP, "witness readback failed");
         }
         if (s.pair >= (uint32_t)launched_pairs.size())
-            return fail(MINDIST_E_HIP, "witness slot holds an invalid pair index");
+            return fail(MINDIST_E_CERT, "witness slot holds an invalid pair index");
         const Flight &lp = launched_pairs[s.pair];
         const int wj = lp.q.j, ww = lp.q.w;
         const std::vector<int> rows = witness_rows(k, lp.q.pp.a, lp.q.pp.b, lp.q.pp.b2, s);
         if ((int)rows.size() != ww)
-            return fail(MINDIST_E_HIP, "witness slot decodes to an invalid combination");
+            return fail(MINDIST_E_CERT, "witness slot decodes to an invalid combination");
         uint64_t word[MINDIST_MAX_WORDS] = {0};
         for (int r : rows) {
             for (int t = 0; t < P.W; ++t) word[t] ^= P.gamma[wj][(size_t)r * P.W + t];
@@ -876,7 +912,7 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         int wt = 0;
         for (int t = 0; t < P.W; ++t) wt += __builtin_popcountll(word[t]);
         if (wt != (int)U_found)
-            return fail(MINDIST_E_HIP, "witness weight " + std::to_string(wt) +
+            return fail(MINDIST_E_CERT, "witness weight " + std::to_string(wt) +
                                            " differs from the found weight " + std::to_string(U_found));
         std::memcpy(out->witness, word, sizeof(uint64_t) * P.W);
         out->witness_j = wj;

@@ -385,3 +385,29 @@ def test_cancel_and_deadline():
             r = m.run()
             assert r["d"] == gold["d"]
             compare_with_trace(r, gold["trace"], gold["counts"], gold["pair_min"], None, w.k)
+
+
+@pytest.mark.parametrize("name", ["rand48x24", "rand150x75"])
+def test_injected_upper_bound_must_pass_the_certificate(name):
+    """A least weight the device never found (seeded below the true d) stops
+    Algorithm 1 early, and the run must then fail its certificate with
+    MINDIST_E_CERT rather than return that value; a seed above d changes
+    nothing, and the context runs correctly again afterwards."""
+    w = WORKLOADS[name]
+    G = w.matrix()
+    ref = md.min_distance(G, w.n, w.k)
+    say("inject U", name, "true d", ref["d"])
+    with md.MinDist(G, w.n, w.k, inject_u=ref["d"] - 1) as m:
+        with pytest.raises(md.MindistError) as e:
+            m.run()
+        assert e.value.code == -9
+        m.set_option("inject_u", 0)
+        r = m.run()
+        assert r["d"] == ref["d"]
+        check_witness(G, w.n, w.k, r)
+    for u in (ref["d"] + 1, ref["d"] + 4):
+        r = md.min_distance(G, w.n, w.k, inject_u=u)
+        assert r["d"] == ref["d"]
+        assert [(p["j"], p["w"], p["pair_min"]) for p in r["pairs"]] == \
+               [(p["j"], p["w"], p["pair_min"]) for p in ref["pairs"]]
+        check_witness(G, w.n, w.k, r)

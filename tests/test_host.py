@@ -6,6 +6,7 @@ oracle follows (column XOR basis + a separate echelon form); they must agree
 bit for bit.  Also: the C ABI loads and exports every declared entry point.
 """
 import ctypes
+import itertools
 import math
 import os
 import re
@@ -143,3 +144,41 @@ def test_server_rejects_an_unknown_engine():
     with pytest.raises(md.MindistError) as e:
         md.Server(engine=2)
     assert e.value.code == -1
+
+
+def _colex_key(c):
+    return tuple(reversed(c))
+
+
+def test_colex_unrank_is_the_colex_bijection():
+    """Every rank of every (hi, r) with hi <= 14, and (hi, r) up to 20 where
+    C(hi, r) <= 20000: the subsets come out ascending, distinct, in colex
+    order (so rank + 1 is the colex successor), with sum_t C(x_t, t) = rank
+    (t from 1) -- against itertools' enumeration sorted by the colex key."""
+    for hi in range(0, 21):
+        for r in range(0, hi + 1):
+            total = math.comb(hi, r)
+            if hi > 14 and total > 20000:
+                continue
+            want = sorted(itertools.combinations(range(hi), r), key=_colex_key)
+            got = [tuple(md.colex_unrank(i, r, hi)) for i in range(total)]
+            assert got == want, (hi, r)
+            for i in (0, total - 1):
+                assert sum(math.comb(x, t + 1) for t, x in enumerate(got[i])) == i
+
+
+def test_colex_unrank_rejects_bad_queries():
+    for rank, r, hi in ((10, 2, 5), (0, 3, 2), (0, 65, 512), (0, 2, 513)):
+        with pytest.raises(md.MindistError) as e:
+            md.colex_unrank(rank, r, hi)
+        assert e.value.code == -1
+
+
+def test_option_and_error_codes_match_the_header():
+    text = open(os.path.join(ROOT, "include", "mindist.h")).read()
+    opts = {m.group(1).lower(): int(m.group(2))
+            for m in re.finditer(r"#define MINDIST_OPT_(\w+)\s+(\d+)", text)}
+    errs = {int(m.group(2)): "E_" + m.group(1)
+            for m in re.finditer(r"#define MINDIST_E_(\w+)\s+(-\d+)", text)}
+    assert opts == md.OPT
+    assert {k: v for k, v in md.E_NAMES.items() if k < 0} == errs

@@ -370,7 +370,9 @@ def test_cancel_and_deadline():
         assert e.value.code == -6
         m.set_option("cancel_after_chunks", 0)
         gold = json.load(open(os.path.join(GOLDEN, "rand150x75.json")))
-        assert m.run()["d"] == gold["d"]      # the context is reusable afterwards
+        r = m.run()                           # the context is reusable afterwards
+        assert r["d"] == gold["d"]
+        compare_with_trace(r, gold["trace"], gold["counts"], gold["pair_min"], None, w.k)
     say("deadline")
     with md.MinDist(w.matrix(), w.n, w.k, deadline_ms=1) as m:
         with pytest.raises(md.MindistError) as e:
@@ -389,9 +391,9 @@ def test_cancel_and_deadline():
 
 @pytest.mark.parametrize("name", ["rand48x24", "rand150x75"])
 def test_injected_upper_bound_must_pass_the_certificate(name):
-    """A least weight the device never found (seeded below the true d) stops
-    Algorithm 1 early, and the run must then fail its certificate with
-    MINDIST_E_CERT rather than return that value; a seed above d changes
+    """A least weight the device never found (seeded below the true d) makes
+    the kernels cut a pair short that the host's own U does not justify: the
+    run must fail its certificate with MINDIST_E_CERT; a seed above d changes
     nothing, and the context runs correctly again afterwards."""
     w = WORKLOADS[name]
     G = w.matrix()

@@ -41,7 +41,7 @@ extern "C" {
  * entry of the last chunk (each entry read once for both). */
 #define MINDIST_CPU_SAVED_UNROLL2  4
 
-/* One pair with `threads` OpenMP threads (0 = all), dynamic schedule over
+/* One pair with `threads` OpenMP threads (0 = the OpenMP default), dynamic schedule over
  * the outermost loop (Section 4's parallelisation).  Outputs: least weight,
  * combinations evaluated (C(k, w)), row additions, and for the saved
  * algorithms the time spent building the saved levels (built on every call;

@@ -54,8 +54,8 @@ static int next_comb(int *c, int m, int k, int fixed) {
 }
 
 /* ---- Algorithm 2 ---------------------------------------------------- */
-static void run_basic(const uint64_t *R, int k, int W, int w, int off, Acc *out) {
-#pragma omp parallel
+static void run_basic(const uint64_t *R, int k, int W, int w, int off, int nt, Acc *out) {
+#pragma omp parallel num_threads(nt)
     {
         Acc a = {INT32_MAX, 0, 0};
 #pragma omp for schedule(dynamic, 1)
@@ -91,9 +91,10 @@ static inline void last_element(const uint64_t *R, int k, int W, int off, const 
     a->adds += (uint64_t)(k - from);
 }
 
-static void run_optimized(const uint64_t *R, int k, int W, int w, int off, int stack, Acc *out) {
+static void run_optimized(const uint64_t *R, int k, int W, int w, int off, int stack, int nt,
+                          Acc *out) {
     const int m = w - 1;      /* size of the prefix combinations */
-#pragma omp parallel
+#pragma omp parallel num_threads(nt)
     {
         Acc a = {INT32_MAX, 0, 0};
 #pragma omp for schedule(dynamic, 1)
@@ -131,7 +132,7 @@ static void run_optimized(const uint64_t *R, int k, int W, int w, int off, int s
 typedef struct {
     uint64_t n;          /* C(k, l) entries */
     uint64_t *sum;       /* n x W */
-    uint8_t *first, *last;
+    uint8_t *last;       /* largest element of each subset */
 } Level;
 
 #define MAX_TABLE_BYTES (8ull << 30)   /* all saved levels of one pair */
@@ -143,22 +144,21 @@ static int build_levels(const uint64_t *R, int k, int W, int s, Level *L) {
     uint64_t bytes = 0;
     for (int l = 1; l <= s; ++l) {
         const uint64_t n = binom(k, l);
-        if (n > (MAX_TABLE_BYTES / (8ull * W + 2))) return MINDIST_CPU_E_NOMEM;
-        bytes += n * (8ull * W + 2);
+        if (n > (MAX_TABLE_BYTES / (8ull * W + 1))) return MINDIST_CPU_E_NOMEM;
+        bytes += n * (8ull * W + 1);
     }
     if (bytes > MAX_TABLE_BYTES) return MINDIST_CPU_E_NOMEM;
     for (int l = 1; l <= s; ++l) {
         Level *v = &L[l];
         v->n = binom(k, l);
         v->sum = (uint64_t *)malloc(sizeof(uint64_t) * W * (v->n ? v->n : 1));
-        v->first = (uint8_t *)malloc(v->n ? v->n : 1);
         v->last = (uint8_t *)malloc(v->n ? v->n : 1);
-        if (!v->sum || !v->first || !v->last) return MINDIST_CPU_E_NOMEM;
+        if (!v->sum || !v->last) return MINDIST_CPU_E_NOMEM;
         uint64_t i = 0;
         for (int x = 0; x < k; ++x) {
             if (l == 1) {
                 memcpy(v->sum + i * W, R + (size_t)x * W, sizeof(uint64_t) * W);
-                v->first[i] = v->last[i] = (uint8_t)x;
+                v->last[i] = (uint8_t)x;
                 ++i;
                 continue;
             }
@@ -166,7 +166,6 @@ static int build_levels(const uint64_t *R, int k, int W, int s, Level *L) {
             const uint64_t from = u->n - binom(k - x - 1, l - 1);
             for (uint64_t j = from; j < u->n; ++j, ++i) {
                 xor_into(v->sum + i * W, R + (size_t)x * W, u->sum + j * W, W);
-                v->first[i] = (uint8_t)x;
                 v->last[i] = u->last[j];
             }
         }
@@ -268,8 +267,8 @@ static void saved_step(const Saved *q, const uint64_t *prefix, int from, int lef
     if (pending != UINT64_MAX) last_chunk(q, pend_sum, v->last[pending] + 1, NULL, 0, 1, a);
 }
 
-static int run_saved(const uint64_t *R, int k, int W, int w, int off, int s, int unroll, Acc *out,
-                     double *table_seconds) {
+static int run_saved(const uint64_t *R, int k, int W, int w, int off, int s, int unroll, int nt,
+                     Acc *out, double *table_seconds) {
     Level L[9];
     memset(L, 0, sizeof(L));
     const int ls = s < w ? s : w;
@@ -285,7 +284,7 @@ static int run_saved(const uint64_t *R, int k, int W, int w, int off, int s, int
         } else {
             const Level *v = &L[ls];
             const int after = w - ls;
-#pragma omp parallel
+#pragma omp parallel num_threads(nt)
             {
                 Acc a = {INT32_MAX, 0, 0};
                 /* the first chunk's entries, a few at a time, dynamically */
@@ -319,7 +318,6 @@ static int run_saved(const uint64_t *R, int k, int W, int w, int off, int s, int
     }
     for (int l = 1; l <= 8; ++l) {
         free(L[l].sum);
-        free(L[l].first);
         free(L[l].last);
     }
     return rc;
@@ -332,13 +330,13 @@ int mindist_cpu_pair(const uint64_t *rows, int k, int words, int w, int offset, 
         algorithm < MINDIST_CPU_BASIC || algorithm > MINDIST_CPU_SAVED_UNROLL2)
         return MINDIST_CPU_E_ARG;
     if (algorithm >= MINDIST_CPU_SAVED && (s < 1 || s > 8)) return MINDIST_CPU_E_ARG;
-    if (threads > 0) omp_set_num_threads(threads);
+    const int nt = threads > 0 ? threads : omp_get_max_threads();
     if (table_seconds) *table_seconds = 0;
     Acc out = {INT32_MAX, 0, 0};
     int rc = 0;
     switch (algorithm) {
         case MINDIST_CPU_BASIC:
-            run_basic(rows, k, words, w, offset, &out);
+            run_basic(rows, k, words, w, offset, nt, &out);
             break;
         case MINDIST_CPU_OPTIMIZED:
         case MINDIST_CPU_STACK:
@@ -350,11 +348,11 @@ int mindist_cpu_pair(const uint64_t *rows, int k, int words, int w, int offset, 
                 }
                 out.combos = (uint64_t)k;
             } else {
-                run_optimized(rows, k, words, w, offset, algorithm == MINDIST_CPU_STACK, &out);
+                run_optimized(rows, k, words, w, offset, algorithm == MINDIST_CPU_STACK, nt, &out);
             }
             break;
         default:
-            rc = run_saved(rows, k, words, w, offset, s, algorithm == MINDIST_CPU_SAVED_UNROLL2, &out,
+            rc = run_saved(rows, k, words, w, offset, s, algorithm == MINDIST_CPU_SAVED_UNROLL2, nt, &out,
                            table_seconds);
     }
     if (rc) return rc;

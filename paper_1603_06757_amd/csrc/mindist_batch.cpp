@@ -136,13 +136,15 @@ int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &
     }
     // the balanced split of the expected top level needs b = top/2; a table
     // is built only if the largest expected pair reads it many times over
-    // (C(k,b) at most 1/64 of C(k,top)): building it costs about as much per
-    // entry as enumerating one codeword
+    // (C(k,b) at most C(k,top) / kTableReuse): in the persistent kernel an
+    // entry costs tens of enumerated codewords to build (a successor step,
+    // a scattered store), so a level that is read less pays for itself
+    // nowhere near
     const int top = expected_top_level(hc);
     const int want = std::max(1, top / 2);
     for (int &b : hc.bcap) {
         b = std::min(b, want);
-        while (b > 1 && B(k, b) > B(k, top) / 64) --b;
+        while (b > 1 && B(k, b) > B(k, top) / kTableReuse) --b;
     }
     size_tables(hc);
     return MINDIST_OK;

@@ -34,6 +34,9 @@ constexpr int kTableChunk = 4096;     // table entries per table-job chunk
 // LDS words per wave for the rows of the set a table chunk builds: k <= 256
 // rows of at most 8 words (4 waves x 8 KB per block, 4 blocks in 128 KB)
 constexpr int kRowsLds = 2048;
+// a saved table of C(k,b) entries is built only if C(k,b) <= C(k,top) /
+// kTableReuse, top = the expected last level of the code
+constexpr uint64_t kTableReuse = 1024;
 // tables of set j: right tables b = 0..bcap (shift 0) at t = j*kTabsPerSet + b,
 // outer tables b1 = 1..bcap over rows [0, k-bcap) (shift bcap, with inner
 // counts) at t = j*kTabsPerSet + (kBatchMaxB+1) + b1

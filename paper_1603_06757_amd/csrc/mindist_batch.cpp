@@ -119,6 +119,10 @@ int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &
     hc.dp.resize(hc.n_gamma);
     hc.bcap.resize(hc.n_gamma);
     hc.rows.resize(hc.n_gamma);
+    // short codes keep their tables small: their table job would otherwise
+    // sit on the launch's critical path (a code's pairs wait for it) and
+    // small tables stay in cache while many codes read theirs at once
+    if (estimated_work(hc) < kSmallCodeWork) table_cap = std::min<uint64_t>(table_cap, kSmallCodeTableBytes);
     for (int j = 0; j < hc.n_gamma; ++j) {
         const std::vector<int> cols = carried_columns(hc.P, j);
         hc.D[j] = (int)((cols.size() + 31) / 32);

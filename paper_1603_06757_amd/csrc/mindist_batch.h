@@ -37,6 +37,10 @@ constexpr int kRowsLds = 2048;
 // a saved table of C(k,b) entries is built only if C(k,b) <= C(k,top) /
 // kTableReuse, top = the expected last level of the code
 constexpr uint64_t kTableReuse = 1024;
+// codes expected to enumerate fewer combinations than this keep every
+// saved table within kSmallCodeTableBytes
+constexpr double kSmallCodeWork = 536870912.0;         // 2^29
+constexpr uint64_t kSmallCodeTableBytes = 256u << 10;  // 256 KiB
 // tables of set j: right tables b = 0..bcap (shift 0) at t = j*kTabsPerSet + b,
 // outer tables b1 = 1..bcap over rows [0, k-bcap) (shift bcap, with inner
 // counts) at t = j*kTabsPerSet + (kBatchMaxB+1) + b1

@@ -1,0 +1,47 @@
+"""CPU checks of bench.py's contract: the roofline object's arithmetic on
+synthetic per-pair records, and the refusal of more than one GPU."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def _pair(launch, dwords, executed, dev_ms, ms=None):
+    return {"launch": launch, "dwords": dwords, "executed": executed, "dev_ms": dev_ms,
+            "ms": dev_ms if ms is None else ms}
+
+
+def test_roofline_groups_launches_and_prices_against_the_peak():
+    # two runs; launch 0 holds two short pairs (their span is the longer
+    # one), launch 1 one long pair; all D = 3
+    run = {"pairs": [_pair(0, 3, 1000, 0.010), _pair(0, 3, 3000, 0.020), _pair(1, 3, 6_000_000_000, 1.0)]}
+    D, roof = bench.roofline([run, run], [run])
+    assert D == 3
+    sec = 2 * (0.020 + 1.0) * 1e-3
+    cw = 2 * (1000 + 3000 + 6_000_000_000)
+    assert roof["launches"] == 4
+    assert roof["achieved"] == pytest.approx(cw * 3 / sec / 1e12)
+    assert roof["peak"] == pytest.approx(256 * 64 * 2.4e9 / 2 / 1e12)
+    assert roof["frac"] == pytest.approx(cw * 3 / sec / (256 * 64 * 2.4e9 / 2))
+    assert roof["bound"] == "alu"
+    assert roof["avg_launch_us"] == pytest.approx(sec / 4 * 1e6)
+    for key in ("unit", "traffic", "kernel", "avg_launch_us_events"):
+        assert key in roof
+
+
+def test_dominant_kernel_is_the_instance_with_the_most_time():
+    run = {"pairs": [_pair(0, 2, 10**9, 0.5), _pair(1, 3, 10**9, 2.0), _pair(2, 2, 10**9, 0.5)]}
+    D, roof = bench.roofline([run], [run])
+    assert D == 3 and roof["launches"] == 1
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

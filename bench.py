@@ -19,6 +19,7 @@ Prints one JSON line:
   serving    open-loop Poisson arrivals of the serving stream at one rate:
              p50/p99 latency and codes/s (requests above a work cap are left
              out and counted); --serving-sweep runs the whole rate sweep
+  section6   the smallest Section 6 code, [232,51], certified (d = 61 claimed)
 --new-codes certifies the codes of Section 6 instead (one line per code);
 --paper-random runs seeded codes of the random sizes the paper times;
 --compare-walk measures the saved-sums kernel against the direct walk;
@@ -297,7 +298,7 @@ PAPER_CPU_S = {
 }
 
 
-def new_codes_leg(names):
+def new_codes_leg(names, quiet: bool = False):
     """Section 6's codes through the single-code path, one fresh context
     each: d against the claimed distance, time, codewords and the share of
     the VALU peak (every pair's codewords times its 32-bit words)."""
@@ -321,7 +322,8 @@ def new_codes_leg(names):
             one, six = PAPER_CPU_S[name]
             rec["paper_cpu_s"] = {"1_core": one, "6_cores": six}
         out.append(rec)
-        print(json.dumps(rec), flush=True)
+        if not quiet:
+            print(json.dumps(rec), flush=True)
     return out
 
 
@@ -492,6 +494,8 @@ def main():
                     help="batch leg: every stride-th code of the stream (1 = all)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-section6", action="store_true",
+                    help="skip certifying the smallest Section 6 code ([232,51,61], ~4 s)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only run the serving sweep (one JSON line per arrival rate) and exit")
     ap.add_argument("--serving-cap", type=float, default=2e10,
@@ -571,6 +575,9 @@ def main():
     if not a.no_serving:
         print("[bench] serving leg", file=sys.stderr, flush=True)
         line["serving"] = serving_leg(300.0, 3.0, a.serving_cap)
+    if not a.no_section6:
+        print("[bench] section 6 code", file=sys.stderr, flush=True)
+        line["section6"] = new_codes_leg(["mp232x51"], quiet=True)[0]
     if not a.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)

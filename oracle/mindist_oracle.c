@@ -61,6 +61,8 @@ enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_RANK = -2, ORC_E_NOMEM = -4,
  *   3 each pair stops one combination early
  *   4 Gamma_j is reduced only below each pivot (not the reduced echelon form)
  *   5 the weight ignores the last word of a codeword
+ *   6 pivots found after the set's own columns (the lower block of the
+ *     partial set) clear their column only in the rows below them
  */
 static int orc_fault = 0;
 void orc_set_fault(int f) { orc_fault = f; }
@@ -242,7 +244,8 @@ int orc_gamma(const uint64_t *G, int n, int k, const int *first, int nfirst, uin
                 Gamma[(size_t)p * W + t] = Gamma[(size_t)r * W + t];
                 Gamma[(size_t)r * W + t] = tmp;
             }
-        for (int i = (orc_fault == 4 ? r + 1 : 0); i < k; i++)
+        int from = (orc_fault == 4 || (orc_fault == 6 && oi >= nfirst)) ? r + 1 : 0;
+        for (int i = from; i < k; i++)
             if (i != r && getbit(Gamma + (size_t)i * W, c))
                 for (int t = 0; t < W; t++) Gamma[(size_t)i * W + t] ^= Gamma[(size_t)r * W + t];
         r++;

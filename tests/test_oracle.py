@@ -219,6 +219,48 @@ def test_gamma_is_systematic_and_row_equivalent():
         assert _rank(np.vstack([Gb, Gam])) == k
 
 
+def _assert_rref(Gam, order, first):
+    """Reduced row echelon form under a column order, by its definition: the
+    leading one of each row (first nonzero in that order) lies strictly to
+    the right of the one above, every leading column is a unit vector, and
+    the first len(first) leading columns are the set's own columns."""
+    k = Gam.shape[0]
+    pos = {c: i for i, c in enumerate(order)}
+    lead = []
+    for r in range(k):
+        nz = [c for c in order if Gam[r, c]]
+        assert nz, f"row {r} is zero"
+        lead.append(nz[0])
+    assert all(pos[lead[r]] < pos[lead[r + 1]] for r in range(k - 1))
+    for r, c in enumerate(lead):
+        col = np.zeros(k, dtype=np.uint8)
+        col[r] = 1
+        assert (Gam[:, c] == col).all(), f"pivot column {c} of row {r} is not a unit vector"
+    assert lead[:len(first)] == list(first)
+    return lead
+
+
+def test_gamma_is_the_reduced_echelon_form_partial_set_included():
+    """Section 2's [[I, A], [0, B]] form of the partial set made unique: every
+    Gamma_j is the reduced row echelon form of G under (set columns, then the
+    others ascending), so the lower block's pivots lie outside the set,
+    ascend, and are cleared in the upper rows too."""
+    seen_lower = 0
+    for (n, k, seed) in [(70, 30, 0), (100, 30, 9), (110, 24, 3), (90, 25, 4)]:
+        G = random_generator(n, k, 11 if n == 70 else seed, 0)
+        full, part = oracle.partition(G, n, k)
+        Gb = codes.unpack(G, n)
+        for s in full + ([part] if part else []):
+            order = list(s) + [c for c in range(n) if c not in set(s)]
+            Gam = codes.unpack(oracle.gamma(G, n, k, s), n)
+            lead = _assert_rref(Gam, order, s)
+            assert _rank(np.vstack([Gb, Gam])) == k
+            lower = lead[len(s):]
+            assert all(c not in set(s) for c in lower) and lower == sorted(lower)
+            seen_lower += len(lower)
+    assert seen_lower > 0
+
+
 # ---- enumeration of one pair ------------------------------------------------
 
 def test_lexicographic_order_example():
@@ -359,6 +401,7 @@ _CATCHERS = {
     3: [lambda: test_stack_cost_lemma(8, 4), lambda: test_pair_weight_sum_closed_form(100, 30, 5),
         test_bz_counts_are_binomials_and_bound_sound],
     4: [test_gamma_is_systematic_and_row_equivalent],
+    6: [test_gamma_is_the_reduced_echelon_form_partial_set_included],
     5: [lambda: test_pair_weight_sum_closed_form(150, 75, 2),
         lambda: test_bz_reed_muller_large_k(2, 7, 32)],
 }
@@ -367,7 +410,8 @@ _CATCHERS = {
 @pytest.mark.parametrize("fault", sorted(_CATCHERS))
 def test_planted_mistakes_are_caught(fault):
     """Each planted mistake (a dropped bound term, a wrong level index, a
-    skipped combination, an incomplete reduction, a dropped word) makes at
+    skipped combination, an incomplete reduction, a dropped word, a partial
+    set whose lower block is left unreduced above its pivots) makes at
     least one pin fail; with no mistake planted all of them pass."""
     with oracle.planted(fault):
         caught = [_fails(p) for p in _CATCHERS[fault]]

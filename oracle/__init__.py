@@ -62,7 +62,7 @@ def lib():
 
 
 class _Opts(C.Structure):
-    _fields_ = [("term_per_level", C.c_int), ("partial_never", C.c_int), ("threads", C.c_int)]
+    _fields_ = [("term_per_level", C.c_int), ("partial_policy", C.c_int), ("threads", C.c_int)]
 
 
 def _u64(a):
@@ -157,9 +157,16 @@ def combo_codeword(Gam, n: int, k: int, g: int, rank: int):
     return combo.tolist(), word
 
 
+PARTIAL_POLICIES = {"always": 0, "never": 1, "when_useful": 2}
+
+
 def bz(G, n: int, k: int, per_level: bool = False, partial_never: bool = False,
-       threads: int = 1) -> dict:
-    """Algorithm 1 (Brouwer-Zimmerman) under the canonical readings."""
+       threads: int = 1, partial: str | None = None) -> dict:
+    """Algorithm 1 (Brouwer-Zimmerman) under the canonical readings.
+    partial: "always" (default), "never" (same as partial_never=True) or
+    "when_useful" (the partial set from the first level its bound term is
+    positive, with its lower levels caught up then)."""
+    policy = PARTIAL_POLICIES[partial] if partial else (1 if partial_never else 0)
     G = _mat(G)
     W = (n + 63) // 64
     cap = n + 1
@@ -173,7 +180,7 @@ def bz(G, n: int, k: int, per_level: bool = False, partial_never: bool = False,
     wit = np.zeros(W, dtype=np.uint64)
     wcombo = np.zeros(ORC_MAXG, dtype=np.int32)
     wmeta = np.zeros(3, dtype=np.uint64)
-    opts = _Opts(1 if per_level else 0, 1 if partial_never else 0, threads)
+    opts = _Opts(1 if per_level else 0, policy, threads)
     _check(lib().orc_bz(_u64(G), n, k, C.cast(C.pointer(opts), C.c_void_p), cap,
                         _i32(sets), _u64(counts), _i32(pmin), _u64(wsum),
                         _i32(trace), tcap, _i32(info), _u64(wit), _i32(wcombo), _u64(wmeta)))

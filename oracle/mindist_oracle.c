@@ -34,7 +34,11 @@
  *     f_full(h) = h+1 and f_partial(h) = max(0, h+1-(k-k_m)); the literal
  *     per-level update of Algorithm 1 is available as an option;
  *   - the partial set is enumerated at every level (literal loop j=1..m)
- *     unless the option drops it together with its bound term;
+ *     unless an option drops it together with its bound term, or defers it
+ *     to the first level g whose term max(0, g+1-(k-k_m)) is positive; the
+ *     term bounds the set's columns only for codewords whose message under
+ *     Gamma_m weighs more than every level enumerated, so that first level
+ *     also enumerates the set's lower levels (ascending, after the full sets);
  *   - L starts at 1, U at n-k+1 (Algorithm 1, first line); a witness only
  *     comes from an enumerated codeword; U_found only moves on a strictly
  *     smaller weight; the witness is the first codeword reaching the final
@@ -63,6 +67,8 @@ enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_RANK = -2, ORC_E_NOMEM = -4,
  *   5 the weight ignores the last word of a codeword
  *   6 pivots found after the set's own columns (the lower block of the
  *     partial set) clear their column only in the rows below them
+ *   7 a partial set deferred to its first useful level enumerates only that
+ *     level, yet its bound term counts as if its lower levels were done
  */
 static int orc_fault = 0;
 void orc_set_fault(int f) { orc_fault = f; }
@@ -408,7 +414,8 @@ int orc_combo_codeword(const uint64_t *Gamma, int n, int k, int g, uint64_t rank
 /* ------------------------------------------------------------------ */
 typedef struct {
     int term_per_level;      /* 0: raise L after every Gamma_j; 1: literal per-level update */
-    int partial_never;       /* 1: drop the partial set and its bound term */
+    int partial_policy;      /* 0: partial set at every level; 1: dropped with its bound
+                                term; 2: from the first level its term is positive */
     int threads;
 } orc_opts;
 
@@ -427,7 +434,10 @@ static int f_bound(int j, int h, int m_full, int k, int k_m)
  *   pair_min   nsets_cap*(k+1) int: minimum weight of pair (j,g), -1 if not visited
  *   wsum       nsets_cap*(k+1) uint64: sum of the weights of pair (j,g)
  *   trace      up to trace_cap entries of 6 ints per visited pair:
- *              (j, g, L_before, L_after, U_after, pair_min)
+ *              (j, h, L_before, L_after, U_after, pair_min), h the level the
+ *              pair enumerates (h = g except the partial set's lower levels
+ *              enumerated late under policy 2); L_after includes the
+ *              per-level update when the pair ends its level
  *   info       8 ints: d, m_full, k_m, n_gamma, pairs_visited, L_final, U_final, last level
  *   witness    W uint64; witness_combo: up to ORC_MAXG ints, witness_meta: (j, g, lex rank)
  */
@@ -442,7 +452,8 @@ int orc_bz(const uint64_t *G, int n, int k, const orc_opts *opt, int nsets_cap,
     int m_full = 0, k_m = 0;
     e = orc_partition(G, n, k, sets, &m_full, &k_m);
     if (e) return e;
-    int has_partial = (k_m >= 1) && !(opt && opt->partial_never);
+    int policy = opt ? opt->partial_policy : 0;
+    int has_partial = (k_m >= 1) && policy != 1;
     int ng = m_full + (has_partial ? 1 : 0);
     if (ng > nsets_cap) return ORC_E_LIMIT;
     int threads = opt ? opt->threads : 1;
@@ -466,42 +477,60 @@ int orc_bz(const uint64_t *G, int n, int k, const orc_opts *opt, int nsets_cap,
     int pairs = 0, last_g = 0;
     int wj = -1, wg = 0;
     uint64_t wrank = 0;
+    /* last level enumerated per set; the pairs (set, level) of one level */
+    int *done = calloc((size_t)ng, sizeof(int));
+    int *pj = malloc(sizeof(int) * (size_t)(m_full + k + 1));
+    int *ph = malloc(sizeof(int) * (size_t)(m_full + k + 1));
+    if (!done || !pj || !ph) { free(done); free(pj); free(ph); free(Gam); return ORC_E_NOMEM; }
     for (int g = 1; g <= k; g++) {
         int U = U_found < singleton ? U_found : singleton;
         if (L >= U) break;
-        if (g > ORC_MAXG) { free(Gam); return ORC_E_LIMIT; }
+        if (g > ORC_MAXG) { free(done); free(pj); free(ph); free(Gam); return ORC_E_LIMIT; }
+        /* the pairs of level g: every full set at level g, then the partial
+           set at g, or under policy 2 (once its term at g is positive) at
+           every level it has not done yet */
+        int np = 0;
+        for (int j = 0; j < m_full; j++) { pj[np] = j; ph[np] = g; np++; }
+        if (has_partial) {
+            if (policy == 0) { pj[np] = m_full; ph[np] = g; np++; }
+            else if (g + 1 - (k - k_m) > 0)
+                for (int h = (orc_fault == 7 ? g : done[m_full] + 1); h <= g; h++) {
+                    pj[np] = m_full; ph[np] = h; np++;
+                }
+        }
         int stop = 0;
-        for (int j = 0; j < ng; j++) {
+        for (int q = 0; q < np; q++) {
+            int j = pj[q], h = ph[q];
             U = U_found < singleton ? U_found : singleton;
             if (!per_level && L >= U) { stop = 1; break; }
             int Lb = L;
             uint64_t mr = 0, ws = 0, cnt = 0;
-            int pm = orc_pair(Gam + (size_t)j * k * W, n, k, g, 0, UINT64_MAX, threads, &mr, &ws, &cnt, NULL);
-            if (pm < 0) { free(Gam); return pm; }
-            counts[(size_t)j * (k + 1) + g] = cnt;
-            wsum[(size_t)j * (k + 1) + g] = ws;
-            pair_min[(size_t)j * (k + 1) + g] = pm;
-            if (pm < U_found) { U_found = pm; wj = j; wg = g; wrank = mr; }
-            if (!per_level) {
+            int pm = orc_pair(Gam + (size_t)j * k * W, n, k, h, 0, UINT64_MAX, threads, &mr, &ws, &cnt, NULL);
+            if (pm < 0) { free(done); free(pj); free(ph); free(Gam); return pm; }
+            counts[(size_t)j * (k + 1) + h] = cnt;
+            wsum[(size_t)j * (k + 1) + h] = ws;
+            pair_min[(size_t)j * (k + 1) + h] = pm;
+            done[j] = h;
+            if (pm < U_found) { U_found = pm; wj = j; wg = h; wrank = mr; }
+            /* the bound from the levels each set has done: after every pair,
+               or only at the end of the level (literal per-level rule) */
+            if (!per_level || q == np - 1) {
                 int s = 0;
-                for (int i = 0; i < ng; i++) s += f_bound(i, (i <= j || orc_fault == 2) ? g : g - 1, m_full, k, k_m);
+                for (int i = 0; i < ng; i++)
+                    s += f_bound(i, (orc_fault == 2 && i < m_full) ? g : done[i], m_full, k, k_m);
                 L = s;
             }
             U = U_found < singleton ? U_found : singleton;
             if (trace && pairs < trace_cap) {
                 int *t = trace + 6 * pairs;
-                t[0] = j; t[1] = g; t[2] = Lb; t[3] = L; t[4] = U; t[5] = pm;
+                t[0] = j; t[1] = h; t[2] = Lb; t[3] = L; t[4] = U; t[5] = pm;
             }
             pairs++;
             last_g = g;
         }
-        if (per_level) {
-            int s = 0;
-            for (int i = 0; i < ng; i++) s += f_bound(i, g, m_full, k, k_m);
-            L = s;
-        }
         if (stop) break;
     }
+    free(done); free(pj); free(ph);
     int U = U_found < singleton ? U_found : singleton;
     if (info) {
         info[0] = U; info[1] = m_full; info[2] = k_m; info[3] = ng;

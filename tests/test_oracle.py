@@ -82,14 +82,14 @@ def test_bz_textbook_small(ctor):
     G, n, k = ctor()
     d_b, _, _ = oracle.brute(G, n, k)
     for per_level in (False, True):
-        for never in (False, True):
-            r = oracle.bz(G, n, k, per_level=per_level, partial_never=never)
+        for partial in ("always", "never", "when_useful"):
+            r = oracle.bz(G, n, k, per_level=per_level, partial=partial)
             assert r["d"] == d_b
 
 
 def test_bz_equals_brute_random_codes():
-    """Plain definition vs Algorithm 1 (both termination rules, with and
-    without the partial set) on 1200 seeded random codes, k <= 20."""
+    """Plain definition vs Algorithm 1 (both termination rules, the partial
+    set always, never or when useful) on 1200 seeded random codes, k <= 20."""
     rng = PCG32(1234, 7)
     checked = 0
     for i in range(1200):
@@ -106,6 +106,8 @@ def test_bz_equals_brute_random_codes():
         assert rl["d"] == d_b
         rn = oracle.bz(G, n, k, partial_never=True)
         assert rn["d"] == d_b
+        ru = oracle.bz(G, n, k, partial="when_useful")
+        assert ru["d"] == d_b
         checked += 1
     assert checked > 1000
 
@@ -383,6 +385,92 @@ def test_bz_per_pair_matches_printed_formula_at_level_ends():
                 assert Lb == mf * g + max(0, g - k + km)
 
 
+# ---- the lower bound is a lower bound ------------------------------------------
+
+def _all_codewords(Gb):
+    k = Gb.shape[0]
+    msgs = ((np.arange(1 << k)[:, None] >> np.arange(k)[None, :]) & 1).astype(np.uint8)
+    return ((msgs @ Gb) % 2)[1:]
+
+
+def _assert_bound_sound(G, n, k, **kw):
+    """Section 2's lower bound by its meaning: after each visited pair, every
+    nonzero codeword that no pair (j, h) so far has enumerated -- its message
+    under Gamma_j, read at the pivot columns, does not weigh h -- weighs at
+    least L (brute force over all 2^k codewords)."""
+    r = oracle.bz(G, n, k, **kw)
+    full, part = oracle.partition(G, n, k)
+    sets = full + ([part] if part and r["n_gamma"] > len(full) else [])
+    X = _all_codewords(codes.unpack(G, n))
+    wt = X.sum(axis=1)
+    msg_wt = []
+    for s in sets:
+        order = list(s) + [c for c in range(n) if c not in set(s)]
+        lead = _assert_rref(codes.unpack(oracle.gamma(G, n, k, s), n), order, s)
+        msg_wt.append(X[:, lead].sum(axis=1))
+    covered = np.zeros(len(X), dtype=bool)
+    for (j, h, Lb, La, U, pm) in r["trace"].tolist():
+        left = wt[~covered]
+        assert left.size == 0 or left.min() >= Lb, (j, h, "before", Lb, left.min())
+        covered |= msg_wt[j] == h
+        left = wt[~covered]
+        assert left.size == 0 or left.min() >= La, (j, h, "after", La, left.min())
+    return r
+
+
+def test_lower_bound_is_sound_by_brute_force():
+    """Every rule and partial-set policy, on 300 seeded random codes with
+    k <= 13: no codeword left unenumerated weighs less than L."""
+    rng = PCG32(4321, 9)
+    checked = 0
+    for _ in range(300):
+        n = rng.uniform_int(10, 40)
+        k = rng.uniform_int(4, min(13, n - 1))
+        G = draw_matrix(rng, n, k)
+        try:
+            oracle.brute(G, n, k)
+        except oracle.OracleError:
+            continue
+        for kw in ({}, {"per_level": True}, {"partial": "when_useful"},
+                   {"partial": "when_useful", "per_level": True}, {"partial": "never"}):
+            _assert_bound_sound(G, n, k, **kw)
+        checked += 1
+    assert checked > 250
+
+
+def _when_useful_code():
+    """A [27,6] code whose partial set (rank 4, so its bound term is positive
+    from level 2 on) holds the only codeword of weight 6 at message weight 1:
+    x = (1,1,1,0,0,0) G weighs 3 on each full set and vanishes on the 15
+    remaining columns, which span only the 4 functionals orthogonal to
+    (1,1,1,0,0,0) and (0,0,0,1,1,1)."""
+    k = 6
+    B = np.array([[1, 1, 1, 0, 1, 1], [1, 0, 0, 1, 0, 0], [0, 1, 0, 1, 0, 0],
+                  [1, 1, 1, 1, 0, 0], [1, 1, 1, 0, 0, 1], [0, 0, 1, 0, 1, 0]], dtype=np.uint8)
+    perp = np.array([[1, 1, 0, 0, 0, 0], [1, 0, 1, 0, 0, 0],
+                     [0, 0, 0, 1, 1, 0], [0, 0, 0, 1, 0, 1]], dtype=np.uint8).T
+    pats = np.array([[(v >> b) & 1 for b in range(4)] for v in range(1, 16)], dtype=np.uint8).T
+    bits = np.concatenate([np.eye(k, dtype=np.uint8), B, (perp @ pats) % 2], axis=1)
+    return codes.pack(bits), bits.shape[1], k
+
+
+def test_partial_set_when_useful_catches_up_its_lower_levels():
+    """Deferring the partial set to its first useful level: its bound term
+    at level 2 needs the set's level 1 too.  Here that level holds the only
+    codeword of minimum weight, found by the catch-up pair (2, 1)."""
+    G, n, k = _when_useful_code()
+    d, _, _ = oracle.brute(G, n, k)
+    assert d == 6
+    full, part = oracle.partition(G, n, k)
+    assert len(full) == 2 and len(part) == 4
+    r = _assert_bound_sound(G, n, k, partial="when_useful")
+    assert r["d"] == 6
+    assert [tuple(t[:2]) for t in r["trace"].tolist()] == [(0, 1), (1, 1), (0, 2), (1, 2), (2, 1)]
+    assert r["witness_pair"] == (2, 1)
+    for policy in ("always", "never"):
+        assert oracle.bz(G, n, k, partial=policy)["d"] == 6
+
+
 # ---- the pins catch plausible mistakes ----------------------------------------
 
 def _fails(pin):
@@ -397,11 +485,13 @@ def _fails(pin):
 _CATCHERS = {
     1: [test_bz_per_level_bound_is_the_printed_formula,
         test_bz_per_pair_matches_printed_formula_at_level_ends],
-    2: [test_bz_equals_brute_random_codes, test_bz_equals_brute_k20],
+    2: [test_bz_equals_brute_random_codes, test_bz_equals_brute_k20,
+        test_lower_bound_is_sound_by_brute_force],
     3: [lambda: test_stack_cost_lemma(8, 4), lambda: test_pair_weight_sum_closed_form(100, 30, 5),
         test_bz_counts_are_binomials_and_bound_sound],
     4: [test_gamma_is_systematic_and_row_equivalent],
     6: [test_gamma_is_the_reduced_echelon_form_partial_set_included],
+    7: [test_partial_set_when_useful_catches_up_its_lower_levels],
     5: [lambda: test_pair_weight_sum_closed_form(150, 75, 2),
         lambda: test_bz_reed_muller_large_k(2, 7, 32)],
 }
@@ -411,7 +501,8 @@ _CATCHERS = {
 def test_planted_mistakes_are_caught(fault):
     """Each planted mistake (a dropped bound term, a wrong level index, a
     skipped combination, an incomplete reduction, a dropped word, a partial
-    set whose lower block is left unreduced above its pivots) makes at
+    set whose lower block is left unreduced above its pivots, a deferred
+    partial set counted without its lower levels) makes at
     least one pin fail; with no mistake planted all of them pass."""
     with oracle.planted(fault):
         caught = [_fails(p) for p in _CATCHERS[fault]]

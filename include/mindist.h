@@ -39,10 +39,11 @@ extern "C" {
 #define MINDIST_E_CANCELLED  -6   /* stopped by MINDIST_OPT_CANCEL_AFTER_CHUNKS */
 #define MINDIST_E_TIMEOUT    -7   /* MINDIST_OPT_DEADLINE_MS elapsed */
 #define MINDIST_E_STATE      -8   /* call out of order (e.g. results before a run) */
-#define MINDIST_E_CERT       -9   /* the result failed its certificate: a pair stopped
-                                     early although the least weight found was above the
-                                     bound before it, or the witness slot does not decode
-                                     to a codeword of the found weight */
+#define MINDIST_E_CERT       -9   /* the result failed its certificate (mindist_certify):
+                                     the visited pairs, their counts or bounds differ from
+                                     Algorithm 1's, a pair stopped early although the least
+                                     weight found was above the bound before it, or the
+                                     witness is not a codeword of weight d */
 
 #define MINDIST_MAX_N      512
 #define MINDIST_MAX_WORDS  8
@@ -57,8 +58,16 @@ extern "C" {
  * per-pair termination); the visited pairs, d and every pair minimum are
  * unchanged, only the executed count of the final pair shrinks. */
 #define MINDIST_OPT_MIDPAIR_EXIT     2
-/* 0 (default) = enumerate the partial (rank k_m < k) set at every level as
- * Algorithm 1's loop over j = 1..m does; 1 = drop it and its bound term. */
+/* The partial (rank k_m < k) information set, Algorithm 1's loop over
+ * j = 1..m with Section 2's bound term f_m(g) = max(0, g+1-(k-k_m)):
+ * 0 (default) = enumerate it at every level, as the loop does;
+ * 1 = drop it and its bound term;
+ * 2 = only when useful: from the first level g0 = k-k_m at which its term is
+ *     positive.  The term counts only once every level up to g is done under
+ *     Gamma_m, so at g0 the set also enumerates its levels 1..g0-1
+ *     (ascending, after the full sets' pairs of level g0); later levels visit
+ *     it once, at their own level.  d is the same under all three; the
+ *     visited pairs differ. */
 #define MINDIST_OPT_PARTIAL          3
 /* 1 = also accumulate the sum of weights of every pair (checkable against a
  * closed form); slower.  0 (default) off. */
@@ -232,6 +241,44 @@ int mindist_plan(const uint64_t *G, int n, int k, int *sets, int *m_full,
  * f_full(h) = h+1, f_partial(h) = max(0, h+1-(k-k_m)). */
 int mindist_bound_after(int k, int m_full, int k_partial, int include_partial,
                         int j, int w);
+
+/* Host-only: Algorithm 1's pair order (Section 2) for a partition with
+ * m_full >= 1 full sets and a partial set of rank k_partial (0 = none) under
+ * MINDIST_OPT_PARTIAL's policy (0, 1, 2) and termination rule (per_level 0 =
+ * raise L after every Gamma_j, 1 = once per level), up to level k, as if no
+ * codeword were ever found.  Pair t is written to out[4t .. 4t+3] = (set j,
+ * level w it enumerates, Algorithm 1's outer level g, L after it); at most
+ * cap pairs are written and *n_out receives the schedule's length.  Errors:
+ * MINDIST_E_ARG. */
+int mindist_schedule(int k, int m_full, int k_partial, int partial_policy, int per_level,
+                     int32_t *out, int cap, int *n_out);
+
+/* the run a certificate checks: the code's size and partition and the
+ * options it ran under */
+typedef struct mindist_cert_spec {
+    int32_t n, k, m_full, k_partial;
+    int32_t partial_policy;   /* MINDIST_OPT_PARTIAL */
+    int32_t per_level;        /* MINDIST_OPT_TERM */
+    int32_t midpair_exit;     /* MINDIST_OPT_MIDPAIR_EXIT */
+} mindist_cert_spec;
+
+/* Host-only: the certificate every run of mindist_run, mindist_run_batch and
+ * the servers passes before it returns a result (Section 2, Algorithm 1's
+ * termination; the run returns MINDIST_E_CERT otherwise).  The visited pairs
+ * must follow mindist_schedule's order from L = 1 and U = n-k+1; each covers
+ * C(k, w) combinations and every completed one evaluated exactly that many;
+ * L_before, L_after and U_after of each pair equal the recomputed values
+ * (U = the least pair minimum so far, capped at n-k+1); Algorithm 1's test
+ * L < U held before each pair (before each level under per_level); only the
+ * last pair may be cut short, only with mid-pair exit, and only when U <= L
+ * before it; the run ended because L >= U, because its last pair was cut,
+ * or because level k was done; d equals the final U and L_final the final L;
+ * exited_midpair says whether the last pair was cut.  Only the fields j, w,
+ * L_before, L_after, U_after, pair_min, count and executed of pairs are
+ * read.  Returns MINDIST_OK, MINDIST_E_CERT (reason in mindist_last_error)
+ * or MINDIST_E_ARG. */
+int mindist_certify(const mindist_cert_spec *spec, const mindist_pair *pairs, int n_pairs,
+                    int d, int L_final, int exited_midpair);
 
 /* Host-only: the r-subset {x_1 < ... < x_r} of [0, hi) whose colex rank
  * sum_t C(x_t, t) is `rank` (the combinatorial number system the kernels

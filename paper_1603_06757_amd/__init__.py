@@ -3,11 +3,18 @@
 Argument marshalling only: every step of the computation runs in the C++
 host code and the HIP kernels of the library.  The binding raises if the
 library has not been built; there is no fallback.
+
+PyTorch interop (a torch stream passed as the "stream" option): torch ships
+its own HIP runtime, and a process must hold only one.  If torch is imported
+before this module first loads the library, the library binds to torch's
+runtime and torch's streams are valid for it; if the library loads first,
+passing a torch stream raises MindistError(E_ARG).
 """
 from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -24,6 +31,9 @@ OPT = {"term": 1, "midpair_exit": 2, "partial": 3, "verify": 4, "stream": 5,
        "inject_u": 18}
 
 MAX_WORDS = 8
+
+# MINDIST_OPT_PARTIAL values
+PARTIAL = {"always": 0, "never": 1, "when_useful": 2}
 
 
 class MindistError(RuntimeError):
@@ -72,6 +82,11 @@ class Pair(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class CertSpec(C.Structure):
+    _fields_ = [("n", C.c_int32), ("k", C.c_int32), ("m_full", C.c_int32), ("k_partial", C.c_int32),
+                ("partial_policy", C.c_int32), ("per_level", C.c_int32), ("midpair_exit", C.c_int32)]
+
+
 class BatchOpts(C.Structure):
     _fields_ = [("tile_min", C.c_int32), ("tile_max", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("use_graph", C.c_int32), ("table_kib", C.c_int32), ("jobs_per_code", C.c_int32),
@@ -107,6 +122,7 @@ class ServerStats(C.Structure):
 
 
 _lib = None
+_with_torch = False      # torch was loaded before the library (one HIP runtime)
 
 
 def lib():
@@ -116,6 +132,8 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1603_06757_amd.build`")
+        global _with_torch
+        _with_torch = "torch" in sys.modules
         L = C.CDLL(LIB_PATH)
         u64p, ip, vp = C.POINTER(C.c_uint64), C.POINTER(C.c_int), C.c_void_p
         L.mindist_create.argtypes = [u64p, C.c_int, C.c_int, C.POINTER(vp)]
@@ -129,6 +147,9 @@ def lib():
         L.mindist_plan.argtypes = [u64p, C.c_int, C.c_int, ip, ip, ip, u64p]
         L.mindist_bound_after.argtypes = [C.c_int] * 6
         L.mindist_colex_unrank.argtypes = [C.c_uint64, C.c_int, C.c_int, ip]
+        L.mindist_schedule.argtypes = [C.c_int] * 5 + [C.POINTER(C.c_int32), C.c_int, ip]
+        L.mindist_certify.argtypes = [C.POINTER(CertSpec), C.POINTER(Pair), C.c_int, C.c_int,
+                                      C.c_int, C.c_int]
         L.mindist_calibrate.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
         L.mindist_device.argtypes = [C.c_char_p, C.c_int, ip]
@@ -209,6 +230,35 @@ def bound_after(k, m_full, k_partial, include_partial, j, w) -> int:
     return _check(lib().mindist_bound_after(k, m_full, k_partial, int(include_partial), j, w))
 
 
+def _policy(partial) -> int:
+    return PARTIAL[partial] if isinstance(partial, str) else int(partial)
+
+
+def schedule(k: int, m_full: int, k_partial: int, partial=0, per_level: bool = False) -> list:
+    """Host-only: Algorithm 1's pairs up to level k as (j, w, g, L_after) tuples."""
+    n = C.c_int(0)
+    _check(lib().mindist_schedule(k, m_full, k_partial, _policy(partial), int(per_level), None, 0,
+                                  C.byref(n)))
+    out = (C.c_int32 * (4 * max(n.value, 1)))()
+    _check(lib().mindist_schedule(k, m_full, k_partial, _policy(partial), int(per_level), out,
+                                  n.value, C.byref(n)))
+    return [tuple(out[4 * t:4 * t + 4]) for t in range(n.value)]
+
+
+def certify(n: int, k: int, m_full: int, k_partial: int, pairs: list, d: int, L_final: int,
+            exited_midpair: int = 0, partial=0, per_level: bool = False,
+            midpair_exit: bool = True) -> int:
+    """Host-only: run the library's certificate over a visited-pair trace
+    (dicts with j, w, L_before, L_after, U_after, pair_min, count, executed).
+    Returns 0; raises MindistError (E_CERT) when the trace fails it."""
+    spec = CertSpec(n, k, m_full, k_partial, _policy(partial), int(per_level), int(midpair_exit))
+    arr = (Pair * max(len(pairs), 1))()
+    for t, p in enumerate(pairs):
+        for f in ("j", "w", "L_before", "L_after", "U_after", "pair_min", "count", "executed"):
+            setattr(arr[t], f, int(p[f]))
+    return _check(lib().mindist_certify(C.byref(spec), arr, len(pairs), d, L_final, exited_midpair))
+
+
 class MinDist:
     """One code: mindist_create / set_option / run / get_pairs / destroy."""
 
@@ -221,7 +271,15 @@ class MinDist:
         for key, v in options.items():
             self.set_option(key, v)
 
-    def set_option(self, key: str, value: int):
+    def set_option(self, key: str, value):
+        if key == "partial":
+            value = _policy(value)
+        if key == "stream" and hasattr(value, "cuda_stream"):
+            # a torch stream object
+            if not _with_torch:
+                raise MindistError(-1, "the library was loaded before torch: import torch "
+                                       "first to share its HIP runtime and streams")
+            value = value.cuda_stream
         _check(lib().mindist_set_option(self._h, OPT[key], int(value)))
 
     def info(self):

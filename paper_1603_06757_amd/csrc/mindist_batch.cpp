@@ -299,26 +299,31 @@ int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *ar
     out.d = (int)std::min<uint32_t>(bc.U_found, singleton);
     out.executed_total = executed;
     out.canonical_total = canonical;
+    {
+        // the device sequencer's decisions, rechecked on the host: per-pair
+        // bounds, the partial set at every level, mid-pair exit
+        CertSpec cs;
+        cs.n = n;
+        cs.k = k;
+        cs.sched = Schedule(k, hc.P.m_full, hc.P.k_m, kPartialAlways);
+        std::vector<PairView> views(trace.size());
+        for (size_t t = 0; t < trace.size(); ++t) {
+            const mindist_pair &r = trace[t];
+            views[t] = PairView{r.j, r.w, r.L_before, r.L_after, r.U_after, r.pair_min, r.count, r.executed};
+        }
+        const int e = certify_trace(cs, views.data(), (int)views.size(), out.d, out.L_final,
+                                    out.exited_midpair);
+        if (e) return e;
+    }
     if (bc.U_found != kInf) {
         const Slot s = slots[bc.U_found];
         if (s.pair < 1 || s.pair >= (uint32_t)bc.njobs)
-            return fail(MINDIST_E_HIP, "batch witness slot holds an invalid job index");
+            return fail(MINDIST_E_CERT, "batch witness slot holds an invalid job index");
         const BatchJob *jb = reinterpret_cast<const BatchJob *>(arena + (size_t)(bc.job[s.pair] - arena_lo) * 128);
-        const int j = jb->j;
         const std::vector<int> rows = witness_rows(k, jb->a, jb->b, jb->b2, s);
-        if ((int)rows.size() != jb->w)
-            return fail(MINDIST_E_HIP, "batch witness decodes to an invalid combination");
-        uint64_t word[MINDIST_MAX_WORDS] = {0};
-        for (int r : rows) {
-            for (int t = 0; t < hc.P.W; ++t) word[t] ^= hc.P.gamma[j][(size_t)r * hc.P.W + t];
-            out.witness_rows[r >> 6] |= 1ull << (r & 63);
-        }
-        int wt = 0;
-        for (int t = 0; t < hc.P.W; ++t) wt += __builtin_popcountll(word[t]);
-        if (wt != (int)bc.U_found)
-            return fail(MINDIST_E_HIP, "batch witness weight differs from the found weight");
-        std::memcpy(out.witness, word, sizeof(uint64_t) * hc.P.W);
-        out.witness_j = j;
+        const int e = certify_witness(hc.P, jb->j, rows, jb->w, (int)bc.U_found, out.witness, out.witness_rows);
+        if (e) return e;
+        out.witness_j = jb->j;
         out.witness_w = jb->w;
     }
     (void)B;
@@ -542,15 +547,22 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
         drc[s] = decode_code(hc[i], eng.h_codes[s], eng.h_arena, 0, slots, out[i], traces[s], eng.wall_hz);
         if (drc[s]) derr[s] = last_error_text();
     });
+    int cert_fail = -1;
     for (int s = 0; s < L; ++s) {
         executed += out[live[s]].executed_total;
         if (drc[s] == MINDIST_E_HIP) return fail(MINDIST_E_HIP, derr[s]);
+        if (drc[s] == MINDIST_E_CERT) {
+            out[live[s]].d = MINDIST_E_CERT;
+            if (cert_fail < 0) cert_fail = s;
+        }
     }
     // the codes routed to the single path, after the persistent launch
     e = run_direct(eng.kernel_seconds);
     if (e) return e;
     for (int i : direct) if (out[i].d > 0) executed += out[i].executed_total;
     write_pairs(&traces);
+    if (cert_fail >= 0)
+        return fail(MINDIST_E_CERT, "batch code " + std::to_string(live[cert_fail]) + ": " + derr[cert_fail]);
     if (timed_out || direct_timed_out)
         return fail(MINDIST_E_TIMEOUT, "batch deadline reached before every code finished");
     o.seconds_kernel = eng.kernel_seconds + direct_s;

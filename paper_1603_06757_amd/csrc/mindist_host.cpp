@@ -37,6 +37,10 @@ const char *last_error_text();
 
 extern "C" const char *mindist_last_error(void) { return md::last_error_text(); }
 
+static PairView view_of(const mindist_pair &r) {
+    return PairView{r.j, r.w, r.L_before, r.L_after, r.U_after, r.pair_min, r.count, r.executed};
+}
+
 namespace {
 
 struct GammaDev {
@@ -66,7 +70,7 @@ struct mindist_ctx {
     int n_gamma = 0;           // enumerated sets (partial included unless dropped)
     std::vector<GammaDev> gd;
     // options
-    int term_per_level = 0, midpair_exit = 1, partial_never = 0, verify = 0, profile = 0;
+    int term_per_level = 0, midpair_exit = 1, partial_policy = kPartialAlways, verify = 0, profile = 0;
     int64_t deadline_ms = 0;
     uint64_t cancel_after = 0;
     uint32_t tile_t = 0;       // 0: chosen per pair
@@ -229,6 +233,44 @@ extern "C" int mindist_bound_after(int k, int m_full, int k_partial, int include
     return bound_after(k, m_full, k_partial, ng, j, w);
 }
 
+extern "C" int mindist_schedule(int k, int m_full, int k_partial, int partial_policy, int per_level,
+                                int32_t *out, int cap, int *n_out) {
+    if (k < 1 || m_full < 1 || k_partial < 0 || k_partial >= k || partial_policy < 0 ||
+        partial_policy > 2 || cap < 0 || (cap > 0 && !out) || !n_out)
+        return fail(MINDIST_E_ARG, "schedule: bad arguments");
+    const Schedule S(k, m_full, k_partial, partial_policy);
+    PairPos p = S.first();
+    int t = 0, L = 1;
+    for (bool more = true; more; more = S.next(p, &p), ++t) {
+        L = S.L_after(p, per_level != 0, L);
+        if (t < cap) {
+            out[4 * t] = p.j;
+            out[4 * t + 1] = p.h;
+            out[4 * t + 2] = p.g;
+            out[4 * t + 3] = L;
+        }
+    }
+    *n_out = t;
+    return MINDIST_OK;
+}
+
+extern "C" int mindist_certify(const mindist_cert_spec *spec, const mindist_pair *pairs, int n_pairs,
+                               int d, int L_final, int exited_midpair) {
+    if (!spec || (n_pairs > 0 && !pairs) || n_pairs < 0) return fail(MINDIST_E_ARG, "certify: bad arguments");
+    if (spec->k < 1 || spec->n <= spec->k || spec->m_full < 1 || spec->k_partial < 0 ||
+        spec->k_partial >= spec->k || spec->partial_policy < 0 || spec->partial_policy > 2)
+        return fail(MINDIST_E_ARG, "certify: bad spec");
+    CertSpec cs;
+    cs.n = spec->n;
+    cs.k = spec->k;
+    cs.sched = Schedule(spec->k, spec->m_full, spec->k_partial, spec->partial_policy);
+    cs.per_level = spec->per_level != 0;
+    cs.midpair_exit = spec->midpair_exit != 0;
+    std::vector<PairView> v((size_t)n_pairs);
+    for (int t = 0; t < n_pairs; ++t) v[t] = view_of(pairs[t]);
+    return certify_trace(cs, v.data(), n_pairs, d, L_final, exited_midpair);
+}
+
 extern "C" int mindist_colex_unrank(uint64_t rank, int r, int hi, int *out) {
     if (!out || r < 0 || r > 64 || hi < r || hi > 512) return fail(MINDIST_E_ARG, "bad unrank query");
     if (rank >= BN()(hi, r)) return fail(MINDIST_E_ARG, "rank out of range");
@@ -299,7 +341,9 @@ extern "C" int mindist_set_option(mindist_ctx *c, int key, int64_t v) {
     switch (key) {
         case MINDIST_OPT_TERM: c->term_per_level = v ? 1 : 0; break;
         case MINDIST_OPT_MIDPAIR_EXIT: c->midpair_exit = v ? 1 : 0; break;
-        case MINDIST_OPT_PARTIAL: c->partial_never = v ? 1 : 0; break;
+        case MINDIST_OPT_PARTIAL:
+            if (v < 0 || v > 2) return fail(MINDIST_E_ARG, "partial policy must be 0, 1 or 2");
+            c->partial_policy = (int)v; break;
         case MINDIST_OPT_VERIFY: c->verify = v ? 1 : 0; break;
         case MINDIST_OPT_STREAM:
             if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -360,7 +404,7 @@ extern "C" int mindist_info(const mindist_ctx *c, int *m_full, int *k_partial, i
     if (!c) return fail(MINDIST_E_ARG, "ctx is NULL");
     if (m_full) *m_full = c->P.m_full;
     if (k_partial) *k_partial = c->P.k_m;
-    if (n_gamma) *n_gamma = c->partial_never ? c->P.m_full : c->n_gamma;
+    if (n_gamma) *n_gamma = Schedule(c->P.k, c->P.m_full, c->P.k_m, c->partial_policy).n_sets();
     return MINDIST_OK;
 }
 
@@ -468,7 +512,9 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
     const auto t0 = std::chrono::steady_clock::now();
     const Plan &P = c->P;
     const int n = P.n, k = P.k;
-    const int ng = c->partial_never ? P.m_full : c->n_gamma;
+    const Schedule S(k, P.m_full, P.k_m, c->partial_policy);
+    const int ng = S.n_sets();
+    const bool per_level = c->term_per_level != 0;
     const Binom &B = BN();
     std::memset(out, 0, sizeof(*out));
     c->trace.clear();
@@ -611,7 +657,7 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
     }
 
     // A pair ready to run as pair index idx with bound L_prev.
-    struct Flight { Prep q; int idx = 0; int L_prev = 0; int blocks = 0; };
+    struct Flight { Prep q; PairPos pos; int idx = 0; int L_prev = 0; int blocks = 0; };
     auto blocks_of = [&](const PairPlan &pp) {
         const uint64_t want = ceil_div(pp.total_chunks, 4);
         return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->cus * c->blocks_per_cu));
@@ -679,14 +725,6 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         ++launches;
         return MINDIST_OK;
     };
-    // the bound after pair (j, w) if it completes (known before its result)
-    auto L_after_pair = [&](int j, int w, int L_now) {
-        if (!c->term_per_level) return bound_after(k, P.m_full, P.k_m, ng, j, w);
-        if (j != ng - 1) return L_now;
-        int sum = 0;
-        for (int i = 0; i < ng; ++i) sum += bound_f(i, w, P.m_full, k, P.k_m);
-        return sum;
-    };
     auto beyond_limit = [&](int w) { return w > MINDIST_MAX_LEVEL || B(k, w) >= (1ull << 63); };
 
     // Pairs run in Algorithm 1's order.  The pair Algorithm 1 visits next is
@@ -700,7 +738,8 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
     // (with mid-pair exit on; otherwise only one pair of at most `speculate`
     // combinations is launched ahead, and no launch is shared).
     std::deque<Flight> fl;          // launched, not read yet; front: next pair visited
-    int nj = 0, nw = 1;             // the next pair to launch
+    PairPos npos = S.first();       // the next pair to launch
+    bool nmore = true;              // npos is a pair of the schedule
     int L_pred = L;                 // the bound before it
     int next_idx = 0;
     PairMail last_mail{};
@@ -708,8 +747,7 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
     const bool grouping = free_exit && c->speculate && !c->order && !c->cancel_after;
     const int resident_blocks = c->cus * c->blocks_per_cu;
     constexpr uint64_t kAheadWork = 1ull << 30;   // queued combinations that stop a second launch ahead
-    auto advance = [&](int &j, int &w) { if (++j >= ng) { j = 0; ++w; } };
-    // Stage pair (nj, nw) as index next_idx with bound L0, extend the launch
+    // Stage pair npos as index next_idx with bound L0, extend the launch
     // with the following short pairs when allowed, launch, and queue them.
     auto launch_from_next = [&](int L0, bool may_group) -> int {
         std::vector<Flight> grp;
@@ -717,13 +755,14 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         int blocks = 0;
         for (;;) {
             Flight f;
-            int e = plan(f.q, nj, nw);
+            f.pos = npos;
+            int e = plan(f.q, npos.j, npos.h);
             if (e) return e;
             f.blocks = blocks_of(f.q.pp);
             if (!grp.empty()) {
                 // joins the launch only if it is short and of the same width
                 const bool ok = f.q.pp.b2 == 0 && grp[0].q.pp.b2 == 0 &&
-                                c->gd[nj].D == c->gd[grp[0].q.j].D &&
+                                c->gd[npos.j].D == c->gd[grp[0].q.j].D &&
                                 (uint64_t)f.q.pp.total_chunks <= 4ull * (uint64_t)f.blocks &&
                                 blocks + f.blocks <= resident_blocks;
                 if (!ok) break;
@@ -738,12 +777,12 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
             f.L_prev = L_cur;
             blocks += f.blocks;
             grp.push_back(f);
-            L_cur = L_after_pair(nj, nw, L_cur);
+            L_cur = S.L_after(npos, per_level, L_cur);
             L_pred = L_cur;
-            advance(nj, nw);
+            nmore = S.next(npos, &npos);
             const bool first_short = (uint64_t)grp[0].q.pp.total_chunks <= 4ull * (uint64_t)grp[0].blocks;
             if (!may_group || !grouping || !first_short || (int)grp.size() >= kGroupMax ||
-                fl.size() + grp.size() >= (size_t)kMailRing - 1 || nw > k || beyond_limit(nw) ||
+                fl.size() + grp.size() >= (size_t)kMailRing - 1 || !nmore || beyond_limit(npos.h) ||
                 next_idx >= c->max_pairs ||
                 L_cur >= (int)std::min<uint32_t>(U_found, (uint32_t)singleton))
                 break;
@@ -754,12 +793,12 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         return MINDIST_OK;
     };
     for (bool more = ng >= 1 && k >= 1; more;) {
-        const int j = fl.empty() ? nj : fl.front().q.j;
-        const int w = fl.empty() ? nw : fl.front().q.w;
+        const PairPos pos = fl.empty() ? npos : fl.front().pos;
+        const int j = pos.j, w = pos.h;
         const int U = (int)std::min<uint32_t>(U_found, (uint32_t)singleton);
         // Algorithm 1's test: before every pair (per-pair rule) or before a
         // level (literal per-level rule)
-        if (L >= U && (!c->term_per_level || j == 0)) break;
+        if (L >= U && (!per_level || S.level_start(pos))) break;
         if (beyond_limit(w)) {
             status = fail(MINDIST_E_LIMIT, "pair (" + std::to_string(j) + "," + std::to_string(w) +
                                                ") exceeds the rank-space limit");
@@ -780,13 +819,13 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         // (not once the U already known is at or below the pair's bound:
         // Algorithm 1 certainly stops before it)
         while (c->speculate && !c->cancel_after && !c->order && fl.size() < (size_t)kMailRing - 1 &&
-               nw <= k && !beyond_limit(nw) && next_idx < c->max_pairs &&
+               nmore && !beyond_limit(npos.h) && next_idx < c->max_pairs &&
                L_pred < (int)std::min<uint32_t>(U_found, (uint32_t)singleton)) {
             uint64_t queued = 0;
             for (const Flight &x : fl) queued += B(k, x.q.w);
             // one pair ahead always; more only while the queued work is short
             if (free_exit ? (fl.size() >= 2 && queued >= kAheadWork)
-                          : (fl.size() >= 2 || B(k, nw) > c->speculate))
+                          : (fl.size() >= 2 || B(k, npos.h) > c->speculate))
                 break;
             int e = launch_from_next(L_pred, true);
             if (e) return e;
@@ -804,7 +843,7 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         U_found = std::min(U_found, hm.pair_min);
         const int Lb = L;
         const bool cut = midpair && hm.executed < B(k, w) && !hm.cancelled;
-        if (!c->term_per_level && !cut) L = bound_after(k, P.m_full, P.k_m, ng, j, w);
+        if (!cut) L = S.L_after(pos, per_level, L);
         mindist_pair rec{};
         rec.j = j; rec.w = w; rec.L_before = Lb; rec.L_after = L;
         rec.U_after = (int)std::min<uint32_t>(U_found, (uint32_t)singleton);
@@ -825,24 +864,13 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         last_j = j;
         last_w = w;
         if (hm.cancelled) { status = fail(MINDIST_E_CANCELLED, "cancelled after the chunk budget"); break; }
-        if (cut) {
-            // the kernels stop a pair only once the least weight they know
-            // (from earlier launches and earlier pairs of this one) is at or
-            // below the bound before it, and the host's U -- the least pair
-            // minimum up to this pair -- is never above theirs: a cut the
-            // host's own U does not justify leaves the enumeration short
-            if ((int)std::min<uint32_t>(U_found, (uint32_t)singleton) > Lb) {
-                status = fail(MINDIST_E_CERT, "pair (" + std::to_string(j) + "," + std::to_string(w) +
-                                                  ") stopped early although U > L before it");
-                break;
-            }
-            exited = 1;
-            break;
-        }
-        if (c->term_per_level && j == ng - 1) L = L_after_pair(j, w, L);
-        int j2 = j, w2 = w;
-        advance(j2, w2);
-        if (w2 > k) break;
+        // the kernels stop a pair only once the least weight they know (from
+        // earlier launches and earlier pairs of this one) is at or below the
+        // bound before it; the certificate below checks that the host's own
+        // U -- the least pair minimum up to this pair -- justifies the cut
+        if (cut) { exited = 1; break; }
+        PairPos nx;
+        if (!S.next(pos, &nx)) break;
     }
     // pairs launched ahead of a stop still run (they find nothing below U
     // and leave at once): return with the stream idle
@@ -879,6 +907,19 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         out->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         return status;
     }
+    {
+        CertSpec cs;
+        cs.n = n;
+        cs.k = k;
+        cs.sched = S;
+        cs.per_level = per_level;
+        cs.midpair_exit = midpair != 0;
+        std::vector<PairView> views(c->trace.size());
+        for (size_t t = 0; t < views.size(); ++t) views[t] = view_of(c->trace[t]);
+        const int e = certify_trace(cs, views.data(), (int)views.size(), out->d, out->L_final,
+                                    out->exited_midpair);
+        if (e) return e;
+    }
     // witness: slot[U_found], written by the wave that first lowered the
     // device's U_found to it, normally reaches the host in the mailbox of the
     // last pair read; it may come from a pair launched with the visited ones
@@ -900,23 +941,12 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         if (s.pair >= (uint32_t)launched_pairs.size())
             return fail(MINDIST_E_CERT, "witness slot holds an invalid pair index");
         const Flight &lp = launched_pairs[s.pair];
-        const int wj = lp.q.j, ww = lp.q.w;
         const std::vector<int> rows = witness_rows(k, lp.q.pp.a, lp.q.pp.b, lp.q.pp.b2, s);
-        if ((int)rows.size() != ww)
-            return fail(MINDIST_E_CERT, "witness slot decodes to an invalid combination");
-        uint64_t word[MINDIST_MAX_WORDS] = {0};
-        for (int r : rows) {
-            for (int t = 0; t < P.W; ++t) word[t] ^= P.gamma[wj][(size_t)r * P.W + t];
-            out->witness_rows[r >> 6] |= 1ull << (r & 63);
-        }
-        int wt = 0;
-        for (int t = 0; t < P.W; ++t) wt += __builtin_popcountll(word[t]);
-        if (wt != (int)U_found)
-            return fail(MINDIST_E_CERT, "witness weight " + std::to_string(wt) +
-                                           " differs from the found weight " + std::to_string(U_found));
-        std::memcpy(out->witness, word, sizeof(uint64_t) * P.W);
-        out->witness_j = wj;
-        out->witness_w = ww;
+        const int e = certify_witness(P, lp.q.j, rows, lp.q.w, (int)U_found, out->witness,
+                                      out->witness_rows);
+        if (e) return e;
+        out->witness_j = lp.q.j;
+        out->witness_w = lp.q.w;
     }
     out->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     c->have_run = true;

@@ -139,6 +139,143 @@ int bound_after(int k, int m_full, int k_m, int n_gamma, int j, int w) {
     return s;
 }
 
+bool Schedule::next(const PairPos &p, PairPos *q) const {
+    PairPos r = p;
+    const int g0 = k - k_m;   // first level the partial term is positive
+    if (p.j < m_full - 1) {
+        r.j = p.j + 1;
+        r.h = p.g;
+    } else if (p.j == m_full - 1 && has_partial() &&
+               (policy == kPartialAlways || p.g >= g0)) {
+        r.j = m_full;
+        r.h = (policy == kPartialWhenUseful && p.g == g0) ? 1 : p.g;
+    } else if (p.j == m_full && p.h < p.g) {
+        r.h = p.h + 1;
+    } else {
+        r.j = 0;
+        r.g = p.g + 1;
+        r.h = r.g;
+    }
+    if (r.g > k) return false;
+    *q = r;
+    return true;
+}
+
+bool Schedule::level_end(const PairPos &p) const {
+    PairPos q;
+    return !next(p, &q) || q.g != p.g;
+}
+
+int Schedule::bound_after(const PairPos &p) const {
+    int s = 0;
+    for (int i = 0; i < m_full; ++i) s += (i <= p.j) ? p.g + 1 : p.g;
+    if (has_partial()) {
+        // the level the partial set has done: h after its own pair, else the
+        // previous level (its term is 0 below g0, so a set not started yet
+        // under policy 2 counts the same)
+        const int done = p.j == m_full ? p.h : p.g - 1;
+        s += bound_f(m_full, done, m_full, k, k_m);
+    }
+    return s;
+}
+
+static int cert_fail(int t, const PairView &r, const std::string &what) {
+    return fail(MINDIST_E_CERT, "certificate: pair " + std::to_string(t) + " (" + std::to_string(r.j) +
+                                    "," + std::to_string(r.w) + "): " + what);
+}
+
+int certify_trace(const CertSpec &cs, const PairView *trace, int np, int d, int L_final,
+                  int exited_midpair) {
+    const Binom &B = BN();
+    const Schedule &S = cs.sched;
+    const int singleton = cs.n - cs.k + 1;
+    const uint32_t kNone = 0xffffffffu;
+    if (np < 1) return fail(MINDIST_E_CERT, "certificate: no pair visited");
+    PairPos pos = S.first();
+    bool more = true;
+    int L = 1;
+    uint32_t U_found = kNone;
+    auto U_now = [&]() { return (int)std::min<uint32_t>(U_found, (uint32_t)singleton); };
+    bool cut = false;
+    for (int t = 0; t < np; ++t) {
+        const PairView &r = trace[t];
+        if (!more) return cert_fail(t, r, "beyond the last level");
+        if (r.j != pos.j || r.w != pos.h)
+            return cert_fail(t, r, "out of order, expected (" + std::to_string(pos.j) + "," +
+                                       std::to_string(pos.h) + ")");
+        if ((!cs.per_level || S.level_start(pos)) && L >= U_now())
+            return cert_fail(t, r, "visited although L >= U before it");
+        if (r.L_before != L)
+            return cert_fail(t, r, "L before " + std::to_string(r.L_before) + ", expected " +
+                                       std::to_string(L));
+        if (r.count != B(cs.k, pos.h)) return cert_fail(t, r, "count is not C(k,w)");
+        if (r.executed > r.count) return cert_fail(t, r, "more combinations evaluated than C(k,w)");
+        if (r.executed > 0 && r.pair_min < 1) return cert_fail(t, r, "no least weight recorded");
+        if (r.pair_min >= 0) U_found = std::min<uint32_t>(U_found, (uint32_t)r.pair_min);
+        if (r.U_after != U_now())
+            return cert_fail(t, r, "U after " + std::to_string(r.U_after) + ", expected " +
+                                       std::to_string(U_now()));
+        if (r.executed < r.count) {
+            // mid-pair exit: the last pair only, and only once U <= L before it
+            if (t != np - 1) return cert_fail(t, r, "cut short but not the last pair");
+            if (!cs.midpair_exit || cs.per_level)
+                return cert_fail(t, r, "cut short with mid-pair exit off");
+            if (U_now() > L)
+                return cert_fail(t, r, "cut short although U = " + std::to_string(U_now()) +
+                                           " > L = " + std::to_string(L) + " before it");
+            if (r.L_after != L) return cert_fail(t, r, "a cut pair raised L");
+            cut = true;
+            break;
+        }
+        const int La = S.L_after(pos, cs.per_level, L);
+        if (r.L_after != La)
+            return cert_fail(t, r, "L after " + std::to_string(r.L_after) + ", expected " +
+                                       std::to_string(La));
+        L = La;
+        more = S.next(pos, &pos);
+    }
+    if (!cut && more && L < U_now())
+        return fail(MINDIST_E_CERT, "certificate: stopped with L = " + std::to_string(L) + " < U = " +
+                                        std::to_string(U_now()));
+    if ((exited_midpair != 0) != cut) return fail(MINDIST_E_CERT, "certificate: mid-pair exit flag");
+    if (d != U_now())
+        return fail(MINDIST_E_CERT, "certificate: d = " + std::to_string(d) + " but U = " +
+                                        std::to_string(U_now()));
+    if (L_final != L)
+        return fail(MINDIST_E_CERT, "certificate: final L = " + std::to_string(L_final) +
+                                        ", expected " + std::to_string(L));
+    if (U_found == kNone) return fail(MINDIST_E_CERT, "certificate: no codeword found");
+    return MINDIST_OK;
+}
+
+int certify_witness(const Plan &P, int j, const std::vector<int> &rows, int w, int d,
+                    uint64_t *word, uint64_t *row_mask) {
+    const int W = P.W;
+    if (j < 0 || j >= (int)P.gamma.size()) return fail(MINDIST_E_CERT, "witness names no set");
+    if ((int)rows.size() != w) return fail(MINDIST_E_CERT, "witness decodes to an invalid combination");
+    for (int t = 0; t < W; ++t) word[t] = 0;
+    for (int t = 0; t < MINDIST_MAX_WORDS; ++t) row_mask[t] = 0;
+    for (int r : rows) {
+        if (r < 0 || r >= P.k) return fail(MINDIST_E_CERT, "witness names a row beyond k");
+        for (int t = 0; t < W; ++t) word[t] ^= P.gamma[j][(size_t)r * W + t];
+        row_mask[r >> 6] |= 1ull << (r & 63);
+    }
+    int wt = 0;
+    for (int t = 0; t < W; ++t) wt += __builtin_popcountll(word[t]);
+    if (wt != d)
+        return fail(MINDIST_E_CERT, "witness weight " + std::to_string(wt) + " differs from d = " +
+                                        std::to_string(d));
+    // Gamma_0 is the identity on S_0: a codeword of the row space is the sum
+    // of the rows its values on S_0 select
+    std::vector<uint64_t> back(W, 0);
+    for (int r = 0; r < P.k; ++r)
+        if (bit_of(word, P.sets[0][r]))
+            for (int t = 0; t < W; ++t) back[t] ^= P.gamma[0][(size_t)r * W + t];
+    for (int t = 0; t < W; ++t)
+        if (back[t] != word[t]) return fail(MINDIST_E_CERT, "witness is not in the row space of G");
+    return MINDIST_OK;
+}
+
 // colex unranking of rho into an r-subset of [0, hi) (elements ascending)
 void colex_unrank(uint64_t rho, int r, int hi, int *out) {
     const Binom &B = BN();

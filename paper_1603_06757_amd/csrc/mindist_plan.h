@@ -60,6 +60,71 @@ void pack_row(const uint64_t *row, const std::vector<int> &cols, uint32_t *out, 
 int bound_f(int i, int h, int m_full, int k, int k_m);
 int bound_after(int k, int m_full, int k_m, int n_gamma, int j, int w);
 
+// Algorithm 1's pair order and bounds (Section 2).  Level g visits every
+// full set at level g, then the partial set (if k_m >= 1): at level g
+// (policy 0, the literal loop over j = 1..m), never (policy 1, its bound
+// term dropped too), or from the first level whose term
+// max(0, g+1-(k-k_m)) is positive (policy 2): that term bounds the weight on
+// the set's columns only once every level up to g is done under Gamma_m, so
+// the first such level g0 = k-k_m also enumerates the set's levels 1..g0-1
+// (ascending, after the full sets); later levels visit it at g only.
+enum { kPartialAlways = 0, kPartialNever = 1, kPartialWhenUseful = 2 };
+struct PairPos {
+    int j = 0;   // set (full sets 0..m_full-1, partial set m_full)
+    int h = 1;   // level the pair enumerates (= g except a catch-up pair)
+    int g = 1;   // level of Algorithm 1's outer loop
+};
+struct Schedule {
+    int k = 0, m_full = 0, k_m = 0, policy = kPartialAlways;
+    Schedule() = default;
+    Schedule(int k_, int m_full_, int k_m_, int policy_)
+        : k(k_), m_full(m_full_), k_m(k_m_), policy(policy_) {}
+    bool has_partial() const { return k_m >= 1 && policy != kPartialNever; }
+    int n_sets() const { return m_full + (has_partial() ? 1 : 0); }
+    PairPos first() const { return PairPos{}; }
+    // the pair after p; false once the levels are exhausted (g > k)
+    bool next(const PairPos &p, PairPos *q) const;
+    // p is the last pair of its level
+    bool level_end(const PairPos &p) const;
+    // p opens its level (Algorithm 1's test under the per-level rule)
+    bool level_start(const PairPos &p) const { return p.j == 0 && p.h == p.g; }
+    // L once p completes: sum over sets of f_i(the level set i has done)
+    int bound_after(const PairPos &p) const;
+    // L after p under the termination rule (per_level: raised only when p
+    // ends its level), given L before p
+    int L_after(const PairPos &p, bool per_level, int L_before) const {
+        return (!per_level || level_end(p)) ? bound_after(p) : L_before;
+    }
+};
+
+// The certificate of a run (Section 2, Algorithm 1's termination): the
+// visited pairs follow the schedule from L = 1, U = n-k+1; each pair covers
+// C(k, h) combinations and every completed one evaluated exactly that many;
+// L before, L after and U after each pair are the recomputed ones (U = the
+// least pair minimum so far, capped at n-k+1); only the last pair may be
+// cut short, and only when U <= L before it (mid-pair exit allowed); the
+// run stopped because L >= U, because the last pair was cut, or because the
+// levels ran out; d and L_final are the recomputed U and L.  Returns
+// MINDIST_OK or MINDIST_E_CERT with the reason as last error.
+struct CertSpec {
+    int n = 0, k = 0;
+    Schedule sched;
+    bool per_level = false;
+    bool midpair_exit = true;
+};
+struct PairView {   // the fields of a trace record the certificate reads
+    int j, w, L_before, L_after, U_after, pair_min;
+    uint64_t count, executed;
+};
+int certify_trace(const CertSpec &cs, const PairView *trace, int np, int d, int L_final,
+                  int exited_midpair);
+// The witness (Section 2): the XOR of the named rows of Gamma_j weighs d
+// and lies in the row space of G (it equals the combination of Gamma_0's
+// rows its own values on Gamma_0's information set select).  Writes the
+// codeword (P.W words) and the row mask; MINDIST_E_CERT otherwise.
+int certify_witness(const Plan &P, int j, const std::vector<int> &rows, int w, int d,
+                    uint64_t *word, uint64_t *row_mask);
+
 // colex unranking of rho into an r-subset of [0, hi) (elements ascending)
 void colex_unrank(uint64_t rho, int r, int hi, int *out);
 

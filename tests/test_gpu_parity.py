@@ -88,9 +88,13 @@ def oracle_tables(r):
     return counts, pmin, ws
 
 
+POLICY_NAMES = {0: "always", 1: "never", 2: "when_useful"}
+
+
 def run_and_compare(G, n, k, verify=True, **opts):
-    r = oracle.bz(G, n, k, threads=4,
-                  per_level=bool(opts.get("term", 0)), partial_never=bool(opts.get("partial", 0)))
+    partial = opts.get("partial", 0)
+    pname = partial if isinstance(partial, str) else POLICY_NAMES[int(partial)]
+    r = oracle.bz(G, n, k, threads=4, per_level=bool(opts.get("term", 0)), partial=pname)
     res = md.min_distance(G, n, k, verify=int(verify), **opts)
     assert res["d"] == r["d"]
     assert res["m_full"] == r["m_full"] and res["k_partial"] == r["k_m"]
@@ -277,7 +281,7 @@ def test_random_codes_vs_oracle():
             continue
         say("random", i, n, k)
         run_and_compare(G, n, k, verify=(i % 3 == 0), term=i % 2,
-                        midpair_exit=(i % 4 != 1), partial=(i % 5 == 4))
+                        midpair_exit=(i % 4 != 1), partial={4: 1, 2: 2}.get(i % 5, 0))
         done += 1
 
 
@@ -413,3 +417,95 @@ def test_injected_upper_bound_must_pass_the_certificate(name):
         assert [(p["j"], p["w"], p["pair_min"]) for p in r["pairs"]] == \
                [(p["j"], p["w"], p["pair_min"]) for p in ref["pairs"]]
         check_witness(G, w.n, w.k, r)
+
+
+def _partial_useful_codes(count):
+    """Seeded codes whose partial set reaches the first level its bound term
+    is positive (n a little under (m_full + 1) k), with the oracle's
+    when-useful run visiting it."""
+    rng = PCG32(8080, 11)
+    out = []
+    while len(out) < count:
+        k = rng.uniform_int(4, 24)
+        m = rng.uniform_int(1, 3)
+        n = m * k + rng.uniform_int(k // 2, k)
+        if n <= k or n > 200:
+            continue
+        G = draw_matrix(rng, n, k)
+        try:
+            full, part = oracle.partition(G, n, k)
+        except oracle.OracleError:
+            continue
+        r = oracle.bz(G, n, k, partial="when_useful")
+        if not any(j == len(full) for j in r["trace"][:, 0].tolist()):
+            continue
+        out.append((G, n, k))
+    return out
+
+
+def test_partial_set_when_useful_vs_oracle():
+    """MINDIST_OPT_PARTIAL = 2: the partial set from the first level its
+    bound term is positive, its lower levels caught up then.  Every visited
+    pair, bound, minimum and weight sum as the oracle's, under both
+    termination rules, on codes that reach that level."""
+    for i, (G, n, k) in enumerate(_partial_useful_codes(24)):
+        say("partial when useful", i, n, k)
+        res, r = run_and_compare(G, n, k, verify=True, partial=2, term=i % 2)
+        full, part, _ = md.plan(G, n, k)
+        hs = [p["w"] for p in res["pairs"] if p["j"] == len(full)]
+        assert hs and hs[0] == 1, hs
+        always, _ = run_and_compare(G, n, k, verify=False, partial=0, term=i % 2)
+        assert always["d"] == res["d"]
+
+
+TORCH_STREAM_SCRIPT = r"""
+import json, sys
+import torch                                  # first: the library then binds to torch's HIP runtime
+sys.path.insert(0, sys.argv[1])
+import paper_1603_06757_amd as md
+from paper_1603_06757_amd.gen import WORKLOADS
+w = WORKLOADS["rand150x75"]
+s = torch.cuda.Stream()
+with torch.cuda.stream(s):
+    x = torch.arange(1 << 20, device="cuda", dtype=torch.int64)
+    y = x * 3
+    with md.MinDist(w.matrix(), w.n, w.k, stream=torch.cuda.current_stream(), verify=1) as m:
+        res = m.run()
+        z = (y + 1).sum()
+s.synchronize()
+maps = open("/proc/self/maps").read()
+print(json.dumps({"z": int(z.item()), "d": res["d"], "pairs": res["pairs"],
+                  "witness": [int(v) for v in res["witness"]], "witness_pair": res["witness_pair"],
+                  "witness_rows": res["witness_rows"],
+                  "runtimes": sorted({l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l})}))
+"""
+
+
+def test_runs_on_a_torch_stream():
+    """MINDIST_OPT_STREAM with torch's current stream: the run's device work
+    goes on a stream torch created and owns, ordered with torch work queued
+    before and after it on that stream, and the result is the oracle's.
+    Torch brings its own HIP runtime, so this runs in a fresh process that
+    imports torch before the library (one runtime for both); this process
+    loaded the library without torch, and passing it a torch stream raises."""
+    import subprocess
+    w = WORKLOADS["rand150x75"]
+    gold = json.load(open(os.path.join(GOLDEN, "rand150x75.json")))
+    G = w.matrix()
+    say("rand150x75 on a torch stream (child process)")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, "-c", TORCH_STREAM_SCRIPT, root], capture_output=True,
+                       text=True, timeout=240)
+    assert p.returncode == 0, p.stderr[-3000:]
+    out = json.loads(p.stdout.strip().splitlines()[-1])
+    assert len(out["runtimes"]) == 1 and "torch" in out["runtimes"][0], out["runtimes"]
+    assert out["z"] == 3 * ((1 << 20) * ((1 << 20) - 1) // 2) + (1 << 20)
+    res = {"d": out["d"], "pairs": out["pairs"], "witness": np.array(out["witness"], dtype=np.uint64),
+           "witness_pair": tuple(out["witness_pair"]), "witness_rows": out["witness_rows"]}
+    assert res["d"] == gold["d"]
+    compare_with_trace(res, gold["trace"], gold["counts"], gold["pair_min"], gold["wsum"], w.k)
+    check_witness(G, w.n, w.k, res)
+    if not md._with_torch:
+        with md.MinDist(G, w.n, w.k) as m:
+            with pytest.raises(md.MindistError):
+                m.set_option("stream", type("S", (), {"cuda_stream": 1})())

@@ -144,3 +144,35 @@ def test_server_destroy_with_waiting_codes(engine):
     srv.close()
     say("destroy with", len(cs), "queued codes took", round(time.time() - t0, 3), "s, engine", engine)
     assert time.time() - t0 < 10.0
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+def test_served_results_equal_the_oracle(engine):
+    """Every served result against the CPU oracle, not only against the
+    single path: d, the whole visited-pair trace (sets, levels, bounds
+    before and after, U after, pair minima, C(k,w) counts) and a valid
+    witness, for light random codes and oracle-cheap requests of the
+    serving stream, arriving in waves while earlier ones run."""
+    import oracle
+    from paper_1603_06757_amd.gen import serving_request
+    from tests.test_gpu_parity import compare_with_trace, oracle_tables, estimated_work
+    cs = light_codes(40, seed=95)
+    cs += [c for c in (serving_request(i) for i in range(400))
+           if estimated_work(c[0], c[1]) <= 2e7][:24]
+    say("server vs oracle:", len(cs), "codes, engine", engine)
+    with md.Server(max_active=12, engine=engine) as srv:
+        for i, (n, k, G) in enumerate(cs):
+            srv.submit(G, n, k, tag=i)
+            if i % 16 == 15:
+                time.sleep(0.002)
+        got = collect(srv, len(cs), timeout=300)
+    for i, (n, k, G) in enumerate(cs):
+        r = got[i]
+        assert r["status"] == 0, (i, r["status"])
+        ref = oracle.bz(G, n, k, threads=4)
+        assert r["d"] == ref["d"], (i, n, k)
+        assert (r["m_full"], r["k_partial"]) == (ref["m_full"], ref["k_m"])
+        counts, pmin, _ = oracle_tables(ref)
+        compare_with_trace(r, ref["trace"].tolist(), counts, pmin, None, k)
+        assert all(p["executed"] == p["count"] for p in r["pairs"][:-1])
+        check_witness(G, n, k, r)

@@ -182,3 +182,137 @@ def test_option_and_error_codes_match_the_header():
             for m in re.finditer(r"#define MINDIST_E_(\w+)\s+(-\d+)", text)}
     assert opts == md.OPT
     assert {k: v for k, v in md.E_NAMES.items() if k < 0} == errs
+
+
+# ---- Algorithm 1's pair order and the run certificate (host-only) ----------
+
+def _policy_cases():
+    """Seeded random codes whose partial sets reach their first useful level
+    (n a little under (m_full + 1) k), plus the workloads' shapes."""
+    from paper_1603_06757_amd.gen import PCG32, draw_matrix
+    rng = PCG32(4321, 3)
+    out = []
+    while len(out) < 60:
+        k = rng.uniform_int(3, 14)
+        m = rng.uniform_int(1, 3)
+        n = min(m * k + rng.uniform_int(1, k), 80)
+        if n <= k:
+            continue
+        G = draw_matrix(rng, n, k)
+        try:
+            oracle.partition(G, n, k)
+        except oracle.OracleError:
+            continue
+        out.append((G, n, k))
+    return out
+
+
+POLICY_VARIANTS = [("always", False), ("always", True), ("never", False), ("never", True),
+                   ("when_useful", False), ("when_useful", True)]
+
+
+def test_schedule_matches_the_oracles_visiting_order():
+    """The library's pair order and bounds (mindist_schedule) against the
+    oracle's visited pairs under every partial-set policy and termination
+    rule: the oracle's trace is a prefix of the schedule, with the same L
+    after every pair."""
+    reached = 0
+    for G, n, k in _policy_cases():
+        full, part = oracle.partition(G, n, k)
+        for partial, per_level in POLICY_VARIANTS:
+            r = oracle.bz(G, n, k, partial=partial, per_level=per_level)
+            sched = md.schedule(k, len(full), len(part), partial, per_level)
+            tr = r["trace"].tolist()
+            assert len(tr) <= len(sched)
+            for (j, h, Lb, La, U, pm), (sj, sh, sg, sL) in zip(tr, sched):
+                assert (j, h, La) == (sj, sh, sL), (n, k, partial, per_level)
+            if partial == "when_useful" and any(j == len(full) for j, *_ in tr):
+                reached += 1
+    assert reached >= 5
+
+
+def _records(r, k):
+    """The oracle's trace as the library's pair records (every pair complete)."""
+    return [{"j": j, "w": h, "L_before": Lb, "L_after": La, "U_after": U, "pair_min": pm,
+             "count": math.comb(k, h), "executed": math.comb(k, h)}
+            for j, h, Lb, La, U, pm in r["trace"].tolist()]
+
+
+def _certify(r, n, k, recs, d=None, L_final=None, exited=0, **kw):
+    return md.certify(n, k, r["m_full"], r["k_m"], recs, r["d"] if d is None else d,
+                      r["L_final"] if L_final is None else L_final, exited, **kw)
+
+
+def test_certificate_accepts_the_oracles_runs():
+    for G, n, k in _policy_cases()[:30]:
+        for partial, per_level in POLICY_VARIANTS:
+            r = oracle.bz(G, n, k, partial=partial, per_level=per_level)
+            assert _certify(r, n, k, _records(r, k), partial=partial, per_level=per_level) == 0
+
+
+def _expect_cert(fn):
+    with pytest.raises(md.MindistError) as e:
+        fn()
+    assert e.value.code == -9, e.value
+
+
+def test_certificate_rejects_broken_traces():
+    """Synthetic pair records: each plausible fault of a device sequencer or
+    a host loop ends in MINDIST_E_CERT."""
+    w = WORKLOADS["rand48x24"]
+    G, n, k = w.matrix(), w.n, w.k
+    r = oracle.bz(G, n, k)
+    base = _records(r, k)
+    assert len(base) >= 3
+    assert _certify(r, n, k, base) == 0
+
+    def mutated(t, **kv):
+        recs = [dict(p) for p in base]
+        recs[t].update(kv)
+        return recs
+    # a completed pair that evaluated fewer or more combinations than C(k,w)
+    _expect_cert(lambda: _certify(r, n, k, mutated(0, executed=base[0]["count"] - 1)))
+    _expect_cert(lambda: _certify(r, n, k, mutated(1, executed=base[1]["count"] + 1)))
+    # a wrong count, a wrong bound, a wrong U
+    _expect_cert(lambda: _certify(r, n, k, mutated(1, count=base[1]["count"] + 1)))
+    _expect_cert(lambda: _certify(r, n, k, mutated(1, L_after=base[1]["L_after"] + 1)))
+    _expect_cert(lambda: _certify(r, n, k, mutated(2, L_before=base[2]["L_before"] - 1)))
+    _expect_cert(lambda: _certify(r, n, k, mutated(0, U_after=base[0]["U_after"] - 1)))
+    # pairs out of order, a pair dropped, the run stopped early
+    sw = [dict(p) for p in base]
+    sw[0]["j"], sw[1]["j"] = sw[1]["j"], sw[0]["j"]
+    _expect_cert(lambda: _certify(r, n, k, sw))
+    _expect_cert(lambda: _certify(r, n, k, base[:1] + base[2:]))
+    short = base[:-1]
+    _expect_cert(lambda: _certify(r, n, k, short, L_final=short[-1]["L_after"]))
+    # a pair visited after L >= U
+    extra = dict(base[-1])
+    _expect_cert(lambda: _certify(r, n, k, base + [extra]))
+    # d or the final bound misreported
+    _expect_cert(lambda: _certify(r, n, k, base, d=r["d"] - 1))
+    _expect_cert(lambda: _certify(r, n, k, base, L_final=r["L_final"] + 1))
+    # a cut last pair: justified only when U <= L before it, and only last
+    last = dict(base[-1], executed=base[-1]["count"] // 2, L_after=base[-1]["L_before"])
+    cut = base[:-1] + [last]
+    U_before_last = cut[-1]["U_after"]
+    if U_before_last <= last["L_before"]:
+        assert _certify(r, n, k, cut, L_final=last["L_before"], exited=1) == 0
+        _expect_cert(lambda: _certify(r, n, k, cut, L_final=last["L_before"], exited=0))
+        _expect_cert(lambda: _certify(r, n, k, cut, L_final=last["L_before"], exited=1,
+                                      midpair_exit=False))
+    mid = mutated(0, executed=base[0]["count"] // 2)
+    _expect_cert(lambda: _certify(r, n, k, mid, exited=1))
+
+
+def test_certificate_rejects_an_unjustified_cut():
+    """A pair cut short while the least weight found is above the bound
+    before it (what a least weight the device never found would cause)."""
+    w = WORKLOADS["rand48x24"]
+    G, n, k = w.matrix(), w.n, w.k
+    r = oracle.bz(G, n, k)
+    base = _records(r, k)
+    t = 1
+    assert base[t]["U_after"] > base[t]["L_before"]
+    recs = base[:t] + [dict(base[t], executed=5, L_after=base[t]["L_before"])]
+    _expect_cert(lambda: _certify(r, n, k, recs, d=recs[-1]["U_after"],
+                                  L_final=base[t]["L_before"], exited=1))

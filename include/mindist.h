@@ -199,6 +199,33 @@ void mindist_destroy(mindist_ctx *ctx);
 
 const char *mindist_last_error(void);
 
+/* For callers that cannot allocate device or pinned memory (work between
+ * HIP graph captures, tight serving loops, harnesses that forbid hipMalloc):
+ * mindist_create + mindist_run + mindist_destroy of one code in a single
+ * call that allocates no device or pinned memory.  Its device state (run
+ * state, mailboxes, per-wave totals, chunk groups, Gamma_j rows and the
+ * saved-sum tables of the pair being enumerated) lives in one static device
+ * buffer of MINDIST_NOALLOC_BYTES per GPU, reserved the first time the call
+ * runs on that GPU and held until the process ends.  Default options
+ * (per-pair termination, mid-pair exit, partial set at every level); pairs
+ * run one at a time (none launched ahead), lanes unrank their left subsets,
+ * and a set's table level is capped so one table's levels fit a quarter of
+ * the buffer's table arena (about 23 MiB): d, the visited pairs, their
+ * bounds, minima and counts equal mindist_run's, timings differ.
+ * G, n, k as in mindist_create; stream: hipStream_t cast to int64, 0 = the
+ * null stream; out: caller-owned result; pairs: optional caller-owned array
+ * of pairs_cap records receiving the visited pairs (*n_pairs = how many were
+ * visited, even beyond pairs_cap; n_pairs may be NULL).  Blocking: the
+ * stream is idle on return.  Calls on one GPU share its buffer and run one
+ * at a time (a lock per GPU; each call clears what it needs); a call that
+ * overlapped another on the same GPU without that lock would race.
+ * Errors: as mindist_create / mindist_run, MINDIST_E_LIMIT if a code needs
+ * more of the buffer than it holds (not reached for n <= 512 on a GPU with
+ * at most 256 compute units). */
+#define MINDIST_NOALLOC_BYTES (96u << 20)
+int mindist_run_noalloc(const uint64_t *G, int n, int k, int64_t stream, mindist_result *out,
+                        mindist_pair *pairs, int pairs_cap, int *n_pairs);
+
 /* Calibration microbenchmark: the enumeration kernel's inner loop (one
  * 32-bit XOR + popcount per carried word and a min per codeword, right sums
  * from scalar loads) over registers and a 64-entry table, on every CU, with

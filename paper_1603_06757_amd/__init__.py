@@ -147,6 +147,8 @@ def lib():
         L.mindist_plan.argtypes = [u64p, C.c_int, C.c_int, ip, ip, ip, u64p]
         L.mindist_bound_after.argtypes = [C.c_int] * 6
         L.mindist_colex_unrank.argtypes = [C.c_uint64, C.c_int, C.c_int, ip]
+        L.mindist_run_noalloc.argtypes = [u64p, C.c_int, C.c_int, C.c_int64, C.POINTER(Result),
+                                          C.POINTER(Pair), C.c_int, ip]
         L.mindist_schedule.argtypes = [C.c_int] * 5 + [C.POINTER(C.c_int32), C.c_int, ip]
         L.mindist_certify.argtypes = [C.POINTER(CertSpec), C.POINTER(Pair), C.c_int, C.c_int,
                                       C.c_int, C.c_int]
@@ -447,6 +449,20 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def run_noalloc(G, n: int, k: int, stream: int = 0, pairs_cap: int = 4096) -> dict:
+    """mindist_run_noalloc: one code through the single path with no device
+    or pinned allocation (a fixed static device buffer per GPU)."""
+    m = _mat(G, n, k)
+    r = Result()
+    arr = (Pair * pairs_cap)()
+    cnt = C.c_int(0)
+    _check(lib().mindist_run_noalloc(_u64(m), n, k, int(stream), C.byref(r), arr, pairs_cap,
+                                     C.byref(cnt)))
+    out = r.to_dict()
+    out["pairs"] = [arr[i].to_dict() for i in range(min(cnt.value, pairs_cap))]
+    return out
 
 
 def min_distance(G, n: int, k: int, **options) -> dict:

@@ -19,7 +19,7 @@ CPU_LIB = os.path.join(HERE, "libmindist_cpu.so")
 CPU_FLAGS = ["-O3", "-fPIC", "-shared", "-fopenmp", "-mpopcnt", "-std=c11"]
 
 SOURCES = ["mindist_kernels.hip", "mindist_batch.hip", "mindist_walk.hip", "mindist_plan.cpp", "mindist_host.cpp",
-           "mindist_pool.cpp", "mindist_batch.cpp", "mindist_server.cpp"]
+           "mindist_pool.cpp", "mindist_batch.cpp", "mindist_server.cpp", "mindist_noalloc.hip"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

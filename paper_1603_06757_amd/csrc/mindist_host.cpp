@@ -12,6 +12,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -108,10 +109,19 @@ struct mindist_ctx {
     // last run
     std::vector<mindist_pair> trace;
     bool have_run = false;
+    // no-allocation mode (mindist_run_noalloc): every device buffer lies in
+    // a fixed region the caller provides; the mailboxes are device memory
+    // read back by copies; each pair's tables are rebuilt in one arena
+    int noalloc = 0;
+    unsigned char *arena = nullptr;
+    uint64_t arena_bytes = 0, arena_used = 0;
+    GroupEntry *d_groups_fixed = nullptr;   // the current pair's chunk groups
+    std::vector<PairMail> mail_host;        // h_mail's storage in this mode
 };
 
 static void free_ctx(mindist_ctx *c) {
     if (!c) return;
+    if (c->noalloc) { delete c; return; }   // nothing of its own on the device
     // a launched-ahead pair may still read this context's buffers
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto &g : c->gd) {
@@ -183,17 +193,34 @@ static int get_table(mindist_ctx *c, int j, int r, int kind, int shift, uint32_t
         if (e) return e;
     }
     const uint64_t ent = BN()(c->P.k - shift, r);
-    uint32_t *t = static_cast<uint32_t *>(dev_alloc(ent * g.DP * 4));
-    uint32_t *cn = shift ? static_cast<uint32_t *>(dev_alloc(ent * 4)) : nullptr;
-    if (!t || (shift && !cn)) {
-        dev_free(t);
-        dev_free(cn);
-        return fail(MINDIST_E_NOMEM, "saved-sum table allocation failed");
+    uint32_t *t = nullptr, *cn = nullptr;
+    if (c->noalloc) {
+        // the arena of the fixed region (reset before every pair)
+        auto take = [&](uint64_t bytes) -> uint32_t * {
+            const uint64_t at = (c->arena_used + 255) & ~255ull;
+            if (at + bytes > c->arena_bytes) return nullptr;
+            c->arena_used = at + bytes;
+            return reinterpret_cast<uint32_t *>(c->arena + at);
+        };
+        t = take(ent * g.DP * 4);
+        cn = shift ? take(ent * 4) : nullptr;
+        if (!t || (shift && !cn))
+            return fail(MINDIST_E_LIMIT, "saved-sum tables exceed the fixed region");
+    } else {
+        t = static_cast<uint32_t *>(dev_alloc(ent * g.DP * 4));
+        cn = shift ? static_cast<uint32_t *>(dev_alloc(ent * 4)) : nullptr;
+        if (!t || (shift && !cn)) {
+            dev_free(t);
+            dev_free(cn);
+            return fail(MINDIST_E_NOMEM, "saved-sum table allocation failed");
+        }
     }
     TableArgs ta{g.rows, c->d_binom, t, cn, ent, c->P.k, r, g.DP, kind ? 1 : 0, shift, prev};
     if (launch_build_table(ta, g.D, c->stream)) {
-        dev_free(t);
-        dev_free(cn);
+        if (!c->noalloc) {
+            dev_free(t);
+            dev_free(cn);
+        }
         return fail(MINDIST_E_HIP, "table kernel launch failed");
     }
     g.tabs[key] = {t, cn};
@@ -521,6 +548,9 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
     c->have_run = false;
     if (launch_init_state(c->d_state, c->max_pairs, c->stream))
         return fail(MINDIST_E_HIP, "init kernel launch failed");
+    if (c->noalloc && launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_mail), 0u,
+                                      kMailRing * sizeof(PairMail) / 4, c->stream))
+        return fail(MINDIST_E_HIP, "mailbox clear failed");
     if (c->inject_u) {
         // testing: the device starts from a least weight it never found
         uint32_t *h = static_cast<uint32_t *>(pinned_alloc(sizeof(uint32_t)));
@@ -555,6 +585,8 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
     // per-wave totals: one entry per wave of the widest launch
     {
         const uint64_t max_waves = (uint64_t)c->cus * c->blocks_per_cu * 4;
+        if (max_waves > c->parts_cap && c->noalloc)
+            return fail(MINDIST_E_LIMIT, "more resident waves than the fixed region holds");
         if (max_waves > c->parts_cap) {
             dev_free(c->d_parts);
             c->d_parts = static_cast<WavePart *>(dev_alloc(sizeof(WavePart) * max_waves));
@@ -574,6 +606,17 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         const std::array<uint64_t, 6> key{(uint64_t)j << 32 | (uint32_t)w, (uint64_t)c->items,
                                           (uint64_t)c->tile_t, (uint64_t)c->blocks_per_cu,
                                           c->min_items, (uint64_t)c->order};
+        if (c->noalloc) {
+            // one pair in flight: its groups go to the fixed slot (the
+            // previous pair has finished; a pageable copy has consumed
+            // plan_tmp when it returns)
+            q.pp = plan_pair(c, j, w, plan_tmp.data(), nullptr);
+            if (hipMemcpyAsync(c->d_groups_fixed, plan_tmp.data(), sizeof(GroupEntry) * q.pp.ngroups,
+                               hipMemcpyHostToDevice, c->stream) != hipSuccess)
+                return fail(MINDIST_E_HIP, "chunk group upload failed");
+            q.groups = c->d_groups_fixed;
+            return MINDIST_OK;
+        }
         if (!c->order) {
             auto it = c->plan_cache.find(key);
             if (it != c->plan_cache.end()) {
@@ -593,6 +636,11 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
     };
     // tables of a planned pair (built in stream order on first use)
     auto stage = [&](Prep &q) -> int {
+        if (c->noalloc) {
+            // tables of one pair at a time, rebuilt in the arena
+            for (auto &g : c->gd) g.tabs.clear();
+            c->arena_used = 0;
+        }
         int e = get_table(c, q.j, q.pp.b, 1, q.pp.b2, &q.table, &q.cnt2);
         if (e) return e;
         if (q.pp.b2) {
@@ -627,6 +675,15 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
     };
     // wait for the mailbox of pair `pr` (the publish kernel behind it fills it)
     auto wait_mail = [&](int pr) -> int {
+        if (c->noalloc) {
+            PairMail *h = &c->h_mail[pr % kMailRing];
+            HIPCHK(hipMemcpyAsync(h, &c->d_mail[pr % kMailRing], sizeof(PairMail), hipMemcpyDeviceToHost,
+                                  c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            if (h->seq != (uint32_t)pr + 1)
+                return fail(MINDIST_E_HIP, "enumeration kernel ended without publishing its pair");
+            return MINDIST_OK;
+        }
         const uint32_t *seq = &c->h_mail[pr % kMailRing].seq;
         std::chrono::steady_clock::time_point idle_since{};
         bool idle = false;
@@ -707,7 +764,7 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
             pa.parts = c->d_parts + (size_t)bs * 4;
             ga.block_start[t] = bs;
             bs += (uint32_t)grp[t].blocks;
-            __atomic_store_n(&c->h_mail[grp[t].idx % kMailRing].seq, 0u, __ATOMIC_RELEASE);
+            if (!c->noalloc) __atomic_store_n(&c->h_mail[grp[t].idx % kMailRing].seq, 0u, __ATOMIC_RELEASE);
             launched_pairs.push_back(grp[t]);
             leader.push_back(grp[0].idx);
         }
@@ -929,13 +986,14 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         if (last_mail.U_found != U_found) {
             // a pair launched but not visited found a lower weight (possible
             // only when the Singleton bound ends the run): read slot[U_found]
-            Slot *h = static_cast<Slot *>(pinned_alloc(sizeof(Slot)));
+            Slot host_slot{};
+            Slot *h = c->noalloc ? &host_slot : static_cast<Slot *>(pinned_alloc(sizeof(Slot)));
             if (!h) return fail(MINDIST_E_NOMEM, "witness readback allocation failed");
             const bool ok = hipMemcpyAsync(h, state_slots(c->d_state) + U_found, sizeof(Slot),
                                            hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
                             hipStreamSynchronize(c->stream) == hipSuccess;
             s = *h;
-            pinned_free(h);
+            if (!c->noalloc) pinned_free(h);
             if (!ok) return fail(MINDIST_E_HIP, "witness readback failed");
         }
         if (s.pair >= (uint32_t)launched_pairs.size())
@@ -960,6 +1018,109 @@ extern "C" int mindist_run(mindist_ctx *c, mindist_result *out) {
     if (e != MINDIST_OK && c && c->stream) (void)hipStreamSynchronize(c->stream);
     return e;
 }
+
+namespace md {
+
+// Fixed-region layout of mindist_run_noalloc (offsets 256-byte aligned):
+// binomial table, run state, mailboxes, per-wave totals, the current pair's
+// chunk groups, the rows of every Gamma_j, then the table arena.
+// pairs of one run: n_gamma * min(k, 64) + 1 with n_gamma <= n/k + 1, at most
+// n + k + 1 <= 577 for k <= 64 and 8 * 64 + 1 for k > 64
+constexpr int kNoallocMaxPairs = 640;
+constexpr uint64_t kNoallocMaxWaves = 256 * 4 * 4;
+constexpr uint64_t kNoallocRowBytes = 256 * 1024;
+
+static uint64_t a256(uint64_t x) { return (x + 255) & ~255ull; }
+
+int noalloc_run(unsigned char *base, uint64_t bytes, bool *binom_ready, const uint64_t *G, int n, int k,
+                hipStream_t stream, mindist_result *out, mindist_pair *pairs, int cap, int *n_pairs) {
+    if (!out || (cap > 0 && !pairs) || cap < 0) return fail(MINDIST_E_ARG, "NULL argument");
+    if (n_pairs) *n_pairs = 0;
+    mindist_ctx *c = new (std::nothrow) mindist_ctx();   // host memory only
+    if (!c) return fail(MINDIST_E_NOMEM, "context allocation failed");
+    std::unique_ptr<mindist_ctx, void (*)(mindist_ctx *)> hold(c, free_ctx);
+    int e = make_plan(G, n, k, c->P);
+    if (e) return e;
+    const Plan &P = c->P;
+    c->noalloc = 1;
+    c->stream = stream;
+    c->own_stream = false;
+    c->speculate = 0;        // one pair in flight: its tables and groups own the region
+    c->left_tables = 0;      // lanes unrank their left subsets
+    c->n_gamma = (int)P.sets.size();
+    c->max_pairs = c->n_gamma * std::min(k, MINDIST_MAX_LEVEL) + 1;
+    if (c->max_pairs > kNoallocMaxPairs) return fail(MINDIST_E_LIMIT, "too many pairs for the fixed region");
+    HIPCHK(hipGetDevice(&c->device));
+    HIPCHK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && khz > 0)
+            c->wall_hz = khz * 1000.0;
+    }
+    // carve the region
+    uint64_t off = 0;
+    auto take = [&](uint64_t sz) { unsigned char *p = base + off; off = a256(off + sz); return p; };
+    const size_t binom_bytes = BN().t.size() * sizeof(uint64_t);
+    c->d_binom = reinterpret_cast<const uint64_t *>(take(binom_bytes));
+    c->d_state = reinterpret_cast<DevState *>(take(state_bytes(kNoallocMaxPairs)));
+    c->d_mail = reinterpret_cast<PairMail *>(take(kMailRing * sizeof(PairMail)));
+    c->d_parts = reinterpret_cast<WavePart *>(take(kNoallocMaxWaves * sizeof(WavePart)));
+    c->parts_cap = kNoallocMaxWaves;
+    c->groups_cap = k + 2;
+    c->d_groups_fixed = reinterpret_cast<GroupEntry *>(take((uint64_t)(kBinomX + 2) * sizeof(GroupEntry)));
+    unsigned char *rows = take(kNoallocRowBytes);
+    c->arena = base + off;
+    if (off >= bytes) return fail(MINDIST_E_LIMIT, "fixed region too small");
+    c->arena_bytes = bytes - off;
+    c->mail_host.assign(kMailRing, PairMail{});
+    c->h_mail = c->mail_host.data();
+    if (!*binom_ready) {
+        // constant for every call on the device: uploaded once
+        HIPCHK(hipMemcpyAsync(const_cast<uint64_t *>(c->d_binom), BN().t.data(), binom_bytes,
+                              hipMemcpyHostToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        *binom_ready = true;
+    }
+    // Gamma rows (packed carried columns) and each set's table level cap: the
+    // levels 1..b of one table within a quarter of the arena, so a pair's
+    // tables (two-level: levels 1..b; three-level: the outer table with its
+    // counts and the inner levels 1..b2) always fit
+    const Binom &B = BN();
+    c->gd.resize(c->n_gamma);
+    std::vector<uint32_t> hrows;
+    uint64_t roff = 0;
+    for (int j = 0; j < c->n_gamma; ++j) {
+        GammaDev &g = c->gd[j];
+        const std::vector<int> cols = carried_columns(P, j);
+        g.stripped = j < P.m_full;
+        g.D = (int)((cols.size() + 31) / 32);
+        g.DP = dp_of_host(g.D);
+        const uint64_t words = (uint64_t)k * g.DP;
+        if (a256(roff + words * 4) > kNoallocRowBytes)
+            return fail(MINDIST_E_LIMIT, "Gamma rows exceed the fixed region");
+        g.rows = reinterpret_cast<uint32_t *>(rows + roff);
+        roff = a256(roff + words * 4);
+        hrows.assign(words, 0);
+        for (int r = 0; r < k; ++r) pack_row(&P.gamma[j][(size_t)r * P.W], cols, &hrows[(size_t)r * g.DP], g.DP);
+        HIPCHK(hipMemcpyAsync(g.rows, hrows.data(), words * 4, hipMemcpyHostToDevice, stream));
+        g.bcap = 0;
+        uint64_t levels = 0;
+        for (int b = 1; b <= 16 && b <= k; ++b) {
+            const uint64_t ent = B(k, b);
+            levels += ent * g.DP * 4 + 256;
+            if (ent >= (1ull << 31) || levels > c->arena_bytes / 4) break;
+            g.bcap = b;
+        }
+    }
+    c->table_cap = c->arena_bytes / 4;
+    e = run_impl(c, out);
+    if (e != MINDIST_OK) (void)hipStreamSynchronize(stream);
+    if (n_pairs) *n_pairs = (int)c->trace.size();
+    for (int t = 0; t < cap && t < (int)c->trace.size(); ++t) pairs[t] = c->trace[t];
+    return e;
+}
+
+}  // namespace md
 
 extern "C" int mindist_get_pairs(const mindist_ctx *c, mindist_pair *out, int cap, int *n_out) {
     if (!c || (!out && cap > 0) || !n_out) return fail(MINDIST_E_ARG, "NULL argument");

@@ -202,6 +202,8 @@ int launch_enum_pair(const GroupArgs &ga, int D, int items, int verify, void *st
 // right behind the enumeration kernel)
 int launch_publish_pair(const GroupArgs &ga, PairMail *mail, void *stream);
 int max_dwords();
+// p[0..count) = v (a fill kernel: no memset node, usable in captured work)
+int launch_fill_u32(uint32_t *p, uint32_t v, uint64_t count, void *stream);
 int launch_peak(const uint32_t *tab, uint32_t steps, uint32_t *out, int D, int blocks, void *stream);
 
 // Split of the w rows of a pair between the levels, chosen identically by

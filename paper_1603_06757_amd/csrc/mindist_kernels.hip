@@ -5,6 +5,7 @@
 // Algorithm 1), with the left/right split described in mindist_internal.h.
 // Rows and tables are a few KB to a few MB; nothing per codeword touches HBM.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 
 #include "mindist_device.h"
 
@@ -367,8 +368,22 @@ __global__ void init_state_kernel(DevState *st, int max_pairs) {
     for (int q = tid; q < max_pairs; q += gridDim.x * blockDim.x) pref[q] = kInf;
 }
 
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 // ---------------------------------------------------------------------------
 int max_dwords() { return 16; }
+
+int launch_fill_u32(uint32_t *p, uint32_t v, uint64_t count, void *stream) {
+    if (!count) return 0;
+    const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 1024);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, p, v,
+                       count);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
 
 static int check(hipError_t e) { return e == hipSuccess ? 0 : -1; }
 

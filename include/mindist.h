@@ -235,6 +235,20 @@ int mindist_run_noalloc(const uint64_t *G, int n, int k, int64_t stream, mindist
  * faster (its right runs are longer than the table walked here). */
 int mindist_calibrate(int dwords, int blocks_per_cu, double *codewords_per_s, double *seconds);
 
+/* The measured ceiling of the enumeration's arithmetic on this GPU: a
+ * register-only kernel on every compute unit (blocks_per_cu blocks of 256
+ * lanes, 1..16) whose loop is nothing but 32-bit XOR + popcount pairs
+ * (v_xor_b32 with a wave-uniform operand that changes every step,
+ * v_bcnt_u32_b32 accumulating) over words held in registers, in independent
+ * chains per lane; no memory operation in the loop.  variant 0..3 sets
+ * (chains per lane, words per chain, steps per loop iteration) = (8, 4, 1),
+ * (8, 4, 4), (4, 6, 4), (16, 2, 4).  Writes the best of three timed launches
+ * (after one warm-up) as 32-bit XOR+popcount operations per second (one per
+ * lane per word) and its duration; seconds may be NULL.  Blocking.  The
+ * best over variants and occupancies is the denominator of the kernels'
+ * VALU roofline where it exceeds the figure derived from the rated clock. */
+int mindist_peak_xorpop(int variant, int blocks_per_cu, double *ops_per_s, double *seconds);
+
 /* Comparison kernel for one pair (Gamma_j, w) of a created context (Section
  * 3.3, the stack-based enumeration of Algorithm 4, as a GPU walk): every
  * lane unranks its own start in lexicographic order (combinatorial number

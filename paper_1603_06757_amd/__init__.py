@@ -155,6 +155,7 @@ def lib():
         L.mindist_calibrate.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
         L.mindist_device.argtypes = [C.c_char_p, C.c_int, ip]
+        L.mindist_peak_xorpop.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.mindist_walk_pair.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int32),
                                         u64p, C.POINTER(C.c_double)]
         if hasattr(L, "mindist_run_batch"):
@@ -210,6 +211,16 @@ def calibrate(dwords: int = 3, blocks_per_cu: int = 4):
     """Measured ceiling of the enumeration's inner loop: (codewords/s, seconds)."""
     r, t = C.c_double(), C.c_double()
     _check(lib().mindist_calibrate(dwords, blocks_per_cu, C.byref(r), C.byref(t)))
+    return r.value, t.value
+
+
+PEAK_VARIANTS = 4
+
+
+def peak_xorpop(variant: int = 1, blocks_per_cu: int = 8):
+    """Measured register-only ceiling: (32-bit XOR+popcount ops/s, seconds)."""
+    r, t = C.c_double(), C.c_double()
+    _check(lib().mindist_peak_xorpop(variant, blocks_per_cu, C.byref(r), C.byref(t)))
     return r.value, t.value
 
 

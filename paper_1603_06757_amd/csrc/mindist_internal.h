@@ -205,6 +205,13 @@ int max_dwords();
 // p[0..count) = v (a fill kernel: no memset node, usable in captured work)
 int launch_fill_u32(uint32_t *p, uint32_t v, uint64_t count, void *stream);
 int launch_peak(const uint32_t *tab, uint32_t steps, uint32_t *out, int D, int blocks, void *stream);
+// register-only XOR + popcount ceiling, variant v < kPeakVariants: blocks x
+// 256 lanes, each doing steps x items x words 32-bit XOR+popcount
+// operations (peak_reg_shape); steps a multiple of 4; out holds one word per
+// lane
+constexpr int kPeakVariants = 4;
+int peak_reg_shape(int v, int *items, int *words);
+int launch_peak_reg(int v, uint32_t steps, uint32_t seed, uint32_t *out, int blocks, void *stream);
 
 // Split of the w rows of a pair between the levels, chosen identically by
 // the host planner and the persistent batch scheduler.  The balanced

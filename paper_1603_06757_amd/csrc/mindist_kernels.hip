@@ -300,6 +300,61 @@ int launch_peak(const uint32_t *tab, uint32_t steps, uint32_t *out, int D, int b
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Register-only ceiling of the enumeration's arithmetic: every lane holds
+// B x D 32-bit words; per step the wave XORs them with D wave-uniform words
+// (scalar registers, new every step) and accumulates their popcounts, one
+// v_xor_b32 + one v_bcnt_u32_b32 per word, into B independent chains; U
+// steps per loop iteration.  No memory operation inside the loop.
+// ops = grid threads x steps x B x D.
+template <int B, int D, int U>
+__global__ __launch_bounds__(256) void peak_reg_kernel(uint32_t steps, uint32_t seed, uint32_t *out) {
+    uint32_t L[B][D], acc[B];
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) L[t][d] = (gid + 1) * 0x9E3779B9u ^ (uint32_t)(t * D + d) * 0x85EBCA6Bu;
+        acc[t] = 0;
+    }
+    for (uint32_t i = 0; i < steps; i += U) {
+        const uint32_t s = uni32(seed ^ (i * 0x27D4EB2Fu));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const uint32_t sd = s + (uint32_t)(u * D + d) * 0x165667B1u;
+#pragma unroll
+                for (int t = 0; t < B; ++t) acc[t] = bcnt_acc(L[t][d] ^ sd, acc[t]);
+            }
+        }
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int t = 0; t < B; ++t) r += acc[t];
+    out[gid] = r;              // every lane stores its sum: the chains stay live
+}
+
+// variant v: (lane items, words, steps per iteration)
+int peak_reg_shape(int v, int *items, int *words) {
+    static const int shape[kPeakVariants][2] = {{8, 4}, {8, 4}, {4, 6}, {16, 2}};
+    if (v < 0 || v >= kPeakVariants) return -1;
+    *items = shape[v][0];
+    *words = shape[v][1];
+    return 0;
+}
+
+int launch_peak_reg(int v, uint32_t steps, uint32_t seed, uint32_t *out, int blocks, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    switch (v) {
+        case 0: hipLaunchKernelGGL((peak_reg_kernel<8, 4, 1>), dim3(blocks), dim3(256), 0, s, steps, seed, out); break;
+        case 1: hipLaunchKernelGGL((peak_reg_kernel<8, 4, 4>), dim3(blocks), dim3(256), 0, s, steps, seed, out); break;
+        case 2: hipLaunchKernelGGL((peak_reg_kernel<4, 6, 4>), dim3(blocks), dim3(256), 0, s, steps, seed, out); break;
+        case 3: hipLaunchKernelGGL((peak_reg_kernel<16, 2, 4>), dim3(blocks), dim3(256), 0, s, steps, seed, out); break;
+        default: return -2;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // Saved sums (see TableArgs): entry i = rows of colex_unrank_b(i) (left) or
 // rows {k-1-shift-z} (right / outer); outer tables also record the number of
 // inner entries C(shift + min z, shift) above each entry.

@@ -20,14 +20,22 @@ def test_roofline_groups_launches_and_prices_against_the_peak():
     # two runs; launch 0 holds two short pairs (their span is the longer
     # one), launch 1 one long pair; all D = 3
     run = {"pairs": [_pair(0, 3, 1000, 0.010), _pair(0, 3, 3000, 0.020), _pair(1, 3, 6_000_000_000, 1.0)]}
-    D, roof = bench.roofline([run, run], [run])
+    nominal = 256 * 64 * 2.4e9 / 2
+    D, roof = bench.roofline([run, run], [run], nominal)
     assert D == 3
     sec = 2 * (0.020 + 1.0) * 1e-3
     cw = 2 * (1000 + 3000 + 6_000_000_000)
     assert roof["launches"] == 4
     assert roof["achieved"] == pytest.approx(cw * 3 / sec / 1e12)
-    assert roof["peak"] == pytest.approx(256 * 64 * 2.4e9 / 2 / 1e12)
-    assert roof["frac"] == pytest.approx(cw * 3 / sec / (256 * 64 * 2.4e9 / 2))
+    assert roof["peak"] == pytest.approx(nominal / 1e12)
+    assert roof["frac"] == pytest.approx(cw * 3 / sec / nominal)
+    # a measured ceiling above the derived figure becomes the denominator;
+    # the nominal share stays beside it
+    _, roof2 = bench.roofline([run, run], [run], 1.1 * nominal)
+    assert roof2["peak"] == pytest.approx(1.1 * nominal / 1e12)
+    assert roof2["frac"] == pytest.approx(roof["frac"] / 1.1)
+    assert roof2["frac_nominal"] == pytest.approx(roof["frac"])
+    assert roof2["peak_nominal"] == pytest.approx(nominal / 1e12)
     assert roof["bound"] == "alu"
     assert roof["avg_launch_us"] == pytest.approx(sec / 4 * 1e6)
     for key in ("unit", "traffic", "kernel", "avg_launch_us_events"):
@@ -36,7 +44,7 @@ def test_roofline_groups_launches_and_prices_against_the_peak():
 
 def test_dominant_kernel_is_the_instance_with_the_most_time():
     run = {"pairs": [_pair(0, 2, 10**9, 0.5), _pair(1, 3, 10**9, 2.0), _pair(2, 2, 10**9, 0.5)]}
-    D, roof = bench.roofline([run], [run])
+    D, roof = bench.roofline([run], [run], 256 * 64 * 2.4e9 / 2)
     assert D == 3 and roof["launches"] == 1
 
 

@@ -3,27 +3,34 @@
 One step = the whole single-code path through the C ABI: mindist_create
 (validate, pack, information sets, Gamma_j, device upload) + mindist_run
 (Algorithm 1: every pair (Gamma_j, w) enumerated by the HIP kernel until
-L >= U, witness rebuilt and checked) + mindist_destroy.  The input matrix
+L >= U, witness rebuilt and certified) + mindist_destroy.  The input matrix
 is generated before the timed region.
 
 Prints one JSON line:
   value      codewords evaluated per second over the timed steps
-  roofline   the enumeration kernel against the chip's 32-bit VALU peak:
-             one codeword = D 32-bit XOR+popcount ops (D = words carried,
-             3 for [150,75] with identity columns stripped), each op = 2 VALU
-             lane instructions, peak = 256 CU x 64 lanes x 2.4 GHz / 2
-  cpu_baseline  the CPU oracle (stack-based BZ enumeration, all threads it
-             was given) on a bounded sample of the same pair
-  batch      a uniform sample of the 4096-code batch stream: one persistent
-             launch vs one mindist_run per code (codes/s, identical results)
-  serving    open-loop Poisson arrivals of the serving stream at one rate:
-             p50/p99 latency and codes/s (requests above a work cap are left
-             out and counted); --serving-sweep runs the whole rate sweep
+  roofline   the dominant enumeration kernel against the VALU ceiling: one
+             codeword = D 32-bit XOR+popcount ops (D = words carried, 3 for
+             [150,75] with identity columns stripped); peak = the larger of
+             the rated-clock figure (256 CU x 64 lanes x 2.4 GHz / 2) and
+             the measured register-only ceiling (mindist_peak_xorpop)
+  time_to_d  the whole path on [48,24], [255,40] (median of repeats) and
+             [150,75] (the timed steps), with the share of the VALU peak
   section6   the smallest Section 6 code, [232,51], certified (d = 61 claimed)
+  serving    open-loop Poisson arrivals of the serving stream at 10, 30, 100,
+             300 and 1000 per second under both engines: p50/p99 latency
+             (all and by work), codes/s, offered load, requests left out by
+             the work cap
+  cpu_baseline  the CPU oracle (stack-based BZ enumeration) on the host's
+             threads (at most 16) and on one thread, median of 3 windows;
+             brute force and the oracle's BZ on [48,24]
+  batch      all 4096 codes of the batch stream: one mindist_run per code,
+             one mindist_run_batch call (long codes routed to the single
+             path) and one persistent launch for every code, results
+             compared in full; per-stratum speed-ups
 --new-codes certifies the codes of Section 6 instead (one line per code);
---paper-random runs seeded codes of the random sizes the paper times;
 --compare-walk measures the saved-sums kernel against the direct walk;
---cpu-family times the paper's CPU algorithms on the host (Table 1's code size).
+--cpu-family times the paper's CPU algorithms on the host (Table 1's code size);
+--peak runs the register-only ceiling kernel alone.
 """
 from __future__ import annotations
 
@@ -144,24 +151,96 @@ def roofline(results, events, peak):
     }
 
 
-def cpu_baseline(w, seconds: float = 12.0):
+def cpu_baseline(w, seconds: float = 4.0, repeats: int = 3):
+    """The CPU oracle on the host: its stack-based enumeration of pair
+    (Gamma_1, w=8) of [150,75] over windows of consecutive lexicographic
+    ranks, on every host thread this process may use (at most 16, the GPU
+    box's share) and on one thread, median of `repeats` windows of about
+    `seconds` each; plus brute force over all 2^24 messages of [48,24] and
+    the oracle's whole BZ run on it, one thread."""
+    import statistics
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
+    from paper_1603_06757_amd.gen import WORKLOADS
+    nproc = os.cpu_count() or 1
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = nproc
+    threads = max(1, min(usable, 16))
     G = w.matrix()
     full, _ = oracle.partition(G, w.n, w.k)
     Gam = oracle.gamma(G, w.n, w.k, full[0])
     end = oracle.binom(w.k, 8)
-    lo, total, t_used = 0, 0, 0.0
-    chunk = 1 << 25
-    while t_used < seconds and lo < end:
-        t = time.perf_counter()
-        _, _, _, cnt, _ = oracle.pair(Gam, w.n, w.k, 8, lo, min(lo + chunk, end), threads)
-        t_used += time.perf_counter() - t
-        lo += chunk
-        total += cnt
-    return {"value": total / t_used, "unit": "codewords/s", "cores": threads, "kind": "oracle",
-            "sample": f"pair (Gamma_1, w=8) of [{w.n},{w.k}], lexicographic ranks [0,{min(lo, end)}), "
-                      f"{t_used:.1f}s, stack-based enumeration, full-width rows"}
+
+    def window(th, r):
+        # window r starts at rank r * end / repeats and runs about `seconds`
+        lo, hi = r * end // repeats, (r + 1) * end // repeats
+        total, t_used = 0, 0.0
+        chunk = 1 << (25 if th > 1 else 22)
+        while t_used < seconds and lo < hi:
+            t = time.perf_counter()
+            _, _, _, cnt, _ = oracle.pair(Gam, w.n, w.k, 8, lo, min(lo + chunk, hi), th)
+            t_used += time.perf_counter() - t
+            lo += chunk
+            total += cnt
+        return total / t_used, total, t_used
+
+    runs = {}
+    for th in (threads, 1):
+        rs = [window(th, r) for r in range(repeats)]
+        runs[th] = rs
+        print(f"[bench] cpu oracle, {th} threads: {statistics.median(r[0] for r in rs):.3e} codewords/s",
+              file=sys.stderr, flush=True)
+    med = lambda th: statistics.median(r[0] for r in runs[th])
+    c1 = WORKLOADS["rand48x24"]
+    G1 = c1.matrix()
+    t = time.perf_counter()
+    d_brute, _, _ = oracle.brute(G1, c1.n, c1.k)
+    t_brute = time.perf_counter() - t
+    t = time.perf_counter()
+    r1 = oracle.bz(G1, c1.n, c1.k, threads=1)
+    t_bz1 = time.perf_counter() - t
+    assert r1["d"] == d_brute
+    return {"value": med(threads), "unit": "codewords/s", "cores": threads, "kind": "oracle",
+            "sample": f"pair (Gamma_1, w=8) of [{w.n},{w.k}]: {repeats} windows of consecutive "
+                      f"lexicographic ranks, ~{seconds:.0f} s each, median; stack-based enumeration, "
+                      f"full-width rows",
+            "nproc": nproc, "usable_cpus": usable,
+            "single_thread": {"value": med(1), "unit": "codewords/s", "cores": 1},
+            "windows": {str(th): [{"codewords": c, "seconds": s_} for _, c, s_ in rs]
+                        for th, rs in runs.items()},
+            "config1_brute_force": {"code": "[48,24]", "d": d_brute, "messages": 2 ** c1.k,
+                                    "seconds": t_brute, "threads": 1,
+                                    "codewords_per_s": (2 ** c1.k) / t_brute},
+            "config1_oracle_bz": {"code": "[48,24]", "d": r1["d"], "seconds": t_bz1, "threads": 1}}
+
+
+def time_to_d_leg(peak: float, repeats=(("rand48x24", 30), ("rand255x40", 10))):
+    """Time to d of the small and the low-rate single codes: the whole path
+    (mindist_create + mindist_run + mindist_destroy) per run, median of the
+    repeats, and the share of the VALU peak over that whole time (each
+    pair's evaluated codewords times its 32-bit words)."""
+    import statistics
+    import paper_1603_06757_amd as md
+    from paper_1603_06757_amd.gen import WORKLOADS
+    out = {}
+    for name, reps in repeats:
+        w = WORKLOADS[name]
+        G = w.matrix()
+        md.min_distance(G, w.n, w.k)             # warm: shapes, pools
+        times, r = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = md.min_distance(G, w.n, w.k)
+            times.append(time.perf_counter() - t0)
+        t = statistics.median(times)
+        ops = sum(p["executed"] * p["dwords"] for p in r["pairs"])
+        out[name] = {"n": w.n, "k": w.k, "d": r["d"], "pairs": r["pairs_visited"],
+                     "codewords": r["executed_total"], "time_to_d_ms": t * 1e3,
+                     "time_to_d_ms_min": min(times) * 1e3, "runs": reps,
+                     "codewords_per_s": r["executed_total"] / t, "valu_frac": ops / t / peak}
+        print(f"[bench] time to d {name}: {t * 1e3:.3f} ms", file=sys.stderr, flush=True)
+    return out
 
 
 def estimated_work(md, G, n: int, k: int) -> float:
@@ -190,15 +269,41 @@ def estimated_work(md, G, n: int, k: int) -> float:
     return work
 
 
-def batch_leg(codes_total: int, stride: int):
-    """Codes i = 0, stride, 2*stride, ... of the 4096-code batch stream:
-    all of them in one persistent launch (hipGraph) vs one mindist_run per
-    code, same GPU, results compared."""
+# work strata of the batch stream, by the codewords a code's run evaluates
+STRATA = (("light", 0.0, 1e9), ("medium", 1e9, 2e10), ("heavy", 2e10, 1e12),
+          ("very_heavy", 1e12, float("inf")))
+
+
+def _pair_key(p):
+    return (p["j"], p["w"], p["L_before"], p["U_after"], p["pair_min"], p["count"])
+
+
+def _same_runs(a, b) -> bool:
+    """d, the whole visited-pair sequence (set, level, bound before, U after,
+    pair minimum, C(k,w)), and L after and executed for every completed pair."""
+    if a.get("d") != b.get("d") or len(a["pairs"]) != len(b["pairs"]):
+        return False
+    for pa, pb in zip(a["pairs"], b["pairs"]):
+        if _pair_key(pa) != _pair_key(pb):
+            return False
+        if pa["executed"] == pa["count"] and pb["executed"] == pb["count"] and pa["L_after"] != pb["L_after"]:
+            return False
+    return all(pa["executed"] == pb["executed"] for pa, pb in zip(a["pairs"][:-1], b["pairs"][:-1]))
+
+
+def batch_leg(codes_total: int, stride: int, strata_calls=("light", "medium", "heavy")):
+    """The batch stream (every `stride`-th code; 1 = all): one mindist_run
+    per code (each timed), the whole stream in one mindist_run_batch call
+    with long codes routed to the single path, and in one persistent launch
+    for every code; every code's result compared in full.  Strata by the
+    codewords each code evaluates; the strata in `strata_calls` are also run
+    as batches of their own, for per-stratum speed-ups."""
     import paper_1603_06757_amd as md
     from paper_1603_06757_amd.gen import batch_code
     from paper_1603_06757_amd.autotune import tuned_options
     idx = list(range(0, codes_total, stride))
     codes = [batch_code(i) for i in idx]
+    say = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
 
     def tuning_sample():
         # other codes of the same stream, without the heaviest (tuning in seconds)
@@ -210,46 +315,95 @@ def batch_leg(codes_total: int, stride: int):
         return out
 
     t0 = time.perf_counter()
-    opts = tuned_options(f"batch stream of {codes_total} codes", tuning_sample,
-                         log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+    opts = tuned_options(f"batch stream of {codes_total} codes", tuning_sample, log=say)
     t_tune = time.perf_counter() - t0
     md.run_batch(codes[:4], pairs=False, **opts)
-    t0 = time.perf_counter()
-    res, info = md.run_batch(codes, pairs=False, deadline_s=600, **opts)
-    tb = time.perf_counter() - t0
-    print(f"[bench] batch of {len(codes)} codes: {tb:.2f}s", file=sys.stderr, flush=True)
-    # the same codes all in the persistent launch (no routing to the single path)
-    t0 = time.perf_counter()
-    res_p, info_p = md.run_batch(codes, pairs=False, deadline_s=600, direct_log2=-1, **opts)
-    tpers = time.perf_counter() - t0
-    print(f"[bench] batch of {len(codes)} codes, persistent launch only: {tpers:.2f}s",
-          file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    plain = [md.min_distance(G, n, k) for n, k, G in codes]
+    # one run per code, each timed
+    plain, t_plain = [], []
+    t0 = t_say = time.perf_counter()
+    for i, (n, k, G) in enumerate(codes):
+        t = time.perf_counter()
+        plain.append(md.min_distance(G, n, k))
+        t_plain.append(time.perf_counter() - t)
+        if time.perf_counter() - t_say > 15:
+            say(f"one run per code: {i + 1}/{len(codes)}")
+            t_say = time.perf_counter()
     tp = time.perf_counter() - t0
-    print(f"[bench] one run per code: {tp:.2f}s", file=sys.stderr, flush=True)
-    same = all(r.get("d") == p["d"] and r.get("canonical_total") == p["canonical_total"]
-               and q.get("d") == p["d"] and q.get("canonical_total") == p["canonical_total"]
-               for r, q, p in zip(res, res_p, plain))
+    say(f"one run per code: {tp:.2f}s")
+    stratum = []
+    for r in plain:
+        for name, lo, hi in STRATA:
+            if lo <= r["executed_total"] < hi:
+                stratum.append(name)
+                break
+    # the whole stream, routed and persistent-only
+    t0 = time.perf_counter()
+    res, info = md.run_batch(codes, pairs=True, deadline_s=400, **opts)
+    tb = time.perf_counter() - t0
+    say(f"batch of {len(codes)} codes, long codes routed: {tb:.2f}s")
+    t0 = time.perf_counter()
+    res_p, info_p = md.run_batch(codes, pairs=True, deadline_s=400, direct_log2=-1, **opts)
+    tpers = time.perf_counter() - t0
+    say(f"batch of {len(codes)} codes, one persistent launch: {tpers:.2f}s")
+    same = [_same_runs(r, p) for r, p in zip(res, plain)]
+    same_p = [_same_runs(q, p) for q, p in zip(res_p, plain)]
+    strata = {}
+    for name, lo, hi in STRATA:
+        members = [i for i, s_ in enumerate(stratum) if s_ == name]
+        if not members:
+            continue
+        rec = {"codewords_range": [lo, hi if hi != float("inf") else None], "codes": len(members),
+               "codewords": sum(plain[i]["executed_total"] for i in members),
+               "plain_s": sum(t_plain[i] for i in members)}
+        rec["codes_per_s_plain"] = len(members) / rec["plain_s"]
+        if name in strata_calls:
+            sub = [codes[i] for i in members]
+            for mode, kw in (("routed", {}), ("persistent_only", {"direct_log2": -1})):
+                t0 = time.perf_counter()
+                sr, _ = md.run_batch(sub, pairs=True, deadline_s=400, **kw, **opts)
+                dt = time.perf_counter() - t0
+                rec[f"{mode}_s"] = dt
+                rec[f"codes_per_s_{mode}"] = len(sub) / dt
+                rec[f"speedup_{mode}"] = rec["plain_s"] / dt
+                rec[f"identical_{mode}"] = all(_same_runs(a, plain[i]) for a, i in zip(sr, members))
+            say(f"stratum {name}: {len(members)} codes, plain {rec['plain_s']:.2f}s, "
+                f"routed {rec['routed_s']:.2f}s, persistent {rec['persistent_only_s']:.2f}s")
+        else:
+            rec["note"] = "not run as a batch of its own: its codes dominate the whole-stream calls"
+        strata[name] = rec
     return {"codes": len(codes), "sample": f"codes 0,{stride},...,{codes_total - stride} of the "
                                             f"{codes_total}-code stream" if stride > 1 else
                                             f"all {codes_total} codes",
-            "batched_s": tb, "plain_s": tp, "codes_per_s_batched": len(codes) / tb,
-            "codes_per_s_plain": len(codes) / tp, "speedup": tp / tb, "identical": same,
+            "plain_s": tp, "codes_per_s_plain": len(codes) / tp,
+            "batched_s": tb, "codes_per_s_batched": len(codes) / tb, "speedup": tp / tb,
+            "persistent_only_s": tpers, "codes_per_s_persistent_only": len(codes) / tpers,
+            "speedup_persistent_only": tp / tpers,
+            "identical": all(same), "identical_codes": sum(same),
+            "identical_persistent_only": all(same_p), "identical_codes_persistent_only": sum(same_p),
+            "identity": "d and the whole visited-pair sequence (set, level, L before, U after, pair "
+                        "minimum, C(k,w); L after and executed of completed pairs) against one "
+                        "mindist_run per code",
             "routing": "codes estimated at >= 2^30 combinations through the single path "
                        "on 8 worker threads, the rest in one persistent launch",
-            "persistent_only_s": tpers, "speedup_persistent_only": tp / tpers,
-            "kernel_s": info["seconds_kernel"], "autotuned": opts, "autotune_s": t_tune,
-            "codewords": info["executed_total"],
-            "codewords_per_s_kernel": info["executed_total"] / info["seconds_kernel"]}
+            "strata": strata,
+            "kernel_s": info["seconds_kernel"], "kernel_s_persistent_only": info_p["seconds_kernel"],
+            "autotuned": opts, "autotune_s": t_tune,
+            "codewords": sum(r["executed_total"] for r in plain),
+            "codewords_per_s_plain": sum(r["executed_total"] for r in plain) / tp}
 
 
-def serving_leg(rate: float, seconds: float, cap: float, max_requests: int = 4000, engine: int = 0):
+SERVING_STRATA = (("under_1e7", 0.0, 1e7), ("1e7_to_1e9", 1e7, 1e9), ("1e9_to_cap", 1e9, float("inf")))
+
+
+def serving_leg(rate: float, seconds: float, cap: float, max_requests: int = 4000, engine: int = 0,
+                rate_codewords: float = 0.0):
     """Open-loop Poisson arrivals of the serving stream at `rate` per second
     for about `seconds`; requests whose estimated work exceeds `cap`
     codewords are left out of the stream (counted in the report).  engine 0:
     worker threads running the single-code path side by side; engine 1: the
-    persistent multi-code kernel in epochs."""
+    persistent multi-code kernel.  Latency = completion - submission;
+    offered load = rate x the mean evaluated codewords per request /
+    rate_codewords (the single path's codewords/s)."""
     import numpy as np
     import paper_1603_06757_amd as md
     from paper_1603_06757_amd.gen import serving_request, poisson_arrivals
@@ -271,25 +425,45 @@ def serving_leg(rate: float, seconds: float, cap: float, max_requests: int = 400
                 time.sleep(dt)
             srv.submit(G, n, k, tag=tag)
         got, t_say = [], time.perf_counter()
-        while len(got) < len(kept) and time.perf_counter() - t_start < 600:
+        while len(got) < len(kept) and time.perf_counter() - t_start < 300:
             got += srv.poll()
-            if time.perf_counter() - t_say > 2.0:
-                print(f"[bench] serving {rate}/s: {len(got)}/{len(kept)} done",
+            if time.perf_counter() - t_say > 5.0:
+                print(f"[bench] serving {rate}/s engine {engine}: {len(got)}/{len(kept)} done",
                       file=sys.stderr, flush=True)
                 t_say = time.perf_counter()
-            time.sleep(0.01)
+            time.sleep(0.002)
         t_end = max(r["t_done"] for r in got) - min(r["t_submit"] for r in got) if got else 0.0
-        t_end += t_start
         st = srv.stats()
     lat = np.array([r["t_done"] - r["t_submit"] for r in got]) if got else np.zeros(1)
-    ok = sum(1 for r in got if r["status"] == 0)
-    return {"engine": engine, "rate_per_s": rate, "requests": len(kept), "completed_ok": ok,
+    ok = [r for r in got if r["status"] == 0]
+    work = [r["executed_total"] for r in ok]
+    mean_work = float(np.mean(work)) if work else 0.0
+    per = {}
+    for name, lo, hi in SERVING_STRATA:
+        ls = [r["t_done"] - r["t_submit"] for r in ok if lo <= r["executed_total"] < hi]
+        if ls:
+            per[name] = {"requests": len(ls), "p50_ms": float(np.percentile(ls, 50) * 1e3),
+                         "p99_ms": float(np.percentile(ls, 99) * 1e3)}
+    return {"engine": engine, "rate_per_s": rate, "requests": len(kept), "completed_ok": len(ok),
             "skipped_over_cap": skipped, "work_cap_codewords": cap,
-            "offered_s": float(arr[-1]), "wall_s": t_end - t_start,
-            "codes_per_s": len(got) / (t_end - t_start),
+            "offered_s": float(arr[-1]), "wall_s": t_end,
+            "codes_per_s": len(got) / t_end if t_end else 0.0,
+            "mean_codewords": mean_work,
+            "offered_load": rate * mean_work / rate_codewords if rate_codewords else None,
             "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
             "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "epochs": st["epochs"], "kernel_s": st["seconds_kernel"]}
+            "by_work": per, "epochs": st["epochs"], "kernel_s": st["seconds_kernel"]}
+
+
+SERVING_RATES = ((10, 8.0), (30, 4.0), (100, 2.5), (300, 1.5), (1000, 1.0))
+
+
+def serving_sweep(cap: float, rate_codewords: float, engines=(0, 1), rates=SERVING_RATES):
+    out = {}
+    for engine in engines:
+        out[f"engine{engine}"] = [serving_leg(r, sec, cap, engine=engine, rate_codewords=rate_codewords)
+                                  for r, sec in rates]
+    return out
 
 
 # Section 6's timings of its best CPU implementation (vectorised saved
@@ -331,62 +505,6 @@ def new_codes_leg(names, quiet: bool = False, peak: float = 0.0):
         out.append(rec)
         if not quiet:
             print(json.dumps(rec), flush=True)
-    return out
-
-
-# The paper's times for its random codes on one AMD Opteron 6128 (2.0 GHz)
-# machine, seconds: vectorised saved additions on 1 core (Table 2) and on 6
-# cores (Table 4), Magma on 6 cores (Table 4).  Context only: its matrices
-# are unpublished, the codes run here are seeded stand-ins of the same size.
-PAPER_RANDOM_S = {
-    (150, 50): (38.9, 7.8, 29.3),
-    (130, 67): (331.3, 64.9, 345.3),
-    (115, 63): (755.1, 134.2, 860.5),
-    (102, 62): (3047.5, 525.1, 3659.8),
-    (150, 77): (10245.4, 1763.1, 9562.8),
-}
-
-
-def paper_random_leg(repeats: int = 3, attempts: int = 64):
-    """Seeded random codes of the sizes the paper times, whole single-code
-    path (fresh context each run, best of `repeats`), next to its times.
-    Work grows steeply with d, so of the first `attempts` seeded matrices of
-    each size the first whose distance equals the paper's code is timed (the
-    closest one if none does)."""
-    import paper_1603_06757_amd as md
-    from paper_1603_06757_amd.gen import PAPER_RANDOM_SIZES, paper_random_code
-    out = []
-    for n, k, d_paper in PAPER_RANDOM_SIZES:
-        pick = None                               # (|d - d_paper|, attempt, G)
-        for attempt in range(attempts):
-            G = paper_random_code(n, k, attempt)
-            try:
-                d = md.min_distance(G, n, k)["d"]
-            except md.MindistError as e:
-                if e.code != -2:                  # rank-deficient draws are skipped
-                    raise
-                continue
-            if pick is None or abs(d - d_paper) < pick[0]:
-                pick = (abs(d - d_paper), attempt, G)
-            if d == d_paper:
-                break
-        _, attempt, G = pick
-        best, r = None, None
-        for _ in range(repeats):
-            t0 = time.perf_counter()
-            r = md.min_distance(G, n, k)
-            dt = time.perf_counter() - t0
-            best = dt if best is None else min(best, dt)
-        one, six, magma6 = PAPER_RANDOM_S[(n, k)]
-        rec = {"paper_random": f"[{n},{k}]", "seed": 6, "stream": 1000 * n + k, "attempt": attempt,
-               "d": r["d"], "d_paper_code": d_paper,
-               "seconds": best, "codewords": r["executed_total"],
-               "codewords_per_s": r["executed_total"] / best,
-               "paper_s": {"vector_saved_1_core": one, "vector_saved_6_cores": six,
-                           "magma_6_cores": magma6,
-                           "machine": "AMD Opteron 6128, 2.0 GHz (cplex)"}}
-        out.append(rec)
-        print(json.dumps(rec), flush=True)
     return out
 
 
@@ -517,8 +635,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run plain device copies of this size (counter reference) and exit")
     ap.add_argument("--batch-codes", type=int, default=4096, help="size of the batch stream")
-    ap.add_argument("--batch-stride", type=int, default=8,
-                    help="batch leg: every stride-th code of the stream (1 = all)")
+    ap.add_argument("--batch-stride", type=int, default=1,
+                    help="batch leg: every stride-th code of the stream (1 = all, the default)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-section6", action="store_true",
@@ -533,9 +651,6 @@ def main():
     ap.add_argument("--compare-walk", action="store_true",
                     help="only compare the saved-sums kernel with the lexicographic walk "
                          "kernel on the pairs of [150,75] with w >= 6, and exit")
-    ap.add_argument("--paper-random", action="store_true",
-                    help="only run seeded random codes of the sizes the paper times "
-                         "(one JSON line per size, with the paper's CPU times) and exit")
     ap.add_argument("--new-codes", nargs="*", default=None,
                     help="only certify Section 6's codes (all, or the names given; "
                          "one JSON line per code) and exit")
@@ -556,9 +671,6 @@ def main():
     if a.compare_walk:
         walk_compare_leg()
         return
-    if a.paper_random:
-        paper_random_leg()
-        return
     if a.new_codes is not None:
         new_codes_leg(a.new_codes)
         return
@@ -568,7 +680,8 @@ def main():
                 if engine == 1 and rate > 1000:
                     continue           # already saturated at 1000/s
                 print(json.dumps({"serving": serving_leg(rate, 4.0 if rate >= 100 else 10.0,
-                                                         a.serving_cap, engine=engine)}), flush=True)
+                                                         a.serving_cap, engine=engine,
+                                                         rate_codewords=5.5e12)}), flush=True)
         return
     w, results, dt, events = single_code_leg(a.steps, a.warmup)
     ref = results[0]
@@ -603,18 +716,24 @@ def main():
         "time_to_d_ms": dt / a.steps * 1e3,
         "roofline": roof,
     }
-    if not a.no_batch:
-        print("[bench] batch leg", file=sys.stderr, flush=True)
-        line["batch"] = batch_leg(a.batch_codes, max(1, a.batch_stride))
-    if not a.no_serving:
-        print("[bench] serving leg", file=sys.stderr, flush=True)
-        line["serving"] = serving_leg(300.0, 3.0, a.serving_cap)
+    print("[bench] time to d, configs [48,24] and [255,40]", file=sys.stderr, flush=True)
+    line["time_to_d"] = time_to_d_leg(max(PEAK_DWORD_OPS, peak["ops_per_s"]))
+    line["time_to_d"]["rand150x75"] = {"time_to_d_ms": dt / a.steps * 1e3, "d": ref["d"],
+                                       "valu_frac": sum(p["executed"] * p["dwords"] for r in results
+                                                        for p in r["pairs"]) / dt
+                                       / max(PEAK_DWORD_OPS, peak["ops_per_s"])}
     if not a.no_section6:
         print("[bench] section 6 code", file=sys.stderr, flush=True)
         line["section6"] = new_codes_leg(["mp232x51"], quiet=True, peak=peak["ops_per_s"])[0]
+    if not a.no_serving:
+        print("[bench] serving sweep", file=sys.stderr, flush=True)
+        line["serving"] = serving_sweep(a.serving_cap, executed / dt)
     if not a.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)
+    if not a.no_batch:
+        print("[bench] batch leg", file=sys.stderr, flush=True)
+        line["batch"] = batch_leg(a.batch_codes, max(1, a.batch_stride))
     print(json.dumps(line), flush=True)
 
 

@@ -106,7 +106,7 @@ int single_path_bytes(const uint64_t *G, int n, int k, uint64_t table_cap, size_
     return MINDIST_OK;
 }
 
-int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &hc) {
+int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &hc, uint64_t heavy_cap) {
     hc = HostCode();
     hc.n = n;
     hc.k = k;
@@ -122,7 +122,9 @@ int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &
     // short codes keep their tables small: their table job would otherwise
     // sit on the launch's critical path (a code's pairs wait for it) and
     // small tables stay in cache while many codes read theirs at once
-    if (estimated_work(hc) < kSmallCodeWork) table_cap = std::min<uint64_t>(table_cap, kSmallCodeTableBytes);
+    const double work = estimated_work(hc);
+    if (work < kSmallCodeWork) table_cap = std::min<uint64_t>(table_cap, kSmallCodeTableBytes);
+    if (work >= kHeavyCodeWork && heavy_cap) table_cap = std::max<uint64_t>(table_cap, heavy_cap);
     for (int j = 0; j < hc.n_gamma; ++j) {
         const std::vector<int> cols = carried_columns(hc.P, j);
         hc.D[j] = (int)((cols.size() + 31) / 32);
@@ -376,7 +378,7 @@ extern "C" int mindist_run_batch(const uint64_t *const *G, const int *n, const i
     std::vector<int> status(B, 0);
     std::vector<std::string> errs(B);
     parallel_for(B, host_threads(), [&](int i) {
-        status[i] = prepare_code(G[i], n[i], k[i], table_cap, hc[i]);
+        status[i] = prepare_code(G[i], n[i], k[i], table_cap, hc[i], o.table_kib > 0 ? 0 : kHeavyCodeTableBytes);
     });
     const auto t_prep = std::chrono::steady_clock::now();
     // routing: a code expected to enumerate at least 2^direct_log2

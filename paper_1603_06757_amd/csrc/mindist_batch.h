@@ -41,6 +41,11 @@ constexpr uint64_t kTableReuse = 1024;
 // saved table within kSmallCodeTableBytes
 constexpr double kSmallCodeWork = 536870912.0;         // 2^29
 constexpr uint64_t kSmallCodeTableBytes = 256u << 10;  // 256 KiB
+// codes expected to enumerate at least 2^34 combinations may keep tables up
+// to the single path's cap (with the default per-table cap): their large
+// pairs then take the same balanced split, whose right runs are longer
+constexpr double kHeavyCodeWork = 17179869184.0;       // 2^34
+constexpr uint64_t kHeavyCodeTableBytes = 1ull << 30;  // 1 GiB
 // tables of set j: right tables b = 0..bcap (shift 0) at t = j*kTabsPerSet + b,
 // outer tables b1 = 1..bcap over rows [0, k-bcap) (shift bcap, with inner
 // counts) at t = j*kTabsPerSet + (kBatchMaxB+1) + b1
@@ -87,7 +92,10 @@ struct alignas(128) BatchJob {
     uint64_t t_open, t_close;     // device wall clock: job opened, last chunk counted
     uint64_t pad_b[2];
     alignas(128) uint64_t done;   // completed chunks
-    uint64_t pad_d[15];
+    uint32_t drained_mask;        // bit r: counter r found past its end (shared, so that a
+                                  // wave leaving a job need not try every counter)
+    uint32_t pad_e;
+    uint64_t pad_d[14];
     struct alignas(128) Counter {
         uint64_t v;
         uint64_t pad[15];

@@ -31,6 +31,21 @@ __device__ __forceinline__ uint64_t ld_acq(const uint64_t *p) {
 __device__ __forceinline__ uint32_t ld_rlx(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Coherent reads of what another wave published during the launch (job
+// records, chunk groups): device-scope loads see the data the publishing
+// wave released, with no cache-wide invalidation.  Each XCD has its own L2:
+// an acquire fence at device scope invalidates the reading XCD's whole L2,
+// which the waves' table reads then pay for; the job's address comes from
+// the published offset, so these loads follow the publication.
+__device__ __forceinline__ uint32_t ldc(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ldc(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ldc(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void st_rel(int32_t *p, int32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -148,12 +163,54 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
     const uint64_t tiles = (n_items + TB - 1) / TB;
     uint32_t T;
     if (b2 == 0) {
-        // right tile: about 4 chunks per resident wave for this pair alone,
-        // between the configured bounds (pairs of many codes run side by side)
+        // Right tile from the exact chunk count at each length 16 << t: a
+        // left tile whose first subset has largest element e meets
+        // C(k-1-e, b) right entries.  The waves this pair can expect are the
+        // launch's waves over the codes still running (the chunks-per-visit
+        // quantum spreads them), and it should leave each of them max(2,
+        // D-1) chunks: from the lower configured bound, longer while the
+        // chunks allow (short codes' per-chunk set-up dominates below that
+        // bound; long pairs gain from long tiles).  Few live codes (a
+        // batch's heavy tail): shorter than the bound where the pair is
+        // short, so it is not a few long tiles walked by a few waves while
+        // the rest wait for its next pair.
         const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-        const uint64_t want = binom(A.binom, k, w) / (TB * waves * 4 + 1);
-        T = A.tile_min;
-        while (T < A.tile_max && T < cs->tile_cap && T < want) T <<= 1;
+        const uint32_t done = A.serving ? 0u : uni32(ld_rlx(&A.g->codes_done));
+        const uint64_t live = (uint64_t)A.n_codes > done ? (uint64_t)A.n_codes - done : 1ull;
+        const uint64_t share = A.serving ? 1ull : (waves / live > 0 ? waves / live : 1ull);
+        const uint64_t need = (uint64_t)(set.D > 3 ? set.D - 1 : 2) * share;
+        constexpr int kCand = 10;                // T = 16 .. 8192
+        uint64_t ch[kCand];
+        for (int t = 0; t < kCand; ++t) ch[t] = 0;
+        for (int e0 = a - 1; e0 <= k - 1 - b; e0 += 64) {
+            const int e = e0 + lane;
+            uint64_t nlt = 0, nr = 0;
+            if (e <= k - 1 - b) {
+                const uint64_t lt_lo = (binom(A.binom, e, a) + TB - 1) / TB;
+                uint64_t lt_hi = (binom(A.binom, e + 1, a) + TB - 1) / TB;
+                if (lt_hi > tiles) lt_hi = tiles;
+                if (lt_hi > lt_lo) {
+                    nlt = lt_hi - lt_lo;
+                    nr = binom(A.binom, k - 1 - e, b);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kCand; ++t) ch[t] += wave_sum_u64(nlt * ((nr + (16ull << t) - 1) >> (4 + t)));
+        }
+        auto chunks_at = [&](uint32_t TT) {
+            uint64_t r = 0;
+#pragma unroll
+            for (int t = 0; t < kCand; ++t)
+                if ((16u << t) == TT) r = ch[t];
+            return r;
+        };
+        const uint32_t t_hi = min(min(A.tile_max, cs->tile_cap), 8192u);
+        T = min(A.tile_min, t_hi);
+        if (chunks_at(T) >= need) {
+            while (T < t_hi && chunks_at(T << 1) >= need) T <<= 1;
+        } else if (share >= 16) {
+            while (T > 16 && chunks_at(T) < need) T >>= 1;
+        }
     } else {
         // outer tile: about 256K codewords per chunk
         const int e = (k - b - b2) * a / (a + 1);
@@ -241,6 +298,7 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
         jb->nctr = job_counters(chunk_base);
         for (int r = 0; r < kJobCounters; ++r) jb->claim[r].v = 0;
         jb->done = 0;
+        jb->drained_mask = 0;
         cs->job[p] = off;
     }
     __threadfence();     // the group entries of every lane, then the record
@@ -268,6 +326,7 @@ __device__ void open_tables(const BatchArgs &A, int c) {
         jb->nctr = job_counters(jb->total_chunks);
         for (int r = 0; r < kJobCounters; ++r) jb->claim[r].v = 0;
         jb->done = 0;
+        jb->drained_mask = 0;
         jb->executed = 0;
         jb->pair_min = kInf;
         cs->job[0] = off;
@@ -436,15 +495,15 @@ __device__ __forceinline__ void load_view(const BatchArgs &A, int c, int p, Batc
     v.c = c;
     v.p = p;
     v.jb = jb;
-    v.kind = (int)uni32((uint32_t)jb->kind);
-    v.total = uni64(jb->total_chunks);
-    v.nctr = uni32(jb->nctr);
+    v.kind = (int)uni32((uint32_t)ldc(&jb->kind));
+    v.total = uni64(ldc(&jb->total_chunks));
+    v.nctr = uni32(ldc(&jb->nctr));
     v.offset = 0;
     if (v.kind == 0) return;
-    v.j = (int)uni32((uint32_t)jb->j);
-    v.a = (int)uni32((uint32_t)jb->a);
-    v.b = (int)uni32((uint32_t)jb->b);
-    v.b2 = (int)uni32((uint32_t)jb->b2);
+    v.j = (int)uni32((uint32_t)ldc(&jb->j));
+    v.a = (int)uni32((uint32_t)ldc(&jb->a));
+    v.b = (int)uni32((uint32_t)ldc(&jb->b));
+    v.b2 = (int)uni32((uint32_t)ldc(&jb->b2));
     v.k = (int)uni32((uint32_t)cs->k);
     const BatchSet &set = cs->sets[v.j];
     v.D = (int)uni32((uint32_t)set.D);
@@ -457,11 +516,11 @@ __device__ __forceinline__ void load_view(const BatchArgs &A, int c, int p, Batc
         v.tab = (const uint32_t *)uni64((uint64_t)set.rtab[v.b]);
         v.cnt2 = v.tab2 = nullptr;
     }
-    v.n_items = uni64(jb->n_items);
-    v.T = uni32(jb->T);
-    v.offset = uni32(jb->offset);
-    v.L_before = uni32(jb->L_before);
-    v.ngroups = (int)uni32(jb->ngroups);
+    v.n_items = uni64(ldc(&jb->n_items));
+    v.T = uni32(ldc(&jb->T));
+    v.offset = uni32(ldc(&jb->offset));
+    v.L_before = uni32(ldc(&jb->L_before));
+    v.ngroups = (int)uni32(ldc(&jb->ngroups));
     v.gr = job_groups(jb);
     v.gi = 0;
 }
@@ -471,22 +530,22 @@ __device__ __forceinline__ void load_view(const BatchArgs &A, int c, int p, Batc
 // to its least weight (without the offset).
 template <int D>
 __device__ __forceinline__ void pair_chunk(const BatchArgs &A, JobView &v, uint64_t ch, uint64_t &exec,
-                           uint32_t &wmin_out) {
+                           uint32_t &wmin_out, bool &wrote) {
     BatchCode *cs = &A.codes[v.c];
     BatchJob *jb = v.jb;
     const int lane = threadIdx.x & 63;
     // group of chunk ch: claims from one counter only grow; a move to
     // another counter may go back
-    if (ch < uni64(v.gr[v.gi].chunk_base)) v.gi = 0;
-    while (v.gi + 1 < v.ngroups && uni64(v.gr[v.gi + 1].chunk_base) <= ch) ++v.gi;
+    if (ch < uni64(ldc(&v.gr[v.gi].chunk_base))) v.gi = 0;
+    while (v.gi + 1 < v.ngroups && uni64(ldc(&v.gr[v.gi + 1].chunk_base)) <= ch) ++v.gi;
     const GroupEntry *ge = v.gr + v.gi;
-    const uint64_t base = uni64(ge->chunk_base), n_rt = uni64(ge->n_rt);
+    const uint64_t base = uni64(ldc(&ge->chunk_base)), n_rt = uni64(ldc(&ge->n_rt));
     const uint64_t offc = ch - base;
     ChunkGeo g;
-    g.lt = uni64(ge->lt_begin) + offc / n_rt;
+    g.lt = uni64(ldc(&ge->lt_begin)) + offc / n_rt;
     g.i_begin = uni32((uint32_t)(offc % n_rt) * v.T);
-    g.i_end = uni32(min(g.i_begin + v.T, uni32(ge->nr_first)));
-    g.e_first = uni32(ge->e);
+    g.i_end = uni32(min(g.i_begin + v.T, uni32(ldc(&ge->nr_first))));
+    g.e_first = uni32(ldc(&ge->e));
     g.clip = false;
     // every address and size of the enumeration re-broadcast from lane 0 at
     // the point of use: the table reads stay scalar loads whatever the
@@ -522,6 +581,7 @@ __device__ __forceinline__ void pair_chunk(const BatchArgs &A, JobView &v, uint6
             cs->slots[val].i2 = hit_i2;
             cs->slots[val].rho = hit_rho;
         }
+        wrote = true;
     }
     if (val <= v.L_before && lane == 0) {
         // U reached the bound before this pair: stop handing out its chunks;
@@ -575,18 +635,23 @@ __device__ void advance(const BatchArgs &A, int c, int p, BatchJob *jb) {
 
 // Next chunk of job jb (total chunks, nctr counters) for this wave, or ~0
 // once every counter is drained.  ctr: the counter tried next; dmask: the
-// counters found drained.
+// counters known drained -- found by this wave, or by others (the job's
+// shared mask, returned by the one atomic a wave spends on a drained
+// counter), so that at the end of a job each wave makes about two claims
+// instead of one per counter.
 __device__ __forceinline__ uint64_t claim_chunk(BatchJob *jb, uint64_t total, uint32_t nctr, uint32_t &ctr,
                                 uint32_t &dmask) {
     const uint32_t all = (1u << nctr) - 1u;
-    while (dmask != all) {
+    while ((dmask & all) != all) {
         const uint32_t r = ctr;
         const uint64_t t = wave_fetch_add(&jb->claim[r].v, 1ull);
         if (t < total) {
             const uint64_t ch = (uint64_t)r + t * nctr;
             if (ch < total) return ch;
         }
-        dmask |= 1u << r;
+        uint32_t seen = 0;
+        if ((threadIdx.x & 63) == 0) seen = atomicOr(&jb->drained_mask, 1u << r);
+        dmask |= uni32((uint32_t)__shfl((int)seen, 0)) | (1u << r);
         for (uint32_t q = 1; q <= nctr; ++q) {
             const uint32_t r2 = (r + q) % nctr;
             if (!(dmask & (1u << r2))) { ctr = r2; break; }
@@ -598,24 +663,30 @@ __device__ __forceinline__ uint64_t claim_chunk(BatchJob *jb, uint64_t total, ui
 // Add a wave's `done` completed chunks of job p of code c (with their
 // `exec` evaluated combinations and least weight `wmin` + offset) to the
 // job; the flush that brings the job's count to `expected` closes the job
-// and applies Algorithm 1's control.
+// and applies Algorithm 1's control.  The counts travel in device-scope
+// atomics; only a wave that wrote plain data since its last flush (table
+// entries, a witness slot) releases it first -- a release at device scope
+// writes back the XCD's whole L2.
 __device__ __noinline__ void flush(const BatchArgs &A, int c, int p, BatchJob *jb, uint64_t done, uint64_t exec,
-                      uint32_t wmin, uint32_t offset) {
+                      uint32_t wmin, uint32_t offset, bool wrote) {
     if (done == 0) return;
     const int lane = threadIdx.x & 63;
+    uint64_t prev = 0, expected = 0;
     if (lane == 0) {
         if (exec) atomicAdd((unsigned long long *)&jb->executed, (unsigned long long)exec);
         if (wmin != kInf) atomicMin(&jb->pair_min, wmin + offset);
     }
-    // release: the chunks' results are performed before they count as done
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    uint64_t prev = 0, expected = 0;
+    // the count atomics (performed at device scope) complete before `done`
+    // is added: a release at workgroup scope waits for them without cache
+    // maintenance; plain data written since the last flush needs the
+    // device-scope release
+    if (wrote) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     if (lane == 0) {
-        prev = atomicAdd((unsigned long long *)&jb->done, (unsigned long long)done);
-        // acquire through `done`: an exit's lowered count, stored before the
-        // exiting wave's own flush, is visible to every later flush
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        expected = atomicAdd((unsigned long long *)&jb->expected, 0ull);
+        prev = __hip_atomic_fetch_add((unsigned long long *)&jb->done, (unsigned long long)done,
+                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        expected = __hip_atomic_fetch_add((unsigned long long *)&jb->expected, 0ull, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
     }
     prev = uni64((uint64_t)__shfl((long long)prev, 0));
     expected = uni64((uint64_t)__shfl((long long)expected, 0));
@@ -647,6 +718,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
     // added to it
     uint32_t ctr = 0, dmask = 0, pmin = kInf, visit = 0;
     uint64_t pdone = 0, pexec = 0;
+    bool wrote = false;            // plain stores since the last flush (tables, a witness slot)
     // profile: ticks in table chunks, enumeration chunks and flushes
     uint64_t tk_table = 0, tk_pair = 0, tk_flush = 0, n_table = 0, n_pair = 0;
     for (;;) {
@@ -667,7 +739,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
         }
         if (stop) {
             // every chunk this wave claimed is complete: count it before leaving
-            if (have) flush(A, v.c, v.p, v.jb, pdone, pexec, pmin, v.offset);
+            if (have) flush(A, v.c, v.p, v.jb, pdone, pexec, pmin, v.offset, wrote);
             if (lane == 0) {
                 atomicAdd((unsigned long long *)&A.g->ticks_table, (unsigned long long)tk_table);
                 atomicAdd((unsigned long long *)&A.g->ticks_pair, (unsigned long long)tk_pair);
@@ -684,18 +756,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
                 const uint64_t t0 = wall_clock64();
                 if (v.kind == 0) {
                     table_chunk(A, &A.codes[v.c], ch, my_rows);
+                    wrote = true;
                     tk_table += wall_clock64() - t0;
                     n_table += 1;
                 } else {
                     switch (v.D) {
-                        case 1: pair_chunk<1>(A, v, ch, pexec, pmin); break;
-                        case 2: pair_chunk<2>(A, v, ch, pexec, pmin); break;
-                        case 3: pair_chunk<3>(A, v, ch, pexec, pmin); break;
-                        case 4: pair_chunk<4>(A, v, ch, pexec, pmin); break;
-                        case 5: pair_chunk<5>(A, v, ch, pexec, pmin); break;
-                        case 6: pair_chunk<6>(A, v, ch, pexec, pmin); break;
-                        case 7: pair_chunk<7>(A, v, ch, pexec, pmin); break;
-                        default: pair_chunk<8>(A, v, ch, pexec, pmin); break;
+                        case 1: pair_chunk<1>(A, v, ch, pexec, pmin, wrote); break;
+                        case 2: pair_chunk<2>(A, v, ch, pexec, pmin, wrote); break;
+                        case 3: pair_chunk<3>(A, v, ch, pexec, pmin, wrote); break;
+                        case 4: pair_chunk<4>(A, v, ch, pexec, pmin, wrote); break;
+                        case 5: pair_chunk<5>(A, v, ch, pexec, pmin, wrote); break;
+                        case 6: pair_chunk<6>(A, v, ch, pexec, pmin, wrote); break;
+                        case 7: pair_chunk<7>(A, v, ch, pexec, pmin, wrote); break;
+                        default: pair_chunk<8>(A, v, ch, pexec, pmin, wrote); break;
                     }
                     tk_pair += wall_clock64() - t0;
                     n_pair += 1;
@@ -708,7 +781,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
             // visit's share is used up: count its chunks and move on
             if (!turn_over && lane == 0) atomicMax(&A.codes[v.c].drained, v.p + 1);
             const uint64_t t0 = wall_clock64();
-            flush(A, v.c, v.p, v.jb, pdone, pexec, pmin, v.offset);
+            flush(A, v.c, v.p, v.jb, pdone, pexec, pmin, v.offset, wrote);
+            wrote = false;
             tk_flush += wall_clock64() - t0;
             if (!turn_over) drained = v.off;
             have = false;
@@ -755,14 +829,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
             __builtin_amdgcn_s_sleep(2);
             continue;
         }
-        // acquire once per job: everything written before the job was
-        // published (record, groups, tables) is visible from here on
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const uint32_t off = uni32(cs->job[p]);
-        if (off == drained) {
-            cur = (c + 1) % nc;
-            continue;
-        }
+        // no acquire fence: the job's record and groups are read with
+        // device-scope loads (ldc) through the published offset, and its
+        // tables were released by the waves that built them (their flushes)
+        // before the pair that reads them was opened
+        const uint32_t off = off0;
         BatchJob *jb = job_at(A, off);
         load_view(A, c, p, jb, v);
         v.off = off;

@@ -29,7 +29,9 @@ struct SlotPlace {
     unsigned char *rows, *tabs, *slots;
 };
 
-int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &hc);
+// heavy_cap: per-table cap for codes expected at or above kHeavyCodeWork
+// combinations (0 = the same cap for every code)
+int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &hc, uint64_t heavy_cap = 0);
 // validate G and estimate the device bytes the single-code path holds for
 // it (rows, saved right and left tables up to half the expected top level,
 // rounded up, within the table cap; run state)

@@ -31,9 +31,14 @@ constexpr int kBatchItemsMaxD4 = 4;
 constexpr int kBatchItemsWide = 2;
 MD_HD constexpr int batch_items(int D) { return D <= 4 ? kBatchItemsMaxD4 : kBatchItemsWide; }
 constexpr int kTableChunk = 4096;     // table entries per table-job chunk
-// LDS words per wave for the rows of the set a table chunk builds: k <= 256
-// rows of at most 8 words (4 waves x 8 KB per block, 4 blocks in 128 KB)
-constexpr int kRowsLds = 2048;
+// LDS words per wave for the rows of the set a table chunk builds (k rows
+// of dp words; a set that does not fit is read from global memory) or the
+// chunk groups of the pair it works on, and the block's slice of the
+// binomial table, C(x, t) for x < 256 and t <= 8, from which lanes unrank
+// their left subsets (subsets of up to 8 rows): 4 waves x 4 KB + 18 KB per
+// block, 4 blocks in 137.5 KB
+constexpr int kRowsLds = 1024;
+constexpr int kLdsBinomX = 256, kLdsBinomT = 9;
 // a saved table of C(k,b) entries is built only if C(k,b) <= C(k,top) /
 // kTableReuse, top = the expected last level of the code
 constexpr uint64_t kTableReuse = 1024;

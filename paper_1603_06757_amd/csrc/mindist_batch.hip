@@ -488,6 +488,9 @@ struct JobView {
     uint64_t n_items;
     const uint32_t *rows, *tab, *tab2, *cnt2;
     const GroupEntry *gr;
+    const GroupEntry *grl;        // the wave's LDS copy of gr, or nullptr
+    uint32_t U;                   // the code's least weight as this wave last saw it (only
+                                  // ever above the true one; lowered by the wave's own finds)
 };
 
 __device__ __forceinline__ void load_view(const BatchArgs &A, int c, int p, BatchJob *jb, JobView &v) {
@@ -522,39 +525,53 @@ __device__ __forceinline__ void load_view(const BatchArgs &A, int c, int p, Batc
     v.L_before = uni32(ldc(&jb->L_before));
     v.ngroups = (int)uni32(ldc(&jb->ngroups));
     v.gr = job_groups(jb);
+    v.grl = nullptr;
     v.gi = 0;
+    v.U = uni32(ld_rlx(&cs->U_found));
 }
 
 // One chunk of pair job v.p of code v.c.
 // Adds the chunk's evaluated combinations to `exec` and lowers `wmin_out`
 // to its least weight (without the offset).
 template <int D>
-__device__ __forceinline__ void pair_chunk(const BatchArgs &A, JobView &v, uint64_t ch, uint64_t &exec,
-                           uint32_t &wmin_out, bool &wrote) {
+__device__ __forceinline__ void pair_chunk(const BatchArgs &A, const uint64_t *lds_binom, JobView &v, uint64_t ch,
+                           uint64_t &exec, uint32_t &wmin_out, bool &wrote) {
     BatchCode *cs = &A.codes[v.c];
     BatchJob *jb = v.jb;
     const int lane = threadIdx.x & 63;
     // group of chunk ch: claims from one counter only grow; a move to
     // another counter may go back
-    if (ch < uni64(ldc(&v.gr[v.gi].chunk_base))) v.gi = 0;
-    while (v.gi + 1 < v.ngroups && uni64(ldc(&v.gr[v.gi + 1].chunk_base)) <= ch) ++v.gi;
+    // the job's chunk groups: from the wave's LDS copy (taken when it
+    // picked the job up), else by device-scope loads
+    auto gbase = [&](int i) {
+        return uni64(v.grl ? v.grl[i].chunk_base : ldc(&v.gr[i].chunk_base));
+    };
+    if (ch < gbase(v.gi)) v.gi = 0;
+    while (v.gi + 1 < v.ngroups && gbase(v.gi + 1) <= ch) ++v.gi;
     const GroupEntry *ge = v.gr + v.gi;
-    const uint64_t base = uni64(ldc(&ge->chunk_base)), n_rt = uni64(ldc(&ge->n_rt));
+    const GroupEntry *gl = v.grl ? v.grl + v.gi : nullptr;
+    const uint64_t base = gbase(v.gi), n_rt = uni64(gl ? gl->n_rt : ldc(&ge->n_rt));
     const uint64_t offc = ch - base;
     ChunkGeo g;
-    g.lt = uni64(ldc(&ge->lt_begin)) + offc / n_rt;
+    g.lt = uni64(gl ? gl->lt_begin : ldc(&ge->lt_begin)) + offc / n_rt;
     g.i_begin = uni32((uint32_t)(offc % n_rt) * v.T);
-    g.i_end = uni32(min(g.i_begin + v.T, uni32(ldc(&ge->nr_first))));
-    g.e_first = uni32(ldc(&ge->e));
+    g.i_end = uni32(min(g.i_begin + v.T, uni32(gl ? gl->nr_first : ldc(&ge->nr_first))));
+    g.e_first = uni32(gl ? gl->e : ldc(&ge->e));
     g.clip = false;
     // every address and size of the enumeration re-broadcast from lane 0 at
     // the point of use: the table reads stay scalar loads whatever the
     // scheduler loop around this call looks like to the compiler
     const int a = (int)uni32((uint32_t)v.a), b = (int)uni32((uint32_t)v.b);
+    // binomials from the block's LDS slice when the subsets are short
+    // enough (a dependent chain of global loads per element otherwise)
+    const int k_ = (int)uni32((uint32_t)v.k), b2_ = (int)uni32((uint32_t)v.b2);
+    const bool lds_b = k_ <= kLdsBinomX && a < kLdsBinomT && b < kLdsBinomT;
+    const uint64_t *bt = lds_b ? lds_binom : A.binom;
+    const int bs = lds_b ? kLdsBinomT : kBinomT;
     const ItemSrc src{(const uint32_t *)uni64((uint64_t)v.rows), (const uint32_t *)uni64((uint64_t)v.tab),
-                      nullptr, A.binom, A.binom + a, A.binom + b, kBinomT, kBinomT,
-                      uni64(v.n_items), (int)uni32((uint32_t)v.k), a, b, (int)uni32((uint32_t)v.b2),
-                      (const uint32_t *)uni64((uint64_t)v.tab2), (const uint32_t *)uni64((uint64_t)v.cnt2)};
+                      nullptr, bt, bt + a, bt + b, bs, bs,
+                      uni64(v.n_items), k_, a, b, b2_,
+                      (const uint32_t *)uni64((uint64_t)v.tab2), (const uint32_t *)uni64((uint64_t)v.cnt2), bs};
     constexpr int BI = batch_items(D);
     uint32_t L[BI][D], nr[BI], lmin, ws;
     uint64_t cnt;
@@ -565,10 +582,11 @@ __device__ __forceinline__ void pair_chunk(const BatchArgs &A, JobView &v, uint6
     if (wmin < wmin_out) wmin_out = wmin;
     if (wmin == kInf) return;
     const uint32_t val = wmin + v.offset;
-    if (val >= uni32(ld_rlx(&cs->U_found))) return;
+    if (val >= v.U) return;
     uint32_t old = 0;
     if (lane == 0) old = atomicMin(&cs->U_found, val);
     old = uni32((uint32_t)__shfl((int)old, 0));
+    v.U = min(old, val);
     if (old > val) {
         uint32_t hit_i, hit_i2 = 0;
         uint64_t hit_rho;
@@ -704,6 +722,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
     // one slice per wave for the rows of the set whose tables it builds
     __shared__ uint32_t s_rows[4 * kRowsLds];
     uint32_t *const my_rows = s_rows + (threadIdx.x >> 6) * kRowsLds;
+    __shared__ uint64_t s_binom[kLdsBinomX * kLdsBinomT];
+    for (int q = threadIdx.x; q < kLdsBinomX * kLdsBinomT; q += blockDim.x)
+        s_binom[q] = binom(A.binom, q / kLdsBinomT, q % kLdsBinomT);
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const uint32_t wave = uni32(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const int nc = A.n_codes;
@@ -761,14 +783,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
                     n_table += 1;
                 } else {
                     switch (v.D) {
-                        case 1: pair_chunk<1>(A, v, ch, pexec, pmin, wrote); break;
-                        case 2: pair_chunk<2>(A, v, ch, pexec, pmin, wrote); break;
-                        case 3: pair_chunk<3>(A, v, ch, pexec, pmin, wrote); break;
-                        case 4: pair_chunk<4>(A, v, ch, pexec, pmin, wrote); break;
-                        case 5: pair_chunk<5>(A, v, ch, pexec, pmin, wrote); break;
-                        case 6: pair_chunk<6>(A, v, ch, pexec, pmin, wrote); break;
-                        case 7: pair_chunk<7>(A, v, ch, pexec, pmin, wrote); break;
-                        default: pair_chunk<8>(A, v, ch, pexec, pmin, wrote); break;
+                        case 1: pair_chunk<1>(A, s_binom, v, ch, pexec, pmin, wrote); break;
+                        case 2: pair_chunk<2>(A, s_binom, v, ch, pexec, pmin, wrote); break;
+                        case 3: pair_chunk<3>(A, s_binom, v, ch, pexec, pmin, wrote); break;
+                        case 4: pair_chunk<4>(A, s_binom, v, ch, pexec, pmin, wrote); break;
+                        case 5: pair_chunk<5>(A, s_binom, v, ch, pexec, pmin, wrote); break;
+                        case 6: pair_chunk<6>(A, s_binom, v, ch, pexec, pmin, wrote); break;
+                        case 7: pair_chunk<7>(A, s_binom, v, ch, pexec, pmin, wrote); break;
+                        default: pair_chunk<8>(A, s_binom, v, ch, pexec, pmin, wrote); break;
                     }
                     tk_pair += wall_clock64() - t0;
                     n_pair += 1;
@@ -836,6 +858,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
         const uint32_t off = off0;
         BatchJob *jb = job_at(A, off);
         load_view(A, c, p, jb, v);
+        if (v.kind == 1 && (uint32_t)v.ngroups * sizeof(GroupEntry) <= kRowsLds * sizeof(uint32_t)) {
+            // the groups into this wave's LDS slice (one round of parallel
+            // device-scope loads instead of a dependent chain per chunk)
+            const uint64_t *src = reinterpret_cast<const uint64_t *>(v.gr);
+            uint64_t *dst = reinterpret_cast<uint64_t *>(my_rows);
+            const int words = v.ngroups * (int)(sizeof(GroupEntry) / sizeof(uint64_t));
+            __builtin_amdgcn_wave_barrier();
+            for (int q = lane; q < words; q += 64) dst[q] = ldc(src + q);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            v.grl = reinterpret_cast<const GroupEntry *>(my_rows);
+        }
         v.off = off;
         ctr = wave % v.nctr;
         dmask = 0;

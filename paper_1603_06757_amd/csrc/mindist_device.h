@@ -64,9 +64,10 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 
 // Colex unranking: the a-subset {x_1 < ... < x_a} of [0, hi) with
 // sum_t C(x_t, t) = rho.  Adds the rows of the subset into acc and returns
-// the largest element.
+// the largest element.  bt holds C(x, t) at bt[x * bs + t] for t <= a and
+// x < hi (zero for t > x): the full table (bs = kBinomT) or a slice of it.
 template <int D>
-__device__ __forceinline__ int unrank_add(const uint64_t *bt, const uint32_t *rows, int dp,
+__device__ __forceinline__ int unrank_add(const uint64_t *bt, int bs, const uint32_t *rows, int dp,
                                           uint64_t rho, int a, int hi, uint32_t (&acc)[D],
                                           bool reflect, int k) {
     int top = -1;
@@ -74,9 +75,9 @@ __device__ __forceinline__ int unrank_add(const uint64_t *bt, const uint32_t *ro
         int lo = t - 1, h = hi - 1;
         while (lo < h) {
             int mid = (lo + h + 1) >> 1;
-            if (binom(bt, mid, t) <= rho) lo = mid; else h = mid - 1;
+            if (bt[mid * bs + t] <= rho) lo = mid; else h = mid - 1;
         }
-        rho -= binom(bt, lo, t);
+        rho -= bt[lo * bs + t];
         hi = lo;
         if (top < 0) top = lo;
         const int r = reflect ? (k - 1 - lo) : lo;
@@ -196,7 +197,7 @@ struct ItemSrc {
     const uint32_t *rows;      // k x DP
     const uint32_t *table;     // right (outer) table
     const uint32_t *ltable;    // left table or nullptr (lanes unrank)
-    const uint64_t *binom;     // full binomial table (unranking)
+    const uint64_t *binom;     // binomials for the unranking: C(x, t) = binom[x * bs + t]
     const uint64_t *colA;      // C(x, a) = colA[x * sA]
     const uint64_t *colB;      // C(x, b) = colB[x * sB]
     int sA, sB;
@@ -205,6 +206,7 @@ struct ItemSrc {
     int b2;
     const uint32_t *table2;    // inner table
     const uint32_t *cnt2;      // inner entries of each outer entry
+    int bs;                    // row stride of binom (kBinomT for the full table)
 };
 
 // The part of the pair one chunk covers: left tile lt, right entries
@@ -249,7 +251,7 @@ __device__ __forceinline__ void run_chunk(const ItemSrc &s, ChunkGeo &g, uint32_
                 if (s.colA[(size_t)mid * s.sA] <= rc) e = mid; else hi = mid - 1;
             }
         } else {
-            e = unrank_add<D>(s.binom, s.rows, DP, rc, s.a, s.k, L[t], false, s.k);
+            e = unrank_add<D>(s.binom, s.bs, s.rows, DP, rc, s.a, s.k, L[t], false, s.k);
         }
         nr[t] = (uint32_t)s.colB[(size_t)(s.k - 1 - e) * s.sB];
         nr_lane_min = min(nr_lane_min, nr[t]);
@@ -392,7 +394,7 @@ __device__ __forceinline__ uint32_t setup_items(const ItemSrc &s, ChunkGeo &g, u
                 if (s.colA[(size_t)mid * s.sA] <= rc) e = mid; else hi = mid - 1;
             }
         } else {
-            e = unrank_add<D>(s.binom, s.rows, DP, rc, s.a, s.k, L[t], false, s.k);
+            e = unrank_add<D>(s.binom, s.bs, s.rows, DP, rc, s.a, s.k, L[t], false, s.k);
         }
         nr[t] = (uint32_t)s.colB[(size_t)(s.k - 1 - s.b2 - e) * s.sB];
         nr_lane_min = min(nr_lane_min, nr[t]);

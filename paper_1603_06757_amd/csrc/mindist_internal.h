@@ -47,6 +47,7 @@ struct GroupEntry {
     uint32_t nr_first;     // C(k-1-e, b): right entries of the tile's first item
     uint32_t e;
 };
+static_assert(sizeof(GroupEntry) == 32, "group entries are copied as four 64-bit words");
 
 // One wave's totals over the chunks it ran in a pair, written with plain
 // stores when the wave ends (no atomics on a shared line at the end of a

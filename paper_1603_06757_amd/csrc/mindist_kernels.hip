@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(GroupArgs ga) {
     }
     __syncthreads();
     const ItemSrc src{p.rows, p.table, p.ltable, p.binom, colA, colB, 1, 1,
-                      p.n_items, p.k, p.a, p.b, p.b2, p.table2, p.cnt2};
+                      p.n_items, p.k, p.a, p.b, p.b2, p.table2, p.cnt2, kBinomT};
     uint32_t rt_cur = 0;
     uint32_t moved = (uint64_t)p.waves >= p.total_chunks ? nq : 0u;
     bool first = true;

@@ -75,6 +75,9 @@ struct BatchSet {
 };
 
 constexpr int kJobCounters = 8;       // chunk dispensers per job (one cache line each)
+// waves that take part in a job: kPickersPerChunk per chunk, at least
+// kPickersMin (the rest pass it over without touching it)
+constexpr uint64_t kPickersPerChunk = 2, kPickersMin = 64;
 constexpr int kBatchDirectWorkers = 8;   // threads running a batch's codes routed to the single path
 
 // one job of a code; GroupEntry groups[ngroups] follow the struct.
@@ -148,7 +151,9 @@ struct BatchGlobal {
     // run); chunks of each kind
     uint64_t ticks_table, ticks_pair, ticks_flush;
     uint64_t chunks_table, chunks_pair;
-    uint64_t pad1[8];
+    uint32_t live0;               // codes to run when the launch starts (0: every slot)
+    uint32_t pad0;
+    uint64_t pad1[7];
 };
 
 struct BatchArgs {

@@ -175,9 +175,10 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
         // short, so it is not a few long tiles walked by a few waves while
         // the rest wait for its next pair.
         const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-        const uint32_t done = A.serving ? 0u : uni32(ld_rlx(&A.g->codes_done));
-        const uint64_t live = (uint64_t)A.n_codes > done ? (uint64_t)A.n_codes - done : 1ull;
-        const uint64_t share = A.serving ? 1ull : (waves / live > 0 ? waves / live : 1ull);
+        const uint32_t done = uni32(ld_rlx(&A.g->codes_done));
+        const uint32_t live0 = A.g->live0 ? A.g->live0 : (uint32_t)A.n_codes;
+        const uint64_t live = live0 > done ? (uint64_t)(live0 - done) : 1ull;
+        const uint64_t share = waves / live > 0 ? waves / live : 1ull;
         const uint64_t need = (uint64_t)(set.D > 3 ? set.D - 1 : 2) * share;
         constexpr int kCand = 10;                // T = 16 .. 8192
         uint64_t ch[kCand];
@@ -857,6 +858,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
         // before the pair that reads them was opened
         const uint32_t off = off0;
         BatchJob *jb = job_at(A, off);
+        {
+            // A job of few chunks is left to a subset of the waves (rotated
+            // by code): every wave that looks at a job claims from it and
+            // marks it drained with device-scope atomics on a few lines, so
+            // thousands of idle waves falling on a one-chunk pair had cost
+            // each pair of a code running alone ~0.35 ms
+            const uint64_t total = uni64(ldc(&jb->total_chunks));
+            const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+            const uint64_t want = total * kPickersPerChunk > kPickersMin ? total * kPickersPerChunk : kPickersMin;
+            if (want < waves) {
+                const uint32_t rank = (wave + (uint32_t)c * 0x9E3779B1u % waves) % waves;
+                if (rank >= want) {
+                    drained = off;
+                    cur = (c + 1) % nc;
+                    continue;
+                }
+            }
+        }
         load_view(A, c, p, jb, v);
         if (v.kind == 1 && (uint32_t)v.ngroups * sizeof(GroupEntry) <= kRowsLds * sizeof(uint32_t)) {
             // the groups into this wave's LDS slice (one round of parallel

@@ -276,6 +276,12 @@ void manager(mindist_server *S) {
         }
         // one epoch
         std::memset(S->h_g, 0, sizeof(BatchGlobal));
+        {
+            // the codes this launch starts with: the pair planner gives each
+            // its share of the waves
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->h_g->live0 = (uint32_t)std::max(1, S->resident);
+        }
         *reinterpret_cast<volatile uint32_t *>(S->h_stop) = 0;
         std::atomic_thread_fence(std::memory_order_seq_cst);
         BatchArgs a{};

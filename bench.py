@@ -608,6 +608,22 @@ def peak_leg(blocks_per_cu=(4, 8, 16)):
             "blocks_per_cu": best["blocks_per_cu"], "runs": out}
 
 
+def batch_stratum_leg(name: str, codes_total: int = 4096):
+    """One work stratum of the batch stream (by estimated codewords: light
+    < 1e9, medium < 2e10, heavy < 1e12) in one persistent launch, once (a
+    profiling target)."""
+    import paper_1603_06757_amd as md
+    from paper_1603_06757_amd.gen import batch_code
+    lo, hi = {"light": (0, 1e9), "medium": (1e9, 2e10), "heavy": (2e10, 1e12)}[name]
+    codes = [c for c in (batch_code(i) for i in range(codes_total)) if lo <= estimated_work(md, c[2], c[0], c[1]) < hi]
+    t0 = time.perf_counter()
+    res, info = md.run_batch(codes, pairs=False, direct_log2=-1, deadline_s=300)
+    dt = time.perf_counter() - t0
+    print(json.dumps({"batch_stratum": name, "codes": len(codes), "seconds": dt,
+                      "kernel_s": info["seconds_kernel"], "codewords": info["executed_total"],
+                      "errors": sum(1 for r in res if "error" in r)}), flush=True)
+
+
 def copy_probe(mib: int):
     """Plain device-to-device copies of a known size: the reference reading
     for the FETCH_SIZE / WRITE_SIZE counters (each copy reads and writes
@@ -630,6 +646,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--batch-stratum", choices=["light", "medium", "heavy"], default=None,
+                    help="only run one work stratum of the batch stream in one persistent launch and exit")
     ap.add_argument("--peak", action="store_true",
                     help="only run the register-only XOR+popcount ceiling kernel and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -659,6 +677,9 @@ def main():
         print("this benchmark runs on one GPU only (single-GPU build); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if a.batch_stratum:
+        batch_stratum_leg(a.batch_stratum)
+        return
     if a.peak:
         print(json.dumps({"peak_xorpop": peak_leg()}), flush=True)
         return

@@ -20,6 +20,21 @@
  *     exception crosses the ABI; mindist_last_error() gives a per-thread
  *     message for the last failure;
  *   - a context is not thread-safe; separate contexts are independent.
+ *
+ * Process-wide state besides the per-thread error text (all of it
+ * mutex-guarded, safe to use from several threads):
+ *   - caches of device memory, pinned host memory, streams and events that
+ *     contexts, batches and servers take from and return to, so that a run
+ *     allocates nothing after warm-up; they grow to the largest working set
+ *     seen and are released when the process ends;
+ *   - per device: the binomial table C(x, t) (x <= 512, t <= 64) and the
+ *     chunk-group tables of the pair shapes met so far (a few KB each), both
+ *     read-only once uploaded;
+ *   - per device, only once mindist_run_noalloc has run there: its static
+ *     buffer of MINDIST_NOALLOC_BYTES and a lock.
+ * The library assumes one HIP runtime in the process: a caller passing
+ * streams from another framework (PyTorch ships its own HIP runtime) must
+ * load that framework's runtime first, so the library binds to it.
  */
 #ifndef MINDIST_H
 #define MINDIST_H

@@ -77,7 +77,7 @@ struct BatchSet {
 constexpr int kJobCounters = 8;       // chunk dispensers per job (one cache line each)
 // waves that take part in a job: kPickersPerChunk per chunk, at least
 // kPickersMin (the rest pass it over without touching it)
-constexpr uint64_t kPickersPerChunk = 2, kPickersMin = 64;
+constexpr uint64_t kPickersPerChunk = 4, kPickersMin = 256;
 constexpr int kBatchDirectWorkers = 8;   // threads running a batch's codes routed to the single path
 
 // one job of a code; GroupEntry groups[ngroups] follow the struct.

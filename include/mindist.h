@@ -390,7 +390,8 @@ typedef struct mindist_batch_opts {
  * code and opens its next pair (one raise of L per Gamma_j, midpair exit).
  * Codes expected to be long (see direct_log2) run through the single-code
  * path instead, on worker threads after the launch.  G[i] points at code
- * i's matrix (layout as above; in the persistent launch n <= 256 and at most
+ * i's matrix (layout as above; in the persistent launch rows of at most 256
+ * carried bits (n <= 256 when there is a partial set), k <= 256 and at most
  * 32 information sets, other codes are routed to the single path unless
  * direct_log2 = -1); out has B caller-owned entries.  Results equal
  * mindist_run's with default options (d, visited pairs, counts, pair minima);

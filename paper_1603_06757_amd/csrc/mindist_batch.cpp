@@ -114,6 +114,11 @@ int prepare_code(const uint64_t *G, int n, int k, uint64_t table_cap, HostCode &
     if (e) return e;
     hc.n_gamma = (int)hc.P.sets.size();
     if (hc.n_gamma > kBatchMaxSets) return fail(MINDIST_E_LIMIT, "more than 32 information sets");
+    // the kernel's table runs read their binomials from an LDS slice of
+    // x < kLdsBinomX (with n <= 512, a code of more rows fits the layout
+    // only if every column outside its one information set is zero; the
+    // single path runs such codes)
+    if (k > kLdsBinomX) return fail(MINDIST_E_LIMIT, "more than 256 rows");
     const Binom &B = BN();
     hc.D.resize(hc.n_gamma);
     hc.dp.resize(hc.n_gamma);

@@ -30,7 +30,8 @@ constexpr int kBatchMaxD = 8;         // 32-bit words carried per row (n <= 256)
 constexpr int kBatchItemsMaxD4 = 4;
 constexpr int kBatchItemsWide = 2;
 MD_HD constexpr int batch_items(int D) { return D <= 4 ? kBatchItemsMaxD4 : kBatchItemsWide; }
-constexpr int kTableChunk = 4096;     // table entries per table-job chunk
+constexpr int kTableChunk = 4096;     // table entries per table-job chunk (at most)
+constexpr int kTableChunkMin = 256, kTableChunksWanted = 16;
 // LDS words per wave for the rows of the set a table chunk builds (k rows
 // of dp words; a set that does not fit is read from global memory) or the
 // chunk groups of the pair it works on, and the block's slice of the
@@ -90,7 +91,8 @@ constexpr int kBatchDirectWorkers = 8;   // threads running a batch's codes rout
 struct alignas(128) BatchJob {
     int32_t kind;                 // 0 = table job, 1 = enumeration pair
     int32_t j, w, a, b;
-    uint32_t T, L_before, offset, ngroups;
+    uint32_t T;                   // pair: right tile length; table job: entries per chunk
+    uint32_t L_before, offset, ngroups;
     int32_t b2;                   // inner subset size (0: two-level split)
     uint64_t n_items, total_chunks, count;
     uint32_t pair_min, exit_flag, L_after, U_after;

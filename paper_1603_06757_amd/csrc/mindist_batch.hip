@@ -302,7 +302,10 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
         jb->drained_mask = 0;
         cs->job[p] = off;
     }
-    __threadfence();     // the group entries of every lane, then the record
+    // the group entries of every lane and the record, then the job count:
+    // the lanes' stores complete, lane 0's release writes them back
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
     if (lane == 0) st_rel(&cs->njobs, p + 1);
 }
 
@@ -320,7 +323,13 @@ __device__ void open_tables(const BatchArgs &A, int c) {
         cs->t_open = wall_clock64();
         jb->kind = 0;
         jb->j = -1;
-        jb->total_chunks = (E + kTableChunk - 1) / kTableChunk;
+        // chunks of kTableChunk entries, halved (down to kTableChunkMin) while
+        // that leaves fewer than kTableChunksWanted of them: a short code's
+        // tables are a few thousand entries, built by as many waves
+        uint32_t tc = kTableChunk;
+        while (tc > kTableChunkMin && (E + tc - 1) / tc < kTableChunksWanted) tc >>= 1;
+        jb->T = tc;
+        jb->total_chunks = (E + tc - 1) / tc;
         jb->expected = jb->total_chunks;
         jb->t_open = wall_clock64();
         jb->t_close = 0;
@@ -346,11 +355,17 @@ __device__ void open_tables(const BatchArgs &A, int c) {
 // kk = k - shift) also stores C(shift + min z, shift), the inner count.
 // BL is a template parameter so that the subset stays in registers; the run
 // is not inlined so that it does not set the persistent kernel's register
-// budget.
+// budget.  The binomials come from the block's LDS slice, C(x, t) at
+// bt[x * kLdsBinomT + t] (x < 256, t <= 8 covers every run of a code of the
+// batch layout: k <= 256, BL and the shift <= kBatchMaxB), so that the first
+// entry's unranking and an outer table's inner counts are not chains of
+// global loads.
+typedef __attribute__((address_space(3))) const uint64_t LdsU64;
 template <int BL>
-__device__ __noinline__ void table_run(const uint64_t *bt, const uint32_t *rows, int dp, int D,
+__device__ __noinline__ void table_run(LdsU64 *bt, const uint32_t *rows, int dp, int D,
                                           int kk, int shift, uint32_t *out, uint32_t *cnt,
                                           uint64_t i, uint64_t n) {
+    auto C = [&](int x, int t) { return (x < 0 || t < 0 || t > x) ? 0ull : bt[x * kLdsBinomT + t]; };
     int z[BL + 1];
     uint32_t acc[kBatchMaxD];
 #pragma unroll
@@ -369,9 +384,9 @@ __device__ __noinline__ void table_run(const uint64_t *bt, const uint32_t *rows,
             int l = t - 1, h = top - 1;
             while (l < h) {
                 const int mid = (l + h + 1) >> 1;
-                if (binom(bt, mid, t) <= r) l = mid; else h = mid - 1;
+                if (C(mid, t) <= r) l = mid; else h = mid - 1;
             }
-            r -= binom(bt, l, t);
+            r -= C(l, t);
             top = l;
             z[t - 1] = l;
             add_row(l);
@@ -391,7 +406,7 @@ __device__ __noinline__ void table_run(const uint64_t *bt, const uint32_t *rows,
             o[0] = acc[0];
         }
         if (BL == 0) continue;
-        if (cnt) cnt[i] = (uint32_t)binom(bt, shift + z[0], shift);
+        if (cnt) cnt[i] = (uint32_t)C(shift + z[0], shift);
         if (e + 1 == n) break;
         // colex successor: the lowest position that can move up by one
         int t0 = BL - 1;
@@ -422,57 +437,61 @@ __device__ __forceinline__ int table_of(const BatchCode *cs, uint64_t x) {
     return lo;
 }
 
-// Chunk ch of the table job: entries [ch*4096, ...) of the flattened list
-// of the code's tables; lane l fills 64 consecutive entries.  When the whole
-// chunk lies in one set's tables (the usual case: a set's tables are
-// contiguous), the wave first copies that set's rows into its own LDS slice
-// (k x dp <= kRowsLds words), so that the successor walk's row reads -- a
-// few dependent reads per entry -- come from LDS instead of L2.
-__device__ void table_chunk(const BatchArgs &A, BatchCode *cs, uint64_t ch, uint32_t *lds) {
+// Chunk ch of the table job: entries [ch*tc, ...) of the flattened list
+// of the code's tables, one table at a time: the chunk's part of each table
+// is split into 64 consecutive runs, one per lane, so that every lane runs
+// the same level (a chunk of a short code spans many small tables; lanes
+// spread over them would run each level's walk one after another).  The
+// wave copies the rows of the set it is in into its own LDS slice (k x dp
+// <= kRowsLds words), so that the successor walk's row reads -- a few
+// dependent reads per entry -- come from LDS instead of L2.
+__device__ void table_chunk(const BatchArgs &A, BatchCode *cs, uint64_t ch, uint32_t tc, uint32_t *lds,
+                            LdsU64 *bt) {
     const int lane = threadIdx.x & 63;
-    const uint64_t E = cs->tab_off[kBatchTabs];
-    const int k = cs->k;
-    const uint64_t first = ch * kTableChunk;
-    const uint64_t last = (first + kTableChunk < E ? first + kTableChunk : E) - 1;
-    const int j0 = table_of(cs, first) / kTabsPerSet;
-    const bool staged = j0 == table_of(cs, last) / kTabsPerSet &&
-                        k * cs->sets[j0].dp <= kRowsLds;
-    if (staged) {
-        const uint32_t *src = cs->sets[j0].rows;
-        const int words = k * cs->sets[j0].dp;
-        __builtin_amdgcn_wave_barrier();
-        for (int w = lane; w < words; w += 64) lds[w] = src[w];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    }
-    uint64_t idx = first + (uint64_t)lane * (kTableChunk / 64);
-    uint64_t left = kTableChunk / 64;
-    while (left > 0 && idx < E) {
-        const int lo = table_of(cs, idx);
-        const int j = lo / kTabsPerSet, r0 = lo % kTabsPerSet;
+    const uint64_t E = uni64(cs->tab_off[kBatchTabs]);
+    const int k = (int)uni32((uint32_t)cs->k);
+    const uint64_t first = ch * tc;
+    const uint64_t end = first + tc < E ? first + tc : E;
+    int staged = -1;                     // the set whose rows the LDS slice holds
+    for (int t = table_of(cs, first); t < kBatchTabs; ++t) {
+        const uint64_t lo = uni64(cs->tab_off[t]), hi = uni64(cs->tab_off[t + 1]);
+        if (lo >= end) break;
+        const uint64_t x0 = lo > first ? lo : first, x1 = hi < end ? hi : end;
+        if (x1 <= x0) continue;          // an empty table
+        const int j = t / kTabsPerSet, r0 = t % kTabsPerSet;
         const BatchSet &set = cs->sets[j];
+        const int dp = (int)uni32((uint32_t)set.dp), D = (int)uni32((uint32_t)set.D);
+        if (j != staged && k * dp <= kRowsLds) {
+            const uint32_t *src = (const uint32_t *)uni64((uint64_t)set.rows);
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            for (int w = lane; w < k * dp; w += 64) lds[w] = src[w];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            staged = j;
+        }
         const bool outer = r0 > kBatchMaxB;
         const int b = outer ? r0 - (kBatchMaxB + 1) : r0;
-        const int shift = outer ? set.bcap : 0;   // outer: rows [0, k-bcap)
-        const uint64_t size = cs->tab_off[lo + 1] - cs->tab_off[lo];
-        const uint64_t i = idx - cs->tab_off[lo];
-        const uint64_t n = min(left, size - i);
-        uint32_t *out = outer ? set.otab[b] : set.rtab[b];
-        uint32_t *cnt = outer ? set.ocnt[b] : nullptr;
+        const int shift = outer ? (int)uni32((uint32_t)set.bcap) : 0;   // outer: rows [0, k-bcap)
+        uint32_t *out = (uint32_t *)uni64((uint64_t)(outer ? set.otab[b] : set.rtab[b]));
+        uint32_t *cnt = outer ? (uint32_t *)uni64((uint64_t)set.ocnt[b]) : nullptr;
         const int kk = k - shift;
-        const uint32_t *rows = staged ? lds : set.rows;   // staged: j == j0 for every entry
-        switch (b) {
-            case 0: table_run<0>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
-            case 1: table_run<1>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
-            case 2: table_run<2>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
-            case 3: table_run<3>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
-            case 4: table_run<4>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
-            case 5: table_run<5>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
-            default: table_run<6>(A.binom, rows, set.dp, set.D, kk, shift, out, cnt, i, n); break;
+        const uint32_t *rows = staged == j ? lds : (const uint32_t *)uni64((uint64_t)set.rows);
+        const uint64_t len = x1 - x0, per = (len + 63) / 64, mine = (uint64_t)lane * per;
+        const uint64_t n = mine < len ? (len - mine < per ? len - mine : per) : 0;
+        const uint64_t i = x0 - lo + mine;
+        if (n > 0) {
+            switch (b) {
+                case 0: table_run<0>(bt, rows, dp, D, kk, shift, out, cnt, i, n); break;
+                case 1: table_run<1>(bt, rows, dp, D, kk, shift, out, cnt, i, n); break;
+                case 2: table_run<2>(bt, rows, dp, D, kk, shift, out, cnt, i, n); break;
+                case 3: table_run<3>(bt, rows, dp, D, kk, shift, out, cnt, i, n); break;
+                case 4: table_run<4>(bt, rows, dp, D, kk, shift, out, cnt, i, n); break;
+                case 5: table_run<5>(bt, rows, dp, D, kk, shift, out, cnt, i, n); break;
+                default: table_run<6>(bt, rows, dp, D, kk, shift, out, cnt, i, n); break;
+            }
         }
-        left -= n;
-        idx += n;
     }
 }
 
@@ -503,6 +522,7 @@ __device__ __forceinline__ void load_view(const BatchArgs &A, int c, int p, Batc
     v.total = uni64(ldc(&jb->total_chunks));
     v.nctr = uni32(ldc(&jb->nctr));
     v.offset = 0;
+    v.T = uni32(ldc(&jb->T));      // table job: entries per chunk
     if (v.kind == 0) return;
     v.j = (int)uni32((uint32_t)ldc(&jb->j));
     v.a = (int)uni32((uint32_t)ldc(&jb->a));
@@ -521,7 +541,6 @@ __device__ __forceinline__ void load_view(const BatchArgs &A, int c, int p, Batc
         v.cnt2 = v.tab2 = nullptr;
     }
     v.n_items = uni64(ldc(&jb->n_items));
-    v.T = uni32(ldc(&jb->T));
     v.offset = uni32(ldc(&jb->offset));
     v.L_before = uni32(ldc(&jb->L_before));
     v.ngroups = (int)uni32(ldc(&jb->ngroups));
@@ -619,11 +638,12 @@ __device__ __forceinline__ void pair_chunk(const BatchArgs &A, const uint64_t *l
     }
 }
 
-// Job p of code c has completed: Algorithm 1's control for that code.
+// Job p of code c has completed: Algorithm 1's control for that code.  The
+// caller's acquire (after the completion count) makes every chunk's
+// results visible; the counters are read coherently.
 __device__ void advance(const BatchArgs &A, int c, int p, BatchJob *jb) {
     BatchCode *cs = &A.codes[c];
     if ((threadIdx.x & 63) == 0) jb->t_close = wall_clock64();
-    __threadfence();
     const int k = cs->k, n = cs->n, ng = cs->n_gamma;
     const uint32_t singleton = (uint32_t)(n - k + 1);
     if (jb->kind == 0) {           // tables built: first pair, L = 1 (Algorithm 1)
@@ -631,9 +651,9 @@ __device__ void advance(const BatchArgs &A, int c, int p, BatchJob *jb) {
         return;
     }
     const int j = jb->j, w = jb->w;
-    const uint32_t Uf = ld_acq(&cs->U_found);
-    const uint64_t executed = ld_acq(&jb->executed);
-    const bool cut = ld_acq(&jb->exit_flag) && executed < jb->count;
+    const uint32_t Uf = uni32(ldc(&cs->U_found));
+    const uint64_t executed = uni64(ldc(&jb->executed));
+    const bool cut = uni32(ldc(&jb->exit_flag)) && executed < jb->count;
     const uint32_t L = cut ? jb->L_before
                            : (uint32_t)bound_after_dev(k, cs->m_full, cs->k_m, ng, j, w);
     const uint32_t U = min(Uf, singleton);
@@ -715,6 +735,19 @@ __device__ __noinline__ void flush(const BatchArgs &A, int c, int p, BatchJob *j
     }
 }
 
+// A wave that found nothing to do sleeps before it looks again, twice as
+// long after each empty look, from ~0.85 us up to ~54 us (s_sleep 32 is
+// 2048 clocks).  Thousands of idle waves re-reading the few lines of the
+// code descriptors every ~0.1 us had queued the working waves' own memory
+// accesses behind them: a chunk of a short pair of a code running alone
+// took ~37 us, ~14 us with the back-off; an eligible picker among hundreds
+// still wakes within a fraction of a microsecond.
+__device__ __forceinline__ void idle_backoff(uint32_t &idle) {
+    const uint32_t n = 1u << (idle < 6u ? idle : 6u);
+    for (uint32_t q = 0; q < n; ++q) __builtin_amdgcn_s_sleep(32);
+    if (idle < 6u) ++idle;
+}
+
 }  // namespace
 
 // At most 128 VGPRs (4 waves per SIMD, 4 blocks of 256 per CU): the few
@@ -742,6 +775,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
     uint32_t ctr = 0, dmask = 0, pmin = kInf, visit = 0;
     uint64_t pdone = 0, pexec = 0;
     bool wrote = false;            // plain stores since the last flush (tables, a witness slot)
+    uint32_t idle = 0;             // empty looks since this wave last took up a job
     // profile: ticks in table chunks, enumeration chunks and flushes
     uint64_t tk_table = 0, tk_pair = 0, tk_flush = 0, n_table = 0, n_pair = 0;
     for (;;) {
@@ -778,7 +812,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
             if (ch != ~0ull) {
                 const uint64_t t0 = wall_clock64();
                 if (v.kind == 0) {
-                    table_chunk(A, &A.codes[v.c], ch, my_rows);
+                    table_chunk(A, &A.codes[v.c], ch, v.T, my_rows, (LdsU64 *)s_binom);
                     wrote = true;
                     tk_table += wall_clock64() - t0;
                     n_table += 1;
@@ -825,7 +859,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
             __ballot(s == kSlotPending || (s == kSlotActive && pj > 0 && pd < pj));
         if (!live) {
             cur = (cur + 64) % nc;
-            __builtin_amdgcn_s_sleep(4);
+            idle_backoff(idle);
             continue;
         }
         const int pick = __builtin_ctzll(live);
@@ -849,7 +883,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
                                                       __HIP_MEMORY_SCOPE_AGENT));
         if (off0 == drained) {     // still waiting for its last chunks
             cur = (c + 1) % nc;
-            __builtin_amdgcn_s_sleep(2);
+            idle_backoff(idle);
             continue;
         }
         // no acquire fence: the job's record and groups are read with
@@ -897,6 +931,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
         pmin = kInf;
         visit = 0;
         have = true;
+        idle = 0;
         cur = c;
     }
 }

@@ -452,7 +452,8 @@ def serving_leg(rate: float, seconds: float, cap: float, max_requests: int = 400
             "offered_load": rate * mean_work / rate_codewords if rate_codewords else None,
             "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
             "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "by_work": per, "epochs": st["epochs"], "kernel_s": st["seconds_kernel"]}
+            "by_work": per, "epochs": st["epochs"], "admitted_live": st["admitted_live"],
+            "kernel_s": st["seconds_kernel"]}
 
 
 SERVING_RATES = ((10, 8.0), (30, 4.0), (100, 2.5), (300, 1.5), (1000, 1.0))

@@ -436,8 +436,9 @@ typedef struct mindist_server_opts {
                                  saved tables and witness slots in a pool allocated at
                                  creation.  Submit fails with MINDIST_E_NOMEM for a code
                                  whose share exceeds it */
-    double  epoch_min_ms;     /* least running time of a launch before waiting codes are
-                                 admitted (0 = 0.5 ms) */
+    double  epoch_min_ms;     /* engine 1: least running time of a launch before it is
+                                 stopped so that waiting codes that cannot be admitted
+                                 into it come in (0 = 0.5 ms) */
     int32_t table_kib;        /* cap on one saved table in KiB (0 = the single-code path's
                                  1 GiB for engine 0, 65536 for engine 1) */
     int32_t jobs_per_code;    /* job records per slot (0 = 96); a code needing more ends
@@ -447,7 +448,7 @@ typedef struct mindist_server_opts {
                                  (mindist_create / run / destroy) on its own stream in one of
                                  max_active worker threads; the device runs the kernels of
                                  the codes in flight side by side.  1: the persistent
-                                 multi-code kernel in epochs (epoch_min_ms, jobs_per_code,
+                                 multi-code kernel, admitting codes while it runs (epoch_min_ms, jobs_per_code,
                                  blocks_per_cu and chunks_per_visit apply to this engine
                                  only) */
 } mindist_server_opts;
@@ -465,11 +466,17 @@ typedef struct mindist_server_result {
 
 typedef struct mindist_server_stats {
     uint64_t submitted, admitted, completed;
-    uint64_t epochs;          /* launches of the persistent kernel (engine 1) */
+    uint64_t epochs;          /* launches of the persistent kernel (engine 1): a launch runs
+                                 while codes are resident and admits arriving ones; it is
+                                 stopped only when a waiting code needs a relaunch to come in
+                                 (every free slot already used in it, pool ranges freed in
+                                 it, rows beyond 32 KiB), and after 10 s */
     double   seconds_kernel;  /* engine 1: summed launch time (HIP events); engine 0: summed
                                  enumeration kernel time of the finished codes (device clock) */
     int32_t  resident;        /* codes on the device (engine 1) or being run (engine 0) now */
     int32_t  pending;         /* codes waiting for admission now */
+    uint64_t admitted_live;   /* engine 1: codes admitted into a running launch (the rest of
+                                 `admitted` were written between launches) */
 } mindist_server_stats;
 
 /* Start a server on the current HIP device (opts may be NULL).  *out is

@@ -118,7 +118,7 @@ class ServerResult(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
                 ("epochs", C.c_uint64), ("seconds_kernel", C.c_double),
-                ("resident", C.c_int32), ("pending", C.c_int32)]
+                ("resident", C.c_int32), ("pending", C.c_int32), ("admitted_live", C.c_uint64)]
 
 
 _lib = None

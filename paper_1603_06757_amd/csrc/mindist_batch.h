@@ -112,13 +112,20 @@ struct alignas(128) BatchJob {
     } claim[kJobCounters];
 };
 
-struct alignas(16) BatchCode {
-    int32_t n, k, m_full, k_m, n_gamma, W;
+// A slot's descriptor.  The first 128-byte line holds only what waves read
+// and write with device-scope atomics while a launch runs (every wave
+// looking for work reads it); the rest is written once, before the status
+// leaves kSlotEmpty, and read with plain loads.  A descriptor is a whole
+// number of lines, so that no line of a slot admitted while a launch runs
+// can already sit in some XCD's L2 (slots are not reused within a launch).
+struct alignas(128) BatchCode {
     int32_t status;               // kSlot* or a negative error
     int32_t njobs;                // jobs opened (the open one is njobs-1)
     int32_t drained;              // njobs value whose open job was found fully
                                   // claimed (a hint for waves looking for work)
     uint32_t U_found;             // least weight found (kInf = none)
+    uint32_t line0_pad[28];
+    int32_t n, k, m_full, k_m, n_gamma, W;
     uint32_t tile_cap;            // largest right tile for this code
     uint32_t L_final, U_final;
     uint64_t seq;                 // submission sequence number (server)
@@ -143,6 +150,17 @@ struct ServeMirror {
     Slot witness;
 };
 
+// Serving: a code the host admits while the launch runs -- its descriptor
+// and packed rows, in pinned host memory, copied to the device by a polling
+// wave (rows to rows_dst, a device address in the code's pool range).
+constexpr size_t kInboxRowsBytes = 32u << 10;
+struct ServeInbox {
+    BatchCode code;
+    uint64_t rows_dst;
+    uint32_t rows_bytes, pad;
+    unsigned char rows[kInboxRowsBytes];
+};
+
 struct BatchGlobal {
     uint32_t codes_done;          // batch: codes finished (done or error)
     uint32_t stop;                // serving: the host's stop request, mirrored on the device
@@ -153,8 +171,10 @@ struct BatchGlobal {
     // run); chunks of each kind
     uint64_t ticks_table, ticks_pair, ticks_flush;
     uint64_t chunks_table, chunks_pair;
-    uint32_t live0;               // codes to run when the launch starts (0: every slot)
-    uint32_t pad0;
+    uint32_t live0;               // codes to run when the launch starts (0: every slot), plus
+                                  // those admitted since
+    uint32_t admit_done;          // serving: ring entries copied to the device this launch
+    uint32_t admit_lock;          // serving: held by the wave copying them
     uint64_t pad1[7];
 };
 
@@ -166,6 +186,14 @@ struct BatchArgs {
     uint32_t *host_done;          // serving: per slot completion word in pinned host memory
     ServeMirror *mirror;          // serving: per slot result mirror in pinned host memory
     const uint32_t *host_stop;    // serving: set by the host to end the launch
+    // serving: codes admitted while the launch runs (pinned host memory):
+    // inbox entries per slot, the ring of their slot indices (n_codes
+    // entries), its count (written by the host) and the count copied so far
+    // (written back by the device); null: no admission during the launch
+    const ServeInbox *inbox;
+    const uint32_t *admit_ring;
+    const uint32_t *admit_count;
+    uint32_t *admit_ack;
     int32_t n_codes;              // code slots
     int32_t serving;              // 0: end when every code is done; 1: end on host_stop
     uint32_t tile_min;            // right tile length bounds

@@ -161,25 +161,26 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
     const uint64_t TB = 64ull * batch_items(set.D);
     const uint64_t n_items = binom(A.binom, k - b - b2, a);
     const uint64_t tiles = (n_items + TB - 1) / TB;
+    // The waves this pair can expect are the launch's waves over the codes
+    // still running (the chunks-per-visit quantum spreads them); it should
+    // leave each of them max(2, D-1) chunks.
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint32_t done = uni32(ld_rlx(&A.g->codes_done));
+    const uint32_t l0 = uni32(ld_rlx(&A.g->live0));
+    const uint32_t live0 = l0 ? l0 : (uint32_t)A.n_codes;
+    const uint64_t live = live0 > done ? (uint64_t)(live0 - done) : 1ull;
+    const uint64_t share = waves / live > 0 ? waves / live : 1ull;
+    const uint64_t need = (uint64_t)(set.D > 3 ? set.D - 1 : 2) * share;
     uint32_t T;
     if (b2 == 0) {
         // Right tile from the exact chunk count at each length 16 << t: a
         // left tile whose first subset has largest element e meets
-        // C(k-1-e, b) right entries.  The waves this pair can expect are the
-        // launch's waves over the codes still running (the chunks-per-visit
-        // quantum spreads them), and it should leave each of them max(2,
-        // D-1) chunks: from the lower configured bound, longer while the
-        // chunks allow (short codes' per-chunk set-up dominates below that
-        // bound; long pairs gain from long tiles).  Few live codes (a
-        // batch's heavy tail): shorter than the bound where the pair is
-        // short, so it is not a few long tiles walked by a few waves while
-        // the rest wait for its next pair.
-        const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-        const uint32_t done = uni32(ld_rlx(&A.g->codes_done));
-        const uint32_t live0 = A.g->live0 ? A.g->live0 : (uint32_t)A.n_codes;
-        const uint64_t live = live0 > done ? (uint64_t)(live0 - done) : 1ull;
-        const uint64_t share = waves / live > 0 ? waves / live : 1ull;
-        const uint64_t need = (uint64_t)(set.D > 3 ? set.D - 1 : 2) * share;
+        // C(k-1-e, b) right entries.  From the lower configured bound, longer
+        // while the chunks allow (short codes' per-chunk set-up dominates
+        // below that bound; long pairs gain from long tiles).  Few live
+        // codes (a batch's heavy tail, a code served alone): shorter than
+        // the bound where the pair is short, so it is not a few long tiles
+        // walked by a few waves while the rest wait for its next pair.
         constexpr int kCand = 10;                // T = 16 .. 8192
         uint64_t ch[kCand];
         for (int t = 0; t < kCand; ++t) ch[t] = 0;
@@ -213,18 +214,28 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
             while (T > 16 && chunks_at(T) < need) T >>= 1;
         }
     } else {
-        // outer tile: about 256K codewords per chunk
+        // outer tile: about 256K codewords per chunk; with at most 4 live
+        // codes, the pair's share per expected chunk, down to 4K (a pair of
+        // 10^7 codewords would otherwise be 40 chunks: 40 waves, each alone
+        // on its CU with nothing to hide its loads behind, ~3 ms instead of
+        // ~0.3-0.6 ms; with more live codes the smaller chunks cost more
+        // than they spread)
         const int e = (k - b - b2) * a / (a + 1);
         const uint64_t outer = binom(A.binom, k - 1 - b2 - e, b);
         const uint64_t both = binom(A.binom, k - 1 - e, b + b2);
         const double n2 = outer ? (double)both / (double)outer : 1.0;
-        const double want = 262144.0 / ((double)TB * (n2 > 1 ? n2 : 1));
+        double target = 262144.0;
+        if (share >= waves / 4) {
+            const double fair = (double)binom(A.binom, k, w) / (double)need;
+            if (fair < target) target = fair > 4096.0 ? fair : 4096.0;
+        }
+        const double want = target / ((double)TB * (n2 > 1 ? n2 : 1));
         T = 1;
         while (T < 1024 && T * 2 <= want) T <<= 1;
     }
     const uint32_t off = alloc_job(A, c, k + 2);
     if (off == 0xFFFFFFFFu) {
-        finish_code(A, c, -5 /* MINDIST_E_LIMIT */, L_before, min(cs->U_found, (uint32_t)(cs->n - k + 1)));
+        finish_code(A, c, -5 /* MINDIST_E_LIMIT */, L_before, min(uni32(ldc(&cs->U_found)), (uint32_t)(cs->n - k + 1)));
         return;
     }
     BatchJob *jb = job_at(A, off);
@@ -271,7 +282,7 @@ __device__ void open_pair(const BatchArgs &A, int c, int p, int j, int w, uint32
         ng += uni32((uint32_t)__shfl((int)inc_n, 63));
     }
     if (chunk_base == 0) {        // cannot happen for w <= k; never leave a job nobody can close
-        finish_code(A, c, -4 /* MINDIST_E_HIP */, L_before, min(cs->U_found, (uint32_t)(cs->n - k + 1)));
+        finish_code(A, c, -4 /* MINDIST_E_HIP */, L_before, min(uni32(ldc(&cs->U_found)), (uint32_t)(cs->n - k + 1)));
         return;
     }
     if (lane == 0) {
@@ -735,6 +746,57 @@ __device__ __noinline__ void flush(const BatchArgs &A, int c, int p, BatchJob *j
     }
 }
 
+// Serving: copy the codes the host admitted while this launch runs to the
+// device.  The host writes a code's descriptor and packed rows into its
+// slot's inbox entry (pinned host memory), the slot into the ring, then the
+// count; the wave holding the admission lock copies each entry (rows into
+// the code's pool range, the descriptor from its second line on), clears
+// the first line's state and turns the slot PENDING after a release, so a
+// wave that sees the status reads the rest from memory.  A slot and a pool
+// range are used at most once per launch: no wave can still hold anything
+// of what they held before, and no XCD's L2 a stale copy of them.
+__device__ __noinline__ void admit_codes(const BatchArgs &A) {
+    const int lane = threadIdx.x & 63;
+    uint32_t got = 0;
+    if (lane == 0) got = atomicCAS(&A.g->admit_lock, 0u, 1u) == 0u ? 1u : 0u;
+    if (!uni32((uint32_t)__shfl((int)got, 0))) return;
+    // the entries were written before the count
+    const uint32_t pub = uni32(__hip_atomic_load(A.admit_count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
+    uint32_t done = uni32(ld_rlx(&A.g->admit_done));
+    constexpr int kLine0 = 128 / 16;
+    for (; done < pub; ++done) {
+        const uint32_t s = uni32(__hip_atomic_load(A.admit_ring + done % (uint32_t)A.n_codes,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+        if (s >= (uint32_t)A.n_codes) continue;          // never written so by the host
+        const ServeInbox *in = A.inbox + s;
+        BatchCode *cs = A.codes + s;
+        const uint4 *src = reinterpret_cast<const uint4 *>(&in->code);
+        uint4 *dst = reinterpret_cast<uint4 *>(cs);
+        for (int q = kLine0 + lane; q < (int)(sizeof(BatchCode) / 16); q += 64) dst[q] = src[q];
+        uint4 *rd = reinterpret_cast<uint4 *>(uni64(in->rows_dst));
+        const uint32_t rq = min(uni32(in->rows_bytes), (uint32_t)kInboxRowsBytes) / 16;
+        const uint4 *rs = reinterpret_cast<const uint4 *>(in->rows);
+        for (uint32_t q = lane; q < rq; q += 64) rd[q] = rs[q];
+        if (lane == 0) {
+            __hip_atomic_store(&cs->njobs, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&cs->drained, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&cs->U_found, kInf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // every lane's stores complete, lane 0's release writes them back
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            atomicAdd(&A.g->live0, 1u);
+            st_rel(&cs->status, (int32_t)kSlotPending);
+        }
+    }
+    if (lane == 0) {
+        __hip_atomic_store(&A.g->admit_done, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(A.admit_ack, pub, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&A.g->admit_lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // A wave that found nothing to do sleeps before it looks again, twice as
 // long after each empty look, from ~0.85 us up to ~54 us (s_sleep 32 is
 // 2048 clocks).  Thousands of idle waves re-reading the few lines of the
@@ -793,6 +855,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
             stop = stop || uni32(ld_rlx(&A.g->stop)) != 0;
         } else if (uni32(ld_rlx(&A.g->codes_done)) >= (uint32_t)nc) {
             stop = true;
+        }
+        if (!stop && A.admit_count && (wave & 63) == 0) {
+            // one wave in 64 watches for codes admitted while the launch runs
+            const uint32_t pub = uni32(__hip_atomic_load(A.admit_count, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_SYSTEM));
+            if (pub != uni32(ld_rlx(&A.g->admit_done))) admit_codes(A);
         }
         if (stop) {
             // every chunk this wave claimed is complete: count it before leaving

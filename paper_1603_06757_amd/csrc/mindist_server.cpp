@@ -9,15 +9,23 @@
 // the compute units another code's short pairs leave idle, and a code's
 // latency is that of the single-code path.
 //
-// Engine 1: the persistent multi-code kernel runs in "epochs": one launch keeps every
-// resident code moving (pair after pair, Algorithm 1's control on the
-// device) until the manager thread asks it to stop because codes are
-// waiting and room has freed up.  Waves finish the chunk they hold and add
-// it to its job before leaving, so a stopped code resumes exactly where it
-// was in the next launch.  Between launches the manager writes the admitted
-// codes into free slots (descriptor, packed rows; tables are built on the
-// device by each code's first job) and relaunches over old and new codes
-// together.  While a launch runs, a finished code's last wave copies what the
+// Engine 1: the persistent multi-code kernel keeps every resident code
+// moving (pair after pair, Algorithm 1's control on the device).  A code
+// that arrives while it runs is admitted into it: the manager thread writes
+// the code's descriptor and packed rows into the slot's inbox entry in
+// pinned host memory and publishes the slot in a ring; one of the kernel's
+// polling waves copies it to the device and makes the slot pending, and the
+// waves take it up like any other (tables are built on the device by each
+// code's first job).  A slot and a pool range serve at most one code per
+// launch -- a wave may still touch a finished code's records for a moment
+// -- so freed ones return at the next launch.  The manager stops the launch
+// ("an epoch") only when a waiting code cannot be admitted into it but would
+// be after a relaunch (every free slot already used in this launch, pool
+// ranges waiting to return, rows too large for an inbox entry), when no code
+// is left, or after 10 s.  Waves finish the chunk they hold and add it to
+// its job before leaving, so a stopped code resumes exactly where it was in
+// the next launch; codes admitted between launches are written by plain
+// copies.  While a launch runs, a finished code's last wave copies what the
 // host needs (descriptor, job records, witness slot) into pinned host memory
 // and then sets the code's completion word there; the manager decodes it
 // without stopping the others and without any device copy.
@@ -103,6 +111,7 @@ struct Resident {
     size_t off = 0;              // in the device pool
     uint64_t seq = 0;
     bool fresh = false;          // admitted, not yet written to the device
+    bool used = false;           // held a code during the current launch
 };
 
 }  // namespace
@@ -133,6 +142,12 @@ struct mindist_server {
     uint32_t *h_done = nullptr, *h_stop = nullptr;   // pinned, coherent
     uint32_t *dv_done = nullptr, *dv_stop = nullptr; // their device addresses
     md::ServeMirror *h_mirror = nullptr, *dv_mirror = nullptr;   // finished codes' records
+    md::ServeInbox *h_inbox = nullptr, *dv_inbox = nullptr;      // codes admitted during a launch
+    uint32_t *h_ring = nullptr, *dv_ring = nullptr;              // their slots, in order
+    uint32_t *h_admit = nullptr, *dv_admit = nullptr;            // [0]: ring count, [32]: copied
+    uint32_t published = 0;                 // ring entries of the current launch
+    bool running = false;                   // a launch is in flight (manager thread)
+    std::vector<std::pair<size_t, size_t>> retired;   // pool ranges freed during the launch
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     uint64_t seg_units = 0;                 // job arena units per slot
@@ -186,7 +201,8 @@ void collect(mindist_server *S, int s, std::vector<unsigned char> &arena_host,
     if (status != MINDIST_OK && res->result.d >= 0) res->result.d = status;
     res->t_done = S->clock();
     std::lock_guard<std::mutex> lk(S->mu);
-    S->pool.release(r.off, r.req->bytes);
+    if (S->running) S->retired.emplace_back(r.off, r.req->bytes);   // returns at the next launch
+    else S->pool.release(r.off, r.req->bytes);
     r.req.reset();
     r.fresh = false;
     --S->resident;
@@ -212,12 +228,61 @@ int admit_locked(mindist_server *S) {
         r.off = off;
         r.seq = S->next_seq++;
         r.fresh = true;
+        r.used = true;
         ++S->resident;
         ++S->st.admitted;
         ++admitted;
         it = S->pending.erase(it);
     }
     return admitted;
+}
+
+// While a launch runs: move waiting requests that fit into slots not used
+// in this launch (submission order among those that fit; rows within an
+// inbox entry).  Returns the slots.  Caller holds the lock.
+std::vector<int> admit_live_locked(mindist_server *S) {
+    std::vector<int> out;
+    int s_next = 0;
+    for (auto it = S->pending.begin(); it != S->pending.end();) {
+        if ((*it)->hc.rows_bytes > kInboxRowsBytes) { ++it; continue; }
+        while (s_next < (int)S->slots.size() && (S->slots[s_next].req || S->slots[s_next].used)) ++s_next;
+        if (s_next >= (int)S->slots.size()) break;
+        size_t off = 0;
+        if (!S->pool.alloc((*it)->bytes, off)) { ++it; continue; }
+        Resident &r = S->slots[s_next];
+        r.req = std::move(*it);
+        r.req->t_admit = S->clock();
+        r.off = off;
+        r.seq = S->next_seq++;
+        r.fresh = false;
+        r.used = true;
+        ++S->resident;
+        ++S->st.admitted;
+        ++S->st.admitted_live;
+        out.push_back(s_next);
+        it = S->pending.erase(it);
+    }
+    return out;
+}
+
+// Write slot s's code into its inbox entry and publish it to the running
+// kernel (the ring entry, then the count, released).
+void publish_live(mindist_server *S, int s, uint32_t tile_max) {
+    Resident &r = S->slots[s];
+    HostCode &hc = r.req->hc;
+    ServeInbox &in = S->h_inbox[s];
+    unsigned char *base = S->d_pool + r.off;
+    SlotPlace pl{base, base + round_up(hc.rows_bytes), base + round_up(hc.rows_bytes) + round_up(hc.tab_bytes)};
+    fill_slot(hc, pl, in.rows, tile_max, r.seq, in.code);
+    in.code.arena_lo = (uint64_t)s * S->seg_units;
+    in.code.arena_hi = (uint64_t)(s + 1) * S->seg_units;
+    in.code.arena_next = in.code.arena_lo;
+    in.rows_dst = (uint64_t)(uintptr_t)pl.rows;
+    in.rows_bytes = (uint32_t)hc.rows_bytes;
+    __atomic_store_n(&S->h_done[s], 0u, __ATOMIC_RELAXED);
+    S->h_ring[S->published] = (uint32_t)s;
+    ++S->published;
+    __atomic_store_n(&S->h_admit[0], S->published, __ATOMIC_RELEASE);
 }
 
 // Write the freshly admitted slots to the device (the kernel is stopped).
@@ -257,9 +322,20 @@ void manager(mindist_server *S) {
     S->wall_hz = khz * 1000.0;
     std::vector<unsigned char> arena_host;
     std::vector<Slot> slot_host;
+    auto die = [&](const std::string &msg) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->fatal = msg;
+        S->quit = true;
+        S->cv.notify_all();
+    };
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(S->mu);
+            // between launches: ranges freed during the last one return to
+            // the pool, and a slot is used only if it holds a code
+            for (auto &rg : S->retired) S->pool.release(rg.first, rg.second);
+            S->retired.clear();
+            for (auto &r : S->slots) r.used = (bool)r.req;
             admit_locked(S);
             if (S->resident == 0) {
                 if (S->quit) return;
@@ -268,20 +344,21 @@ void manager(mindist_server *S) {
             }
         }
         if (upload_fresh(S, tile_max)) {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->fatal = last_error_text();
-            S->quit = true;
-            S->cv.notify_all();
+            die(last_error_text());
             return;
         }
-        // one epoch
+        // one launch
         std::memset(S->h_g, 0, sizeof(BatchGlobal));
         {
             // the codes this launch starts with: the pair planner gives each
-            // its share of the waves
+            // its share of the waves (the kernel counts the ones admitted later)
             std::lock_guard<std::mutex> lk(S->mu);
             S->h_g->live0 = (uint32_t)std::max(1, S->resident);
+            S->running = true;
         }
+        S->published = 0;
+        __atomic_store_n(&S->h_admit[0], 0u, __ATOMIC_RELAXED);
+        __atomic_store_n(&S->h_admit[32], 0u, __ATOMIC_RELAXED);
         *reinterpret_cast<volatile uint32_t *>(S->h_stop) = 0;
         std::atomic_thread_fence(std::memory_order_seq_cst);
         BatchArgs a{};
@@ -292,6 +369,10 @@ void manager(mindist_server *S) {
         a.host_done = S->dv_done;
         a.host_stop = S->dv_stop;
         a.mirror = S->dv_mirror;
+        a.inbox = S->dv_inbox;
+        a.admit_ring = S->dv_ring;
+        a.admit_count = S->dv_admit;
+        a.admit_ack = S->dv_admit + 32;
         a.n_codes = (int)S->slots.size();
         a.serving = 1;
         a.tile_min = tile_min;
@@ -303,10 +384,7 @@ void manager(mindist_server *S) {
             hipMemcpyAsync(S->d_g, S->h_g, sizeof(BatchGlobal), hipMemcpyHostToDevice, S->stream) != hipSuccess ||
             hipEventRecord(S->ev0, S->stream) != hipSuccess || launch_persistent(a, blocks, S->stream) ||
             hipEventRecord(S->ev1, S->stream) != hipSuccess) {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->fatal = "server: launch failed";
-            S->quit = true;
-            S->cv.notify_all();
+            die("server: launch failed");
             return;
         }
         const double t_launch = S->clock();
@@ -321,17 +399,30 @@ void manager(mindist_server *S) {
                 if (v == (uint32_t)r.seq) collect(S, s, arena_host, slot_host);
             }
             if (q != hipErrorNotReady) break;
+            // codes that arrived: into the running kernel
+            std::vector<int> live;
+            if (!stop_sent) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (!S->quit) live = admit_live_locked(S);
+            }
+            for (int s : live) publish_live(S, s, tile_max);
             bool stop = false;
             {
                 std::unique_lock<std::mutex> lk(S->mu);
                 if (S->quit || S->resident == 0) stop = true;
                 else if (!S->pending.empty() && S->clock() - t_launch >= epoch_min) {
-                    // stop only if a waiting code would fit now
-                    bool has_slot = false;
-                    for (auto &r : S->slots) has_slot = has_slot || !r.req;
-                    stop = has_slot;
+                    // a waiting code could not come in: stop only if a relaunch
+                    // would let it (a free slot used earlier in this launch,
+                    // pool ranges waiting to return, rows beyond an inbox entry)
+                    bool free_slot = false;
+                    for (auto &r : S->slots) free_slot = free_slot || !r.req;
+                    bool wide = false;
+                    for (auto &p : S->pending) wide = wide || p->hc.rows_bytes > kInboxRowsBytes;
+                    stop = free_slot && (!S->retired.empty() || wide ||
+                                         std::none_of(S->slots.begin(), S->slots.end(),
+                                                      [](const Resident &r) { return !r.req && !r.used; }));
                 }
-                if (!stop) S->cv.wait_for(lk, std::chrono::microseconds(50));
+                if (!stop && live.empty()) S->cv.wait_for(lk, std::chrono::microseconds(50));
             }
             if (stop && !stop_sent) {
                 __atomic_store_n(S->h_stop, 1u, __ATOMIC_RELEASE);
@@ -339,10 +430,7 @@ void manager(mindist_server *S) {
             }
         }
         if (hipStreamSynchronize(S->stream) != hipSuccess) {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->fatal = std::string("server: kernel failed: ") + hipGetErrorString(hipGetLastError());
-            S->quit = true;
-            S->cv.notify_all();
+            die(std::string("server: kernel failed: ") + hipGetErrorString(hipGetLastError()));
             return;
         }
         float ms = 0;
@@ -351,6 +439,11 @@ void manager(mindist_server *S) {
             std::lock_guard<std::mutex> lk(S->mu);
             ++S->st.epochs;
             S->st.seconds_kernel += ms * 1e-3;
+            S->running = false;
+            // published codes the kernel did not copy in before it ended are
+            // written by the next launch's upload
+            const uint32_t copied = __atomic_load_n(&S->h_admit[32], __ATOMIC_ACQUIRE);
+            for (uint32_t i = copied; i < S->published; ++i) S->slots[S->h_ring[i]].fresh = true;
         }
         // codes that finished right before the launch ended
         for (int s = 0; s < (int)S->slots.size(); ++s) {
@@ -434,6 +527,9 @@ void release(mindist_server *S) {
     if (S->h_done) (void)hipHostFree(S->h_done);
     if (S->h_stop) (void)hipHostFree(S->h_stop);
     if (S->h_mirror) (void)hipHostFree(S->h_mirror);
+    if (S->h_inbox) (void)hipHostFree(S->h_inbox);
+    if (S->h_ring) (void)hipHostFree(S->h_ring);
+    if (S->h_admit) (void)hipHostFree(S->h_admit);
     if (S->stream) stream_put(S->stream);
     if (S->ev0) event_put(S->ev0);
     if (S->ev1) event_put(S->ev1);
@@ -498,10 +594,20 @@ extern "C" int mindist_server_create(const mindist_server_opts *opts, mindist_se
         hipHostGetDevicePointer((void **)&S->dv_stop, S->h_stop, 0) != hipSuccess ||
         hipHostMalloc((void **)&S->h_mirror, sizeof(ServeMirror) * (size_t)slots,
                       hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
-        hipHostGetDevicePointer((void **)&S->dv_mirror, S->h_mirror, 0) != hipSuccess) {
+        hipHostGetDevicePointer((void **)&S->dv_mirror, S->h_mirror, 0) != hipSuccess ||
+        hipHostMalloc((void **)&S->h_inbox, sizeof(ServeInbox) * (size_t)slots,
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&S->dv_inbox, S->h_inbox, 0) != hipSuccess ||
+        hipHostMalloc((void **)&S->h_ring, sizeof(uint32_t) * (size_t)slots,
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&S->dv_ring, S->h_ring, 0) != hipSuccess ||
+        hipHostMalloc((void **)&S->h_admit, 256, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&S->dv_admit, S->h_admit, 0) != hipSuccess) {
         release(S.get());
         return fail(MINDIST_E_NOMEM, "server: pinned flag allocation failed");
     }
+    std::memset(S->h_ring, 0xFF, sizeof(uint32_t) * (size_t)slots);
+    std::memset(S->h_admit, 0, 256);
     std::memset(S->h_done, 0, sizeof(uint32_t) * (size_t)slots);
     *S->h_stop = 0;
     // every slot starts empty on the device

@@ -1,6 +1,7 @@
 """GPU tests of the serving loop (continuous batching of arriving codes),
 under both engines: worker threads running the single-code path side by
-side (engine 0) and the persistent multi-code kernel in epochs (engine 1).
+side (engine 0) and the persistent multi-code kernel, which admits arriving
+codes while it runs (engine 1).
 
 Each request's result in the mix must be exactly its result alone (d, the
 visited pairs, their bounds, counts and minima), with a valid witness; codes
@@ -85,7 +86,9 @@ def test_server_admits_while_others_run(engine):
                for i in range(len(light))]
     assert sum(overlap) >= 7, "no light code ran while the heavy one was on the device"
     if engine == 1:
-        assert st["epochs"] >= 2
+        # the light codes come into the running launch (7 free slots), the
+        # rest after a relaunch frees the slots the first ones used
+        assert st["admitted_live"] >= 7, st
     for i, (n, k, G) in enumerate(light):
         assert got[i]["status"] == 0
         same_as_single(got[i], md.min_distance(G, n, k))

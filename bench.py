@@ -618,10 +618,14 @@ def batch_stratum_leg(name: str, codes_total: int = 4096):
     lo, hi = {"light": (0, 1e9), "medium": (1e9, 2e10), "heavy": (2e10, 1e12)}[name]
     codes = [c for c in (batch_code(i) for i in range(codes_total)) if lo <= estimated_work(md, c[2], c[0], c[1]) < hi]
     t0 = time.perf_counter()
-    res, info = md.run_batch(codes, pairs=False, direct_log2=-1, deadline_s=300)
+    res, info = md.run_batch(codes, pairs=True, direct_log2=-1, deadline_s=300)
     dt = time.perf_counter() - t0
+    # 32-bit XOR + popcount operations: every pair's codewords times the
+    # words its set carries
+    ops = sum(p["executed"] * p["dwords"] for r in res if "error" not in r for p in r["pairs"])
     print(json.dumps({"batch_stratum": name, "codes": len(codes), "seconds": dt,
                       "kernel_s": info["seconds_kernel"], "codewords": info["executed_total"],
+                      "dword_ops": ops, "dword_ops_per_s_kernel": ops / info["seconds_kernel"],
                       "errors": sum(1 for r in res if "error" in r)}), flush=True)
 
 

@@ -82,6 +82,24 @@ class Pair(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+# Pair records viewed as a numpy structured array (the same bytes), so that
+# thousands of them become dicts without a ctypes attribute read per field
+_PAIR_NAMES = [f for f, _ in Pair._fields_]
+_NP_OF = {C.c_int32: np.int32, C.c_uint64: np.uint64, C.c_double: np.float64}
+_PAIR_DTYPE = np.dtype({"names": _PAIR_NAMES,
+                        "formats": [_NP_OF[t] for _, t in Pair._fields_],
+                        "offsets": [getattr(Pair, f).offset for f in _PAIR_NAMES],
+                        "itemsize": C.sizeof(Pair)})
+
+
+def _pair_dicts(arr, lo: int, hi: int):
+    """Records lo..hi-1 of a ctypes Pair array as dicts."""
+    if hi <= lo:
+        return []
+    view = np.frombuffer(arr, dtype=_PAIR_DTYPE, count=hi, offset=0)[lo:hi]
+    return [dict(zip(_PAIR_NAMES, t)) for t in view.tolist()]
+
+
 class CertSpec(C.Structure):
     _fields_ = [("n", C.c_int32), ("k", C.c_int32), ("m_full", C.c_int32), ("k_partial", C.c_int32),
                 ("partial_policy", C.c_int32), ("per_level", C.c_int32), ("midpair_exit", C.c_int32)]
@@ -319,7 +337,7 @@ class MinDist:
         _check(lib().mindist_get_pairs(self._h, None, 0, C.byref(cnt)))
         arr = (Pair * max(cnt.value, 1))()
         _check(lib().mindist_get_pairs(self._h, arr, cnt.value, C.byref(cnt)))
-        return [arr[i].to_dict() for i in range(cnt.value)]
+        return _pair_dicts(arr, 0, cnt.value)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -371,7 +389,8 @@ def run_batch(codes, tile_min: int = 0, tile_max: int = 0, blocks_per_cu: int = 
     o.done_s = C.cast(done, C.c_void_p)
     if pairs:
         cap = B * BATCH_MAX_PAIRS
-        parr = (Pair * cap)()
+        # not zero-filled: the library writes every record the index names
+        parr = (Pair * cap).from_buffer(np.empty(max(cap, 1) * C.sizeof(Pair), dtype=np.uint8))
         idx = (C.c_int64 * (B + 1))()
         o.pairs = C.cast(parr, C.c_void_p)
         o.pairs_cap = cap
@@ -384,7 +403,7 @@ def run_batch(codes, tile_min: int = 0, tile_max: int = 0, blocks_per_cu: int = 
             continue
         r = out[i].to_dict()
         if pairs:
-            r["pairs"] = [parr[t].to_dict() for t in range(idx[i], min(idx[i + 1], cap))]
+            r["pairs"] = _pair_dicts(parr, idx[i], min(idx[i + 1], cap))
         results.append(r)
     info = {"seconds_kernel": o.seconds_kernel, "seconds_total": o.seconds_total,
             "seconds_prep": o.seconds_prep, "executed_total": o.executed_total,
@@ -428,7 +447,7 @@ class Server:
                      "t_admit": r.t_admit, "t_done": r.t_done}
                 if r.status == 0:
                     d.update(r.result.to_dict())
-                    d["pairs"] = [r.pairs[i].to_dict() for i in range(r.n_pairs)]
+                    d["pairs"] = _pair_dicts(r.pairs, 0, r.n_pairs)
                 out.append(d)
             if got.value < len(self._buf):
                 return out
@@ -472,7 +491,7 @@ def run_noalloc(G, n: int, k: int, stream: int = 0, pairs_cap: int = 4096) -> di
     _check(lib().mindist_run_noalloc(_u64(m), n, k, int(stream), C.byref(r), arr, pairs_cap,
                                      C.byref(cnt)))
     out = r.to_dict()
-    out["pairs"] = [arr[i].to_dict() for i in range(min(cnt.value, pairs_cap))]
+    out["pairs"] = _pair_dicts(arr, 0, min(cnt.value, pairs_cap))
     return out
 
 

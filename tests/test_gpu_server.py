@@ -179,3 +179,43 @@ def test_served_results_equal_the_oracle(engine):
         compare_with_trace(r, ref["trace"].tolist(), counts, pmin, None, k)
         assert all(p["executed"] == p["count"] for p in r["pairs"][:-1])
         check_witness(G, n, k, r)
+
+
+def test_engine1_admission_under_slot_and_memory_pressure():
+    """Engine 1 with 3 slots and a small device pool, a longer code first and
+    30 light codes arriving in bursts: codes come into the running launch
+    while slots and pool ranges are fresh, and the launch is stopped and
+    restarted when only a relaunch frees them (slots and ranges serve one
+    code per launch).  Every result equals the code's result alone and the
+    oracle's, with a valid witness."""
+    import oracle
+    from tests.test_gpu_parity import compare_with_trace, oracle_tables
+    w = WORKLOADS["rand255x40"]
+    first = (w.n, w.k, w.matrix())
+    light = light_codes(30, seed=98)
+    say("engine 1 pressure: 3 slots, 24 MiB pool, [255,40] then 30 light codes in bursts")
+    with md.Server(max_active=3, device_bytes=24 << 20, engine=1, epoch_min_ms=0.05) as srv:
+        srv.submit(first[2], first[0], first[1], tag=1000)
+        time.sleep(0.002)
+        for i, (n, k, G) in enumerate(light):
+            srv.submit(G, n, k, tag=i)
+            if i % 5 == 4:
+                time.sleep(0.001)
+        got = collect(srv, len(light) + 1, timeout=300)
+        st = srv.stats()
+    say("stats", st)
+    assert st["completed"] == len(light) + 1
+    assert st["admitted_live"] >= 2, st
+    assert st["epochs"] >= 2, st
+    h = got[1000]
+    assert h["status"] == 0
+    same_as_single(h, md.min_distance(first[2], first[0], first[1]))
+    check_witness(first[2], first[0], first[1], h)
+    for i, (n, k, G) in enumerate(light):
+        r = got[i]
+        assert r["status"] == 0, (i, r["status"])
+        ref = oracle.bz(G, n, k, threads=4)
+        assert r["d"] == ref["d"], (i, n, k)
+        counts, pmin, _ = oracle_tables(ref)
+        compare_with_trace(r, ref["trace"].tolist(), counts, pmin, None, k)
+        check_witness(G, n, k, r)

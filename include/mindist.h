@@ -353,7 +353,8 @@ typedef struct mindist_batch_opts {
     int32_t jobs_per_code;    /* job-arena sizing: average jobs per code (0 = 96) */
     int32_t chunks_per_visit; /* chunks a wave runs on one code's job before it moves on to
                                  the next code with work (0 = 4; -1 = until the job is fully
-                                 claimed): the share of waves each live code gets */
+                                 claimed): the share of waves each live code gets; a job of
+                                 1024 chunks or more is always run until fully claimed */
     int32_t direct_log2;      /* routing: a code expected to enumerate at least 2^direct_log2
                                  combinations (estimate: every pair while the bound is below a
                                  Gilbert-Varshamov estimate of d), or beyond the persistent

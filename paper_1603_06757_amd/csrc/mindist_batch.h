@@ -76,6 +76,7 @@ struct BatchSet {
 };
 
 constexpr int kJobCounters = 8;       // chunk dispensers per job (one cache line each)
+constexpr uint64_t kQuantumJobChunks = 1024;   // jobs this large ignore the chunks-per-visit quantum
 // waves that take part in a job: kPickersPerChunk per chunk, at least
 // kPickersMin (the rest pass it over without touching it)
 constexpr uint64_t kPickersPerChunk = 4, kPickersMin = 256;

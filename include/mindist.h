@@ -450,8 +450,11 @@ typedef struct mindist_server_opts {
                                  max_active worker threads; the device runs the kernels of
                                  the codes in flight side by side.  1: the persistent
                                  multi-code kernel, admitting codes while it runs (epoch_min_ms, jobs_per_code,
-                                 blocks_per_cu and chunks_per_visit apply to this engine
-                                 only) */
+                                 blocks_per_cu, chunks_per_visit and linger_ms apply to this
+                                 engine only) */
+    double  linger_ms;        /* engine 1: how long a launch with no code left keeps running
+                                 for the next arrivals (0 = 200 ms, negative = it ends at
+                                 once); its idle waves sleep between looks */
 } mindist_server_opts;
 
 #define MINDIST_SERVER_MAX_PAIRS 256

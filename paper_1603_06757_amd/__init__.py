@@ -124,7 +124,7 @@ class ServerOpts(C.Structure):
     _fields_ = [("max_active", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("device_bytes", C.c_int64), ("epoch_min_ms", C.c_double),
                 ("table_kib", C.c_int32), ("jobs_per_code", C.c_int32),
-                ("chunks_per_visit", C.c_int32), ("engine", C.c_int32)]
+                ("chunks_per_visit", C.c_int32), ("engine", C.c_int32), ("linger_ms", C.c_double)]
 
 
 class ServerResult(C.Structure):
@@ -424,9 +424,9 @@ class Server:
 
     def __init__(self, max_active: int = 0, blocks_per_cu: int = 0, device_bytes: int = 0,
                  epoch_min_ms: float = 0.0, table_kib: int = 0, jobs_per_code: int = 0,
-                 chunks_per_visit: int = 0, engine: int = 0):
+                 chunks_per_visit: int = 0, engine: int = 0, linger_ms: float = 0.0):
         o = ServerOpts(max_active, blocks_per_cu, device_bytes, epoch_min_ms, table_kib,
-                       jobs_per_code, chunks_per_visit, engine)
+                       jobs_per_code, chunks_per_visit, engine, linger_ms)
         h = C.c_void_p()
         _check(lib().mindist_server_create(C.byref(o), C.byref(h)))
         self._h = h

@@ -316,6 +316,9 @@ void manager(mindist_server *S) {
     const int resident_bpc = persistent_resident_blocks_per_cu();
     const int blocks = S->cus * (resident_bpc > 0 && bpc_req > resident_bpc ? resident_bpc : bpc_req);
     const double epoch_min = (S->o.epoch_min_ms > 0 ? S->o.epoch_min_ms : 0.5) * 1e-3;
+    // a launch with no code left waits this long for the next arrivals
+    // (admitted into it) before it ends
+    const double linger = S->o.linger_ms > 0 ? S->o.linger_ms * 1e-3 : S->o.linger_ms < 0 ? 0.0 : 0.2;
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, S->device) != hipSuccess || khz <= 0)
         khz = 100000;
@@ -388,6 +391,7 @@ void manager(mindist_server *S) {
             return;
         }
         const double t_launch = S->clock();
+        double t_idle = -1;                 // when the launch last became empty
         bool stop_sent = false;
         for (;;) {
             const hipError_t q = hipEventQuery(S->ev1);
@@ -409,8 +413,12 @@ void manager(mindist_server *S) {
             bool stop = false;
             {
                 std::unique_lock<std::mutex> lk(S->mu);
-                if (S->quit || S->resident == 0) stop = true;
-                else if (!S->pending.empty() && S->clock() - t_launch >= epoch_min) {
+                const double now = S->clock();
+                if (S->resident > 0) t_idle = -1;
+                else if (t_idle < 0) t_idle = now;
+                if (S->quit) stop = true;
+                else if (S->resident == 0 && S->pending.empty() && now - t_idle >= linger) stop = true;
+                else if (!S->pending.empty() && now - t_launch >= epoch_min) {
                     // a waiting code could not come in: stop only if a relaunch
                     // would let it (a free slot used earlier in this launch,
                     // pool ranges waiting to return, rows beyond an inbox entry)

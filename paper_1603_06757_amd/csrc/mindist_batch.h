@@ -78,8 +78,11 @@ struct BatchSet {
 constexpr int kJobCounters = 8;       // chunk dispensers per job (one cache line each)
 constexpr uint64_t kQuantumJobChunks = 1024;   // jobs this large ignore the chunks-per-visit quantum
 // waves that take part in a job: kPickersPerChunk per chunk, at least
-// kPickersMin (the rest pass it over without touching it)
+// kPickersMin (the rest pass it over without touching it); with at most
+// kFewLiveCodes codes live, the Few figures
 constexpr uint64_t kPickersPerChunk = 4, kPickersMin = 256;
+constexpr uint64_t kPickersPerChunkFew = 1, kPickersMinFew = 64;
+constexpr uint32_t kFewLiveCodes = 4;
 constexpr int kBatchDirectWorkers = 8;   // threads running a batch's codes routed to the single path
 
 // one job of a code; GroupEntry groups[ngroups] follow the struct.

@@ -969,10 +969,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
             // by code): every wave that looks at a job claims from it and
             // marks it drained with device-scope atomics on a few lines, so
             // thousands of idle waves falling on a one-chunk pair had cost
-            // each pair of a code running alone ~0.35 ms
+            // each pair of a code running alone ~0.35 ms.  With at most 4
+            // live codes, one picker per chunk (at least 64): the waves
+            // that would only find the job drained add claims and
+            // completion atomics to its lines (a code alone: 10-15 % per
+            // pair); with more, 4 per chunk (at least 256) spread the waves
+            // better over many short jobs
             const uint64_t total = uni64(ldc(&jb->total_chunks));
             const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-            const uint64_t want = total * kPickersPerChunk > kPickersMin ? total * kPickersPerChunk : kPickersMin;
+            const uint32_t l0 = uni32(ld_rlx(&A.g->live0)), cd = uni32(ld_rlx(&A.g->codes_done));
+            const bool few = (l0 ? l0 : (uint32_t)nc) <= cd + kFewLiveCodes;
+            const uint64_t per = few ? kPickersPerChunkFew : kPickersPerChunk;
+            const uint64_t lo = few ? kPickersMinFew : kPickersMin;
+            const uint64_t want = total * per > lo ? total * per : lo;
             if (want < waves) {
                 const uint32_t rank = (wave + (uint32_t)c * 0x9E3779B1u % waves) % waves;
                 if (rank >= want) {

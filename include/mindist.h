@@ -455,6 +455,11 @@ typedef struct mindist_server_opts {
     double  linger_ms;        /* engine 1: how long a launch with no code left keeps running
                                  for the next arrivals (0 = 200 ms, negative = it ends at
                                  once); its idle waves sleep between looks */
+    int32_t route_log2;       /* engine 1: codes expected to enumerate at least
+                                 2^route_log2 combinations run through the single-code
+                                 path on 4 worker threads beside the persistent kernel,
+                                 which then holds 2 blocks per CU unless blocks_per_cu says
+                                 otherwise (0 = 2^24; -1 = none, every code in the kernel) */
 } mindist_server_opts;
 
 #define MINDIST_SERVER_MAX_PAIRS 256
@@ -480,7 +485,8 @@ typedef struct mindist_server_stats {
     int32_t  resident;        /* codes on the device (engine 1) or being run (engine 0) now */
     int32_t  pending;         /* codes waiting for admission now */
     uint64_t admitted_live;   /* engine 1: codes admitted into a running launch (the rest of
-                                 `admitted` were written between launches) */
+                                 `admitted` were written between launches or routed) */
+    uint64_t routed;          /* engine 1: codes run through the single path (route_log2) */
 } mindist_server_stats;
 
 /* Start a server on the current HIP device (opts may be NULL).  *out is

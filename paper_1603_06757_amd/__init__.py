@@ -124,7 +124,8 @@ class ServerOpts(C.Structure):
     _fields_ = [("max_active", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("device_bytes", C.c_int64), ("epoch_min_ms", C.c_double),
                 ("table_kib", C.c_int32), ("jobs_per_code", C.c_int32),
-                ("chunks_per_visit", C.c_int32), ("engine", C.c_int32), ("linger_ms", C.c_double)]
+                ("chunks_per_visit", C.c_int32), ("engine", C.c_int32), ("linger_ms", C.c_double),
+                ("route_log2", C.c_int32)]
 
 
 class ServerResult(C.Structure):
@@ -136,7 +137,8 @@ class ServerResult(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
                 ("epochs", C.c_uint64), ("seconds_kernel", C.c_double),
-                ("resident", C.c_int32), ("pending", C.c_int32), ("admitted_live", C.c_uint64)]
+                ("resident", C.c_int32), ("pending", C.c_int32), ("admitted_live", C.c_uint64),
+                ("routed", C.c_uint64)]
 
 
 _lib = None
@@ -424,9 +426,10 @@ class Server:
 
     def __init__(self, max_active: int = 0, blocks_per_cu: int = 0, device_bytes: int = 0,
                  epoch_min_ms: float = 0.0, table_kib: int = 0, jobs_per_code: int = 0,
-                 chunks_per_visit: int = 0, engine: int = 0, linger_ms: float = 0.0):
+                 chunks_per_visit: int = 0, engine: int = 0, linger_ms: float = 0.0,
+                 route_log2: int = 0):
         o = ServerOpts(max_active, blocks_per_cu, device_bytes, epoch_min_ms, table_kib,
-                       jobs_per_code, chunks_per_visit, engine, linger_ms)
+                       jobs_per_code, chunks_per_visit, engine, linger_ms, route_log2)
         h = C.c_void_p()
         _check(lib().mindist_server_create(C.byref(o), C.byref(h)))
         self._h = h

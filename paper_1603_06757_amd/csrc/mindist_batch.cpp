@@ -58,7 +58,7 @@ static int expected_top_level(const HostCode &hc) {
 // Combinations Algorithm 1 is expected to enumerate: every pair in order
 // while the bound is below a Gilbert-Varshamov estimate of d (the least w
 // with sum_{i<=w} C(n,i) >= 2^(n-k)).
-static double estimated_work(const HostCode &hc) {
+double estimated_work(const HostCode &hc) {
     const int n = hc.n, k = hc.k;
     auto log2c = [](int a, int b) {
         return (std::lgamma(a + 1.0) - std::lgamma(b + 1.0) - std::lgamma(a - b + 1.0)) / std::log(2.0);

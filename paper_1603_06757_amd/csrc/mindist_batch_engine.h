@@ -50,6 +50,9 @@ int decode_code(const HostCode &hc, const BatchCode &bc, const unsigned char *ar
 size_t job_bytes(int k);
 void parallel_for(int count, int threads, const std::function<void(int)> &fn);
 int host_threads();
+// combinations Algorithm 1 is expected to enumerate for a prepared code (every
+// pair while the bound is below a Gilbert-Varshamov estimate of d)
+double estimated_work(const HostCode &hc);
 
 // device buffers and launch of the persistent kernel over `slots` codes
 struct Engine {

@@ -10,7 +10,12 @@
 // latency is that of the single-code path.
 //
 // Engine 1: the persistent multi-code kernel keeps every resident code
-// moving (pair after pair, Algorithm 1's control on the device).  A code
+// moving (pair after pair, Algorithm 1's control on the device); codes
+// expected to enumerate at least 2^route_log2 combinations (and codes beyond
+// the kernel's layout) run through the single-code path on 4 worker threads
+// beside it instead, the kernel then holding 2 blocks per CU so that their
+// kernels find room: alone in the persistent kernel such a code's pairs run
+// on the few waves their chunks occupy, several times slower.  A code
 // that arrives while it runs is admitted into it: the manager thread writes
 // the code's descriptor and packed rows into the slot's inbox entry in
 // pinned host memory and publishes the slot in a ring; one of the kernel's
@@ -58,6 +63,8 @@ namespace md {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kRouteWorkers = 4;     // engine 1: single-path workers for the routed codes
+constexpr double kRouteLaunchMax = 0.02;   // s: longest launch while routed codes are in flight
 
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -126,6 +133,9 @@ struct mindist_server {
     std::mutex mu;
     std::condition_variable cv;       // submits, completions, shutdown
     std::deque<std::unique_ptr<md::Request>> pending;
+    std::deque<std::unique_ptr<md::Request>> routed;   // engine 1: codes for the single-path workers
+    int routed_active = 0;                  // engine 1: routed codes being run
+    double route_min = 0;                   // engine 1: estimated combinations from which a code is routed (0: none)
     std::deque<std::unique_ptr<mindist_server_result>> done;
     std::vector<md::Resident> slots;
     int resident = 0;
@@ -312,7 +322,9 @@ int upload_fresh(mindist_server *S, const uint32_t tile_max) {
 void manager(mindist_server *S) {
     (void)hipSetDevice(S->device);
     const uint32_t tile_min = 2048, tile_max = 4096;   // as the batch defaults
-    const int bpc_req = S->o.blocks_per_cu > 0 ? S->o.blocks_per_cu : 4;
+    // with codes routed to single-path workers, 2 blocks per CU leave room
+    // for their kernels beside the persistent one
+    const int bpc_req = S->o.blocks_per_cu > 0 ? S->o.blocks_per_cu : S->route_min > 0 ? 2 : 4;
     const int resident_bpc = persistent_resident_blocks_per_cu();
     const int blocks = S->cus * (resident_bpc > 0 && bpc_req > resident_bpc ? resident_bpc : bpc_req);
     const double epoch_min = (S->o.epoch_min_ms > 0 ? S->o.epoch_min_ms : 0.5) * 1e-3;
@@ -416,8 +428,16 @@ void manager(mindist_server *S) {
                 const double now = S->clock();
                 if (S->resident > 0) t_idle = -1;
                 else if (t_idle < 0) t_idle = now;
+                // Streams beyond the process's hardware queues share them, and
+                // a queue runs its kernels in order: a routed code's kernels
+                // may wait behind the persistent launch.  While routed codes
+                // are in flight, a launch neither lingers nor runs longer
+                // than kRouteLaunchMax (then it is relaunched over its codes)
+                const bool routed_busy = S->routed_active > 0 || !S->routed.empty();
                 if (S->quit) stop = true;
-                else if (S->resident == 0 && S->pending.empty() && now - t_idle >= linger) stop = true;
+                else if (S->resident == 0 && S->pending.empty() && now - t_idle >= (routed_busy ? 0.0 : linger))
+                    stop = true;
+                else if (routed_busy && now - t_launch >= kRouteLaunchMax) stop = true;
                 else if (!S->pending.empty() && now - t_launch >= epoch_min) {
                     // a waiting code could not come in: stop only if a relaunch
                     // would let it (a free slot used earlier in this launch,
@@ -470,27 +490,37 @@ void manager(mindist_server *S) {
 // order among the codes that fit); the single-code path allocates nothing
 // per code after warm-up (process-wide caches of device memory, streams
 // and events).
-void direct_worker(mindist_server *S) {
+//
+// routed (engine 1): the same, over the codes routed to the single path by
+// their estimated work, beside the persistent kernel; no memory budget (the
+// single path's own device memory), one code per worker.
+void direct_worker(mindist_server *S, bool routed) {
     (void)hipSetDevice(S->device);
-    const int table_mib = S->o.table_kib > 0 ? std::max(1, S->o.table_kib / 1024) : 0;
+    const int table_mib = S->o.table_kib > 0 && !routed ? std::max(1, S->o.table_kib / 1024) : 0;
+    auto &queue = routed ? S->routed : S->pending;
     for (;;) {
         std::unique_ptr<Request> req;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            auto fitting = S->pending.end();
+            auto fitting = queue.end();
             S->cv.wait(lk, [&] {
                 if (S->quit) return true;
-                fitting = std::find_if(S->pending.begin(), S->pending.end(), [&](const auto &r) {
-                    return S->bytes_in_flight + r->bytes <= S->bytes_budget;
+                fitting = std::find_if(queue.begin(), queue.end(), [&](const auto &r) {
+                    return routed || S->bytes_in_flight + r->bytes <= S->bytes_budget;
                 });
-                return fitting != S->pending.end();
+                return fitting != queue.end();
             });
             if (S->quit) return;
             req = std::move(*fitting);
-            S->pending.erase(fitting);
+            queue.erase(fitting);
             req->t_admit = S->clock();
-            S->bytes_in_flight += req->bytes;
-            ++S->resident;
+            if (routed) {
+                ++S->routed_active;
+                ++S->st.routed;
+            } else {
+                S->bytes_in_flight += req->bytes;
+                ++S->resident;
+            }
             ++S->st.admitted;
         }
         auto res = std::make_unique<mindist_server_result>();
@@ -515,8 +545,12 @@ void direct_worker(mindist_server *S) {
         if (status != MINDIST_OK && res->result.d >= 0) res->result.d = status;
         res->t_done = S->clock();
         std::lock_guard<std::mutex> lk(S->mu);
-        --S->resident;
-        S->bytes_in_flight -= req->bytes;
+        if (routed) {
+            --S->routed_active;
+        } else {
+            --S->resident;
+            S->bytes_in_flight -= req->bytes;
+        }
         ++S->st.completed;
         S->st.seconds_kernel += kernel_s;
         S->done.push_back(std::move(res));
@@ -570,7 +604,7 @@ extern "C" int mindist_server_create(const mindist_server_opts *opts, mindist_se
         S->bytes_budget = S->o.device_bytes > 0 ? (size_t)S->o.device_bytes : (size_t)8 << 30;
         S->t0 = std::chrono::steady_clock::now();
         mindist_server *raw = S.get();
-        for (int t = 0; t < workers; ++t) raw->workers.emplace_back(direct_worker, raw);
+        for (int t = 0; t < workers; ++t) raw->workers.emplace_back(direct_worker, raw, false);
         *out = S.release();
         return MINDIST_OK;
     }
@@ -632,8 +666,22 @@ extern "C" int mindist_server_create(const mindist_server_opts *opts, mindist_se
         return fail(MINDIST_E_HIP, "server: stream setup failed");
     }
     S->pool = RangePool(pool_bytes);
+    if (S->o.route_log2 >= 0) {
+        S->route_min = std::ldexp(1.0, S->o.route_log2 > 0 ? S->o.route_log2 : 24);
+        // warm one stream per routed worker and the binomial table
+        std::vector<hipStream_t> ss;
+        for (int t = 0; t < kRouteWorkers; ++t) ss.push_back(stream_get());
+        for (hipStream_t st : ss)
+            if (st) stream_put(st);
+        if (!device_binom_from(BN().t.data())) {
+            release(S.get());
+            return fail(MINDIST_E_NOMEM, "binomial table upload failed");
+        }
+    }
     mindist_server *raw = S.get();
     raw->mgr = std::thread(manager, raw);
+    if (raw->route_min > 0)
+        for (int t = 0; t < kRouteWorkers; ++t) raw->workers.emplace_back(direct_worker, raw, true);
     *out = S.release();
     return MINDIST_OK;
 }
@@ -664,7 +712,31 @@ extern "C" int mindist_server_submit(mindist_server *S, const uint64_t *G, int n
     }
     const uint64_t table_cap = (uint64_t)(S->o.table_kib > 0 ? S->o.table_kib : 65536) << 10;
     int e = prepare_code(G, n, k, table_cap, r->hc);
+    if (e == MINDIST_E_LIMIT && S->route_min > 0) {
+        // beyond the persistent kernel's layout: the single path runs it
+        r->n = n;
+        r->k = k;
+        r->G.assign(G, G + (size_t)k * ((n + 63) / 64));
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->quit) return fail(MINDIST_E_STATE, "server is shutting down");
+        S->routed.push_back(std::move(r));
+        ++S->st.submitted;
+        S->cv.notify_all();
+        return MINDIST_OK;
+    }
     if (e) return e;
+    if (S->route_min > 0 && estimated_work(r->hc) >= S->route_min) {
+        r->n = n;
+        r->k = k;
+        r->G.assign(G, G + (size_t)k * ((n + 63) / 64));
+        r->hc = HostCode();
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->quit) return fail(MINDIST_E_STATE, "server is shutting down");
+        S->routed.push_back(std::move(r));
+        ++S->st.submitted;
+        S->cv.notify_all();
+        return MINDIST_OK;
+    }
     const size_t pool_bytes = S->o.device_bytes > 0 ? (size_t)S->o.device_bytes : (size_t)8 << 30;
     // one code may take at most a quarter of the pool: lower its table levels if needed
     std::vector<HostCode *> one{&r->hc};
@@ -698,7 +770,8 @@ extern "C" int mindist_server_wait(mindist_server *S, double timeout_s) {
     const auto until = std::chrono::steady_clock::now() +
                        std::chrono::microseconds((int64_t)(std::max(timeout_s, 0.0) * 1e6));
     const bool ok = S->cv.wait_until(lk, until, [&] {
-        return S->quit || (S->pending.empty() && S->resident == 0);
+        return S->quit || (S->pending.empty() && S->resident == 0 && S->routed.empty() &&
+                           S->routed_active == 0);
     });
     if (!S->fatal.empty()) return fail(MINDIST_E_HIP, S->fatal);
     return ok ? MINDIST_OK : fail(MINDIST_E_TIMEOUT, "server: codes still waiting or running");
@@ -711,8 +784,8 @@ extern "C" int mindist_server_stats_get(const mindist_server *S, mindist_server_
     auto *M = const_cast<mindist_server *>(S);
     std::lock_guard<std::mutex> lk(M->mu);
     *out = M->st;
-    out->resident = M->resident;
-    out->pending = (int32_t)M->pending.size();
+    out->resident = M->resident + M->routed_active;
+    out->pending = (int32_t)(M->pending.size() + M->routed.size());
     return MINDIST_OK;
 }
 

@@ -68,7 +68,9 @@ def test_server_admits_while_others_run(engine):
     heavy = (w.n, w.k, w.matrix())
     light = light_codes(24, seed=92)
     say("server: heavy", heavy[:2], "then 24 light codes while it runs, engine", engine)
-    with md.Server(max_active=8, engine=engine) as srv:
+    # engine 1 without routing: the heavier code in the persistent kernel too
+    route = {"route_log2": -1} if engine == 1 else {}
+    with md.Server(max_active=8, engine=engine, **route) as srv:
         srv.submit(heavy[2], heavy[0], heavy[1], tag=1000)
         time.sleep(0.001)
         for i, (n, k, G) in enumerate(light):
@@ -101,14 +103,16 @@ def test_server_admission_by_device_memory(engine):
     exceeds the whole budget is refused at submit."""
     cs = [serving_request(i) for i in range(40)]
     cs = [(n, k, G) for n, k, G in cs if n <= 120][:16]
-    with md.Server(max_active=4, device_bytes=1024, engine=engine) as srv:
+    # engine 1 without routing: every code goes to its device pool
+    route = {"route_log2": -1} if engine == 1 else {}
+    with md.Server(max_active=4, device_bytes=1024, engine=engine, **route) as srv:
         with pytest.raises(md.MindistError) as e:
             srv.submit(cs[0][2], cs[0][0], cs[0][1], tag=0)
         assert e.value.code == -3
     # 48 MiB: the largest of these codes needs about 29 MiB (engine 0's
     # estimate), so only a few are in flight at once
     say("server: 16 serving-stream codes, 48 MiB of device memory, engine", engine)
-    with md.Server(max_active=64, device_bytes=48 << 20, engine=engine) as srv:
+    with md.Server(max_active=64, device_bytes=48 << 20, engine=engine, **route) as srv:
         for i, (n, k, G) in enumerate(cs):
             srv.submit(G, n, k, tag=i)
         got = collect(srv, len(cs), timeout=300)
@@ -194,7 +198,7 @@ def test_engine1_admission_under_slot_and_memory_pressure():
     first = (w.n, w.k, w.matrix())
     light = light_codes(30, seed=98)
     say("engine 1 pressure: 3 slots, 24 MiB pool, [255,40] then 30 light codes in bursts")
-    with md.Server(max_active=3, device_bytes=24 << 20, engine=1, epoch_min_ms=0.05) as srv:
+    with md.Server(max_active=3, device_bytes=24 << 20, engine=1, epoch_min_ms=0.05, route_log2=-1) as srv:
         srv.submit(first[2], first[0], first[1], tag=1000)
         time.sleep(0.002)
         for i, (n, k, G) in enumerate(light):
@@ -219,3 +223,28 @@ def test_engine1_admission_under_slot_and_memory_pressure():
         counts, pmin, _ = oracle_tables(ref)
         compare_with_trace(r, ref["trace"].tolist(), counts, pmin, None, k)
         check_witness(G, n, k, r)
+
+
+def test_engine1_routes_heavier_codes_to_the_single_path():
+    """Engine 1 with its default routing: light codes run in the persistent
+    kernel (2 blocks per CU), codes expected at 2^24 combinations or more on
+    single-path workers beside it, at the same time; every result equals
+    the code's result alone."""
+    from tests.test_gpu_parity import estimated_work
+    cs = [serving_request(i) for i in range(120)]
+    cs = [c for c in cs if estimated_work(c[0], c[1]) <= 2e10][:40]
+    say("engine 1 routing: 40 serving-stream codes")
+    with md.Server(engine=1) as srv:
+        for i, (n, k, G) in enumerate(cs):
+            srv.submit(G, n, k, tag=i)
+            if i % 8 == 7:
+                time.sleep(0.002)
+        got = collect(srv, len(cs), timeout=300)
+        st = srv.stats()
+    say("stats", st)
+    assert st["completed"] == len(cs)
+    assert 0 < st["routed"] < len(cs), st
+    for i, (n, k, G) in enumerate(cs):
+        assert got[i]["status"] == 0
+        same_as_single(got[i], md.min_distance(G, n, k))
+        check_witness(G, n, k, got[i])

@@ -453,6 +453,7 @@ def serving_leg(rate: float, seconds: float, cap: float, max_requests: int = 400
             "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
             "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
             "by_work": per, "epochs": st["epochs"], "admitted_live": st["admitted_live"],
+            "routed": st["routed"],
             "kernel_s": st["seconds_kernel"]}
 
 

@@ -429,14 +429,16 @@ typedef struct mindist_server mindist_server;
 typedef struct mindist_server_opts {
     int32_t max_active;       /* codes running at once: engine 0, worker threads (0 = 8);
                                  engine 1, code slots resident on the device (0 = 256) */
-    int32_t blocks_per_cu;    /* resident workgroups per CU (0 = 4) */
+    int32_t blocks_per_cu;    /* resident workgroups per CU (0 = 4; engine 1 routing codes to
+                                 the single path: 2) */
     int64_t device_bytes;     /* device memory for the codes in flight: a code is admitted
                                  only when its share fits beside theirs (0 = 8 GiB).  Engine
                                  0: estimated rows, saved right and left tables up to half
                                  the expected top level, run state; engine 1: rows,
                                  saved tables and witness slots in a pool allocated at
-                                 creation.  Submit fails with MINDIST_E_NOMEM for a code
-                                 whose share exceeds it */
+                                 creation (routed codes use the single path's own memory).
+                                 Submit fails with MINDIST_E_NOMEM for a code whose share
+                                 exceeds it */
     double  epoch_min_ms;     /* engine 1: least running time of a launch before it is
                                  stopped so that waiting codes that cannot be admitted
                                  into it come in (0 = 0.5 ms) */
@@ -477,12 +479,14 @@ typedef struct mindist_server_stats {
     uint64_t submitted, admitted, completed;
     uint64_t epochs;          /* launches of the persistent kernel (engine 1): a launch runs
                                  while codes are resident and admits arriving ones; it is
-                                 stopped only when a waiting code needs a relaunch to come in
+                                 stopped when a waiting code needs a relaunch to come in
                                  (every free slot already used in it, pool ranges freed in
-                                 it, rows beyond 32 KiB), and after 10 s */
+                                 it, rows beyond 32 KiB), when no code has been left for
+                                 linger_ms, after 20 ms while routed codes are in flight,
+                                 and after 10 s */
     double   seconds_kernel;  /* engine 1: summed launch time (HIP events); engine 0: summed
                                  enumeration kernel time of the finished codes (device clock) */
-    int32_t  resident;        /* codes on the device (engine 1) or being run (engine 0) now */
+    int32_t  resident;        /* codes being run now (engine 1: on the device or routed) */
     int32_t  pending;         /* codes waiting for admission now */
     uint64_t admitted_live;   /* engine 1: codes admitted into a running launch (the rest of
                                  `admitted` were written between launches or routed) */

@@ -500,7 +500,7 @@ def new_codes_leg(names, quiet: bool = False, peak: float = 0.0):
                "seconds": dt, "pairs": r["pairs_visited"], "codewords": r["executed_total"],
                "codewords_per_s": r["executed_total"] / dt,
                "valu_frac": ops / dt / max(peak, PEAK_DWORD_OPS),
-               "valu_frac_nominal": ops / dt / PEAK_DWORD_OPS}
+               "ops_per_s": ops / dt}
         if name in PAPER_CPU_S:
             one, six = PAPER_CPU_S[name]
             rec["paper_cpu_s"] = {"1_core": one, "6_cores": six}

@@ -422,7 +422,9 @@ class Server:
     returns finished results as dicts with the request's tag, its result,
     its visited pairs and t_submit / t_admit / t_done on the server clock.
     engine 0: worker threads running the single-code path side by side;
-    engine 1: the persistent multi-code kernel in epochs."""
+    engine 1: the persistent multi-code kernel, admitting codes while it
+    runs, with codes above 2^route_log2 estimated combinations on
+    single-path workers beside it."""
 
     def __init__(self, max_active: int = 0, blocks_per_cu: int = 0, device_bytes: int = 0,
                  epoch_min_ms: float = 0.0, table_kib: int = 0, jobs_per_code: int = 0,

@@ -316,3 +316,26 @@ def test_certificate_rejects_an_unjustified_cut():
     recs = base[:t] + [dict(base[t], executed=5, L_after=base[t]["L_before"])]
     _expect_cert(lambda: _certify(r, n, k, recs, d=recs[-1]["U_after"],
                                   L_final=base[t]["L_before"], exited=1))
+
+
+def test_pair_records_convert_to_the_same_dicts():
+    """The binding's numpy view of pair records gives exactly the dicts of
+    the ctypes fields (types included), for every field of the struct."""
+    import random
+    arr = (md.Pair * 40)()
+    rng = random.Random(3)
+    for i in range(40):
+        p = arr[i]
+        for f, t in md.Pair._fields_:
+            if t is ctypes.c_int32:
+                setattr(p, f, rng.randint(-2**31, 2**31 - 1))
+            elif t is ctypes.c_uint64:
+                setattr(p, f, rng.randint(0, 2**64 - 1))
+            else:
+                setattr(p, f, rng.random() * 1e6)
+    ref = [arr[i].to_dict() for i in range(40)]
+    got = md._pair_dicts(arr, 0, 40)
+    assert got == ref
+    assert [type(v) for v in got[0].values()] == [type(v) for v in ref[0].values()]
+    assert md._pair_dicts(arr, 7, 19) == ref[7:19]
+    assert md._pair_dicts(arr, 5, 5) == []

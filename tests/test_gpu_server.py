@@ -248,3 +248,28 @@ def test_engine1_routes_heavier_codes_to_the_single_path():
         assert got[i]["status"] == 0
         same_as_single(got[i], md.min_distance(G, n, k))
         check_witness(G, n, k, got[i])
+
+
+def test_engine1_code_beyond_the_kernel_layout():
+    """A code with more than 32 information sets is beyond the persistent
+    kernel's layout: engine 1 routes it to the single path (its result
+    equals the single path's and the oracle's d); without routing, submit
+    refuses it with MINDIST_E_LIMIT."""
+    import oracle
+    from paper_1603_06757_amd.gen import random_generator
+    G = random_generator(200, 3, 1, 2)
+    ref = oracle.bz(G, 200, 3)
+    say("engine 1: [200,3] code, 66 information sets")
+    with md.Server(engine=1) as srv:
+        srv.submit(G, 200, 3, tag=5)
+        got = collect(srv, 1)
+        st = srv.stats()
+    assert st["routed"] == 1
+    r = got[5]
+    assert r["status"] == 0 and r["d"] == ref["d"]
+    same_as_single(r, md.min_distance(G, 200, 3))
+    check_witness(G, 200, 3, r)
+    with md.Server(engine=1, route_log2=-1) as srv:
+        with pytest.raises(md.MindistError) as e:
+            srv.submit(G, 200, 3, tag=6)
+        assert e.value.code == -5

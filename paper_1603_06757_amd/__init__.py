@@ -62,12 +62,27 @@ class Result(C.Structure):
             "pairs_visited": self.pairs_visited, "exited_midpair": self.exited_midpair,
             "witness_pair": (self.witness_j, self.witness_w),
             "witness": np.array(self.witness[:W], dtype=np.uint64),
-            "witness_rows": [r for r in range(self.k)
-                             if (self.witness_rows[r // 64] >> (r % 64)) & 1],
+            "witness_rows": _set_bits(self.witness_rows, self.k),
             "executed_total": self.executed_total, "canonical_total": self.canonical_total,
             "seconds_total": self.seconds_total, "seconds_enum": self.seconds_enum,
             "enum_launches": self.enum_launches,
         }
+
+
+def _set_bits(words, limit: int):
+    """Indices below limit of the set bits of a little-endian uint64 word
+    array, ascending (one step per set bit)."""
+    out = []
+    for wi in range((limit + 63) // 64):
+        v = words[wi]
+        while v:
+            low = v & -v
+            i = wi * 64 + low.bit_length() - 1
+            if i >= limit:
+                break
+            out.append(i)
+            v ^= low
+    return out
 
 
 class Pair(C.Structure):

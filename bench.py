@@ -45,6 +45,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_DWORD_OPS = 256 * 64 * 2.4e9 / 2      # derived: 32-bit XOR+popcount per second at the rated clock
 LANE_ITEMS = 4                              # left subsets per lane (library default)
+MFMA_MAX_WORDS = 4                          # widest codeword the matrix-core inner loop takes
 
 
 def single_code_leg(steps: int, warmup: int):
@@ -101,9 +102,15 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
-def roofline(results, events, peak):
+PEAK_INT8_OPS = 5.0e15                      # MI355X dense int8 matrix-core peak, ops/s
+
+
+def roofline(results, events, peak, mfma=True):
     """peak: the larger of the derived figure and the measured register-only
-    ceiling, in 32-bit XOR+popcount ops/s."""
+    ceiling, in 32-bit XOR+popcount ops/s.  mfma: the library's default
+    inner loop for codewords of at most 4 words, a 32 x 32 x 32 int8 product
+    per word (64 D ops per codeword) priced against the int8 matrix-core
+    peak; the vector-ALU figures stay beside it."""
     # dominant kernel: the enumeration instance (dwords carried) with the most
     # time.  Launch times of the timed steps come from the device clock (the
     # kernel's first wave start to its last wave end, published with each
@@ -128,7 +135,8 @@ def roofline(results, events, peak):
     D, (sec, cw, launches) = max(per_d.items(), key=lambda kv: kv[1][0])
     ev_sec, ev_cw, ev_launches = per_dwords(events, "ms").get(D, (0.0, 0, 0))
     achieved = cw * D / sec
-    return D, {
+    on_mfma = mfma and D <= MFMA_MAX_WORDS
+    roof = {
         "bound": "alu",
         "achieved": achieved / 1e12,
         "peak": peak / 1e12,
@@ -138,17 +146,37 @@ def roofline(results, events, peak):
         "frac_nominal": achieved / PEAK_DWORD_OPS,
         "peak_source": "measured register-only ceiling (mindist_peak_xorpop, best shape and occupancy)"
                        if peak > PEAK_DWORD_OPS else "derived: 256 CU x 64 lanes x 2.4 GHz / 2",
+    }
+    if on_mfma:
+        ops = cw * 64 * D / sec
+        roof = {
+            "bound": "mfma",
+            "achieved": ops / 1e12,
+            "peak": PEAK_INT8_OPS / 1e12,
+            "unit": "TOP/s (int8)",
+            "frac": ops / PEAK_INT8_OPS,
+            "ops_per_codeword": 64 * D,
+            "peak_source": "MI355X dense int8 matrix-core peak",
+            # the same launches as XOR+popcount work, against the vector-ALU ceiling
+            "xorpop_equiv": achieved / 1e12,
+            "xorpop_equiv_unit": "T 32-bit xor+popcount/s",
+            "xorpop_equiv_over_valu_peak": achieved / peak,
+            "valu_peak": peak / 1e12,
+            "valu_peak_nominal": PEAK_DWORD_OPS / 1e12,
+        }
+    roof.update({
         "traffic": measured_traffic(),
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-        "kernel": f"md::enum_pair_kernel<{D}, {LANE_ITEMS}, false>",
+        "kernel": f"md::enum_pair_kernel<{D}, {LANE_ITEMS}, false, {'true' if on_mfma else 'false'}>",
         "launches": launches,
         "avg_launch_us": sec / launches * 1e6,
         "timing": "device clock per launch in the timed steps; HIP events in 2 untimed runs",
         "avg_launch_us_events": ev_sec / ev_launches * 1e6 if ev_launches else None,
         "codewords_per_s_kernel_events": ev_cw / ev_sec if ev_sec else None,
-        "ops_per_launch": cw * D / launches,
+        "ops_per_launch": cw * (64 * D if on_mfma else D) / launches,
         "codewords_per_s_kernel": cw / sec,
-    }
+    })
+    return D, roof
 
 
 def cpu_baseline(w, seconds: float = 4.0, repeats: int = 3):
@@ -731,7 +759,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "i8" if roof["bound"] == "mfma" else "u32",
         "data": "synthetic",
         "config": {"workload": f"random [{w.n},{w.k}] binary code, PCG32 seed {w.seed} "
                                f"attempt {w.attempt}, Bernoulli(1/2), 2 information sets",

@@ -97,8 +97,10 @@ extern "C" {
  * resident waves, else the longest (128..1024) that leaves every wave at
  * least max(2, D-1) chunks (D = 32-bit words per codeword). */
 #define MINDIST_OPT_TILE_T           7
-/* kernel shape: resident workgroups per CU for the enumeration launch
- * (default 4). */
+/* kernel shape: resident workgroups per CU the enumeration launches are
+ * sized for; 0 (default) = 4, or for the matrix-core kernel (MINDIST_OPT_MFMA)
+ * as many as its registers let one CU hold, at most 4 (2 at 3 and 4 words
+ * with 4 lane items). */
 #define MINDIST_OPT_BLOCKS_PER_CU    8
 /* 1 = time every enumeration launch with HIP events (seconds_enum). */
 #define MINDIST_OPT_PROFILE          9
@@ -140,6 +142,13 @@ extern "C" {
  * with MINDIST_E_CERT instead of returning a result whose enumeration
  * stopped short.  A value above the true distance changes nothing. */
 #define MINDIST_OPT_INJECT_U         18
+/* inner loop of the two-level pairs of at most 4 words per codeword (the
+ * weights are the same either way): 1 (default) = the part of a chunk that
+ * every lane subset covers, in whole blocks of 32 right entries, on the
+ * int8 matrix cores (wt(l ^ r) = wt(l) + sum_k r_k (1 - 2 l_k), one
+ * 32 x 32 x 32 product per word); 0 = XOR and popcount on the vector ALUs
+ * throughout.  VERIFY runs always use the vector ALUs. */
+#define MINDIST_OPT_MFMA             19
 
 typedef struct mindist_ctx mindist_ctx;
 

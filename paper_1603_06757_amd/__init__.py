@@ -28,7 +28,7 @@ OPT = {"term": 1, "midpair_exit": 2, "partial": 3, "verify": 4, "stream": 5,
        "deadline_ms": 6, "tile_t": 7, "blocks_per_cu": 8, "profile": 9,
        "cancel_after_chunks": 10, "table_mib": 11, "lane_items": 12,
        "left_tables": 13, "chunk_order": 14, "counters": 15, "min_items": 16, "speculate": 17,
-       "inject_u": 18}
+       "inject_u": 18, "mfma": 19}
 
 MAX_WORDS = 8
 

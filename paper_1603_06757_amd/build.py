@@ -22,8 +22,11 @@ SOURCES = ["mindist_kernels.hip", "mindist_batch.hip", "mindist_walk.hip", "mind
            "mindist_pool.cpp", "mindist_batch.cpp", "mindist_server.cpp", "mindist_noalloc.hip"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.
+# Matrix-core results go to VGPRs, where the minima read them, instead of
+# AGPRs (which would add one v_accvgpr_read per result).
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-mllvm", "-amdgpu-mfma-vgpr-form",
              "-Wno-unused-command-line-argument"]
 
 

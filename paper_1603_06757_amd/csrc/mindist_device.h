@@ -2,8 +2,10 @@
 // per-chunk work of one pair (left subsets per lane, right sums by scalar
 // loads, one XOR + popcount per carried word) and the witness search.
 //
-// Per codeword the hot loop issues D x v_xor_b32 (lane row sum ^ scalar
-// right sum), D x v_bcnt_u32_b32 (accumulating popcount) and one v_min_u32.
+// Per codeword the vector-ALU loop issues D x v_xor_b32 (lane row sum ^
+// scalar right sum), D x v_bcnt_u32_b32 (accumulating popcount) and half a
+// v_min3_u32.  Up to 4 words the part of a chunk every lane subset covers
+// runs instead as int8 products on the matrix cores (run_range_mfma).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -190,6 +192,111 @@ __device__ __forceinline__ void run_range(const uint32_t *tab, uint32_t i0, uint
 }
 
 
+// ---- the same minimum on the int8 matrix cores --------------------------
+// For bit vectors l and r, wt(l ^ r) = wt(l) + sum_k r_k (1 - 2 l_k): the
+// weight of every (left, right) combination is wt(l) plus an integer inner
+// product, so a block of 32 right entries against 32 left subsets is one
+// 32 x 32 product over k = 32 D bit positions -- D v_mfma_i32_32x32x32_i8,
+// right bits as 0/1 bytes (rows), left bits as +1/-1 bytes (columns).
+// Operand layout of that instruction: lane i + 32h holds k = 16h .. 16h+15
+// of row (A) or column (B) i, one byte each, in both operands; result value
+// r of lane l is row 8(r/4) + 4(l/32) + r%4 of column l%32.  Word d of a
+// sum supplies k = 32d .. 32d+31, so a lane takes bits 16h .. 16h+15 of
+// each word.  Exact: |inner product| <= 32 D.
+typedef int mf_v4i __attribute__((ext_vector_type(4)));
+typedef int mf_v16i __attribute__((ext_vector_type(16)));
+
+// bits 4c .. 4c+3 of x as bytes 0/1 (bit 4c+p -> byte p)
+__device__ __forceinline__ uint32_t bit_bytes4(uint32_t x, int c) {
+    return __umul24((x >> (4 * c)) & 0xFu, 0x00204081u) & 0x01010101u;
+}
+// the 16 low bits of x as 16 bytes 0/1
+__device__ __forceinline__ mf_v4i bits01(uint32_t x) {
+    return mf_v4i{(int)bit_bytes4(x, 0), (int)bit_bytes4(x, 1), (int)bit_bytes4(x, 2), (int)bit_bytes4(x, 3)};
+}
+// the 16 low bits of x as 16 bytes +1 (clear) / -1 (set)
+__device__ __forceinline__ mf_v4i bits_pm(uint32_t x) {
+    mf_v4i v;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const uint32_t b = bit_bytes4(x, c);
+        v[c] = (int)(((b << 8) - b) | 0x01010101u);   // 0xff per set bit, then 0x01 on every byte
+    }
+    return v;
+}
+
+// Right entries [i0, i0 + 32 nb) against the wave's 64 B left subsets (item t
+// of lane u: L[t] of lane u), all of them in range: m[t] = min(m[t], least
+// weight of item t).  Column tile q holds items t = q/2 of lanes
+// 32(q%2) .. 32(q%2)+31.
+template <int D, int B>
+__device__ __forceinline__ void run_range_mfma(const uint32_t *tab, uint32_t i0, uint32_t nb,
+                                               const uint32_t (&L)[B][D], uint32_t (&m)[B]) {
+    constexpr int DP = dp_of(D);
+    constexpr int Q = 2 * B;
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5;
+    const uint32_t sh = 16u * (uint32_t)h;
+    mf_v4i lb[Q][D];
+#pragma unroll
+    for (int t = 0; t < B; ++t)
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const uint32_t own = L[t][d];
+            const uint32_t oth = (uint32_t)__shfl_xor((int)own, 32);
+            lb[2 * t][d] = bits_pm((h ? oth : own) >> sh);       // column tile 2t: lanes 0..31's items
+            lb[2 * t + 1][d] = bits_pm((h ? own : oth) >> sh);   // tile 2t+1: lanes 32..63's
+        }
+    int32_t rmin[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) rmin[q] = 0x7fffffff;
+    // this lane's row of every block: entry i0 + 32b + lane%32.  The next
+    // block's words are requested before the current block's products and
+    // turned into bytes after them; the minima of tile q are taken while the
+    // products of tile q+1 run.
+    const uint32_t *rp = tab + (size_t)(i0 + (uint32_t)(lane & 31)) * DP;
+    uint32_t nxt[D];
+    mf_v4i ra[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) nxt[d] = rp[d];
+#pragma unroll
+    for (int d = 0; d < D; ++d) ra[d] = bits01(nxt[d] >> sh);
+    for (uint32_t b = 0; b < nb; ++b) {
+        const uint32_t *np = rp + (size_t)(b + 1 < nb ? b + 1 : b) * 32 * DP;
+#pragma unroll
+        for (int d = 0; d < D; ++d) nxt[d] = np[d];
+        mf_v16i prev = {0};
+#pragma unroll
+        for (int d = 0; d < D; ++d) prev = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[0][d], prev, 0, 0, 0);
+#pragma unroll
+        for (int q = 1; q <= Q; ++q) {
+            mf_v16i acc = {0};
+            if (q < Q) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[q][d], acc, 0, 0, 0);
+            }
+            int32_t v = rmin[q - 1];
+#pragma unroll
+            for (int r = 0; r < 16; r += 2) v = min(min(v, prev[r]), prev[r + 1]);
+            rmin[q - 1] = v;
+            prev = acc;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) ra[d] = bits01(nxt[d] >> sh);
+    }
+    // column j of tile 2t+h is item t of lane 32h + j: this lane's own item;
+    // its other 16 rows per block sit in lane ^ 32
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+        const int32_t mine = h ? rmin[2 * t + 1] : rmin[2 * t];
+        const int32_t theirs = __shfl_xor(h ? rmin[2 * t] : rmin[2 * t + 1], 32);
+        uint32_t wl = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) wl += __builtin_popcount(L[t][d]);
+        m[t] = min(m[t], (uint32_t)((int32_t)wl + min(mine, theirs)));
+    }
+}
+
 // Where the left and right sums of one pair come from.  b is the size of the
 // (outer) right subsets; b2 > 0 selects the three-level split with inner
 // subsets of size b2 from table2.
@@ -223,8 +330,9 @@ struct ChunkGeo {
 // the last valid one) against right entries [i_begin, i_end).  Returns the
 // lane's least weight (without the identity offset), the number of
 // combinations it evaluated and (VERIFY) their weight sum; L and nr stay
-// valid for a witness search.
-template <int D, int B, bool VERIFY>
+// valid for a witness search.  MF (D <= 4, not with VERIFY): the range every
+// item covers runs on the matrix cores, in whole blocks of 32 entries.
+template <int D, int B, bool VERIFY, bool MF = false>
 __device__ __forceinline__ void run_chunk(const ItemSrc &s, ChunkGeo &g, uint32_t (&L)[B][D],
                                           uint32_t (&nr)[B], uint32_t &lmin, uint64_t &cnt,
                                           uint32_t &ws) {
@@ -268,7 +376,15 @@ __device__ __forceinline__ void run_chunk(const ItemSrc &s, ChunkGeo &g, uint32_
         vm[t] = (tile0 + (uint64_t)t * 64 < s.n_items) ? kInf : 0u;
     }
     ws = 0;
-    run_range<D, B, false, VERIFY>(s.table, g.i_begin, fast_end, L, nr, vm, m, ws);
+    uint32_t i_mid = g.i_begin;
+    if constexpr (MF) {
+        // whole 32-entry blocks of the range every item covers on the matrix
+        // cores, the rest on the VALU
+        const uint32_t nb = (fast_end - g.i_begin) / 32;
+        if (nb) run_range_mfma<D, B>(s.table, g.i_begin, nb, L, m);
+        i_mid = g.i_begin + 32 * nb;
+    }
+    run_range<D, B, false, VERIFY>(s.table, i_mid, fast_end, L, nr, vm, m, ws);
     run_range<D, B, true, VERIFY>(s.table, fast_end, g.i_end, L, nr, vm, m, ws);
     lmin = kInf;
     cnt = 0;

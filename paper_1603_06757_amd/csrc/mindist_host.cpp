@@ -75,11 +75,12 @@ struct mindist_ctx {
     int64_t deadline_ms = 0;
     uint64_t cancel_after = 0;
     uint32_t tile_t = 0;       // 0: chosen per pair
-    int blocks_per_cu = 4;
+    int blocks_per_cu = 0;     // 0: blocks_per_cu_for's default
     int items = 4;             // lane items per chunk (kernel template B)
     int order = 0;             // chunk order: 0 left-tile-major, 1 right-tile-major
     int counters = kCounters;  // chunk dispensers (1 or kCounters)
     int left_tables = 1;       // read left subsets from saved tables when they fit
+    int mfma = 1;              // full right blocks of D <= 4 pairs on the int8 matrix cores
     uint64_t table_cap = kTableCapDefault;
     uint64_t min_items = 0;    // left subsets a pair's split should give (0 = balanced split)
     uint32_t inject_u = 0;             // testing: initial least weight on the device (0 = off)
@@ -387,6 +388,7 @@ extern "C" int mindist_set_option(mindist_ctx *c, int key, int64_t v) {
             if (v < 0 || v > (1 << 20)) return fail(MINDIST_E_ARG, "tile_t out of range");
             c->tile_t = (uint32_t)v; break;
         case MINDIST_OPT_LEFT_TABLES: c->left_tables = v ? 1 : 0; break;
+        case MINDIST_OPT_MFMA: c->mfma = v ? 1 : 0; break;
         case MINDIST_OPT_CHUNK_ORDER: c->order = v ? 1 : 0; break;
         case MINDIST_OPT_SPECULATE:
             if (v < 0) return fail(MINDIST_E_ARG, "speculate must be >= 0");
@@ -401,7 +403,7 @@ extern "C" int mindist_set_option(mindist_ctx *c, int key, int64_t v) {
             if (v != 1 && v != kCounters) return fail(MINDIST_E_ARG, "counters must be 1 or 8");
             c->counters = (int)v; break;
         case MINDIST_OPT_BLOCKS_PER_CU:
-            if (v < 1 || v > 64) return fail(MINDIST_E_ARG, "blocks_per_cu out of range");
+            if (v < 0 || v > 64) return fail(MINDIST_E_ARG, "blocks_per_cu out of range");
             c->blocks_per_cu = (int)v; break;
         case MINDIST_OPT_PROFILE: c->profile = v ? 1 : 0; break;
         case MINDIST_OPT_LANE_ITEMS:
@@ -439,6 +441,22 @@ extern "C" int mindist_info(const mindist_ctx *c, int *m_full, int *k_partial, i
 // one pair of Algorithm 1 on the device
 namespace {
 
+constexpr int kDefaultBlocksPerCu = 4;
+
+// Resident workgroups per CU the enumeration launches of set j's pairs are
+// sized for: the option when set; else 4, or, for the matrix-core kernel
+// (its products and operands hold up to 216 VGPRs), as many as its
+// registers let one CU hold, at most 4.
+int blocks_per_cu_for(const mindist_ctx *c, int j) {
+    if (c->blocks_per_cu) return c->blocks_per_cu;
+    const int D = c->gd[j].D;
+    if (c->mfma && !c->verify && D <= kMfmaMaxD) {
+        const int n = enum_mfma_resident_blocks(D, c->items);
+        if (n >= 1) return std::min(n, kDefaultBlocksPerCu);
+    }
+    return kDefaultBlocksPerCu;
+}
+
 
 // Chunks of a pair.  Left tiles are runs of 64*items consecutive left
 // subsets (colex order); a left tile whose first subset has largest element
@@ -468,7 +486,7 @@ PairPlan plan_pair(const mindist_ctx *c, int j, int w, GroupEntry *groups,
         // (fewer chunk set-ups) that still leaves every wave max(2, D-1)
         // chunks, so the last chunks leave little idle time (a chunk takes
         // longer as D grows).  Measured per pair on D = 3 and D = 7 codes.
-        const uint64_t waves = (uint64_t)c->cus * c->blocks_per_cu * 4;
+        const uint64_t waves = (uint64_t)c->cus * blocks_per_cu_for(c, j) * 4;
         // left tiles and right entries of each group, then chunks per T
         std::vector<std::pair<uint64_t, uint64_t>> grp;
         {
@@ -584,7 +602,7 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
     };
     // per-wave totals: one entry per wave of the widest launch
     {
-        const uint64_t max_waves = (uint64_t)c->cus * c->blocks_per_cu * 4;
+        const uint64_t max_waves = (uint64_t)c->cus * std::max(kDefaultBlocksPerCu, c->blocks_per_cu) * 4;
         if (max_waves > c->parts_cap && c->noalloc)
             return fail(MINDIST_E_LIMIT, "more resident waves than the fixed region holds");
         if (max_waves > c->parts_cap) {
@@ -715,9 +733,9 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
 
     // A pair ready to run as pair index idx with bound L_prev.
     struct Flight { Prep q; PairPos pos; int idx = 0; int L_prev = 0; int blocks = 0; };
-    auto blocks_of = [&](const PairPlan &pp) {
-        const uint64_t want = ceil_div(pp.total_chunks, 4);
-        return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->cus * c->blocks_per_cu));
+    auto blocks_of = [&](const Prep &q) {
+        const uint64_t want = ceil_div(q.pp.total_chunks, 4);
+        return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->cus * blocks_per_cu_for(c, q.j)));
     };
     // the plan of every pair launched in this run (a witness may come from a
     // pair launched but not visited, in a launch shared with visited ones)
@@ -773,7 +791,7 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
         const int idx0 = grp[0].idx;
         if (c->profile && hipEventRecord(c->pair_ev[2 * idx0], c->stream) != hipSuccess)
             return fail(MINDIST_E_HIP, "event record failed");
-        if (launch_enum_pair(ga, c->gd[grp[0].q.j].D, c->items, c->verify, c->stream))
+        if (launch_enum_pair(ga, c->gd[grp[0].q.j].D, c->items, c->verify, c->mfma, c->stream))
             return fail(MINDIST_E_HIP, "enumeration kernel launch failed");
         if (c->profile && hipEventRecord(c->pair_ev[2 * idx0 + 1], c->stream) != hipSuccess)
             return fail(MINDIST_E_HIP, "event record failed");
@@ -802,7 +820,6 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
     PairMail last_mail{};
     const bool free_exit = midpair && !c->deadline_ms;
     const bool grouping = free_exit && c->speculate && !c->order && !c->cancel_after;
-    const int resident_blocks = c->cus * c->blocks_per_cu;
     constexpr uint64_t kAheadWork = 1ull << 30;   // queued combinations that stop a second launch ahead
     // Stage pair npos as index next_idx with bound L0, extend the launch
     // with the following short pairs when allowed, launch, and queue them.
@@ -815,13 +832,13 @@ static int run_impl(mindist_ctx *c, mindist_result *out) {
             f.pos = npos;
             int e = plan(f.q, npos.j, npos.h);
             if (e) return e;
-            f.blocks = blocks_of(f.q.pp);
+            f.blocks = blocks_of(f.q);
             if (!grp.empty()) {
                 // joins the launch only if it is short and of the same width
                 const bool ok = f.q.pp.b2 == 0 && grp[0].q.pp.b2 == 0 &&
                                 c->gd[npos.j].D == c->gd[grp[0].q.j].D &&
                                 (uint64_t)f.q.pp.total_chunks <= 4ull * (uint64_t)f.blocks &&
-                                blocks + f.blocks <= resident_blocks;
+                                blocks + f.blocks <= c->cus * blocks_per_cu_for(c, grp[0].q.j);
                 if (!ok) break;
             }
             e = stage(f.q);

@@ -36,6 +36,7 @@
 namespace md {
 
 constexpr int kBinomT = 65;          // binomial table: t in [0, 64]
+constexpr int kMfmaMaxD = 4;         // words per codeword the matrix-core inner loop takes
 constexpr int kBinomX = 513;         // x in [0, 512]
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 
@@ -196,7 +197,12 @@ int launch_init_state(DevState *st, int max_pairs, void *stream);
 int launch_build_table(const TableArgs &ta, int D, void *stream);
 // items: lane items per chunk (2 or 4)
 // all pairs of one launch share D and the lane items
-int launch_enum_pair(const GroupArgs &ga, int D, int items, int verify, void *stream);
+// mfma: the two-level pairs of at most kMfmaMaxD words run their full
+// 32-entry blocks on the int8 matrix cores (ignored with verify)
+int launch_enum_pair(const GroupArgs &ga, int D, int items, int verify, int mfma, void *stream);
+// workgroups of 256 threads of the matrix-core enumeration kernel (D words,
+// items lane items) one CU holds at once; 0 if the runtime cannot tell
+int enum_mfma_resident_blocks(int D, int items);
 // one block: reduce the waves' totals of every pair of the launch, read the
 // run state and publish them to the pairs' mailboxes (mail[pair %
 // kMailRing]), then record U_found as the next launch's U_base (launched

@@ -6,6 +6,7 @@
 // Rows and tables are a few KB to a few MB; nothing per codeword touches HBM.
 #include <hip/hip_runtime.h>
 #include <algorithm>
+#include <atomic>
 
 #include "mindist_device.h"
 
@@ -13,7 +14,7 @@ namespace md {
 
 static_assert(sizeof(GroupArgs) <= 4096, "launch arguments exceed the kernel argument space");
 
-template <int D, int B, bool VERIFY>
+template <int D, int B, bool VERIFY, bool MF>
 __global__ __launch_bounds__(256) void enum_pair_kernel(GroupArgs ga) {
     const uint64_t t_begin = wall_clock64();
     const int lane = threadIdx.x & 63;
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(GroupArgs ga) {
         uint32_t L[B][D], nr[B], lmin, ws;
         uint64_t cnt;
         if (p.b2) run_chunk3<D, B, VERIFY>(src, g, L, nr, lmin, cnt, ws);
-        else run_chunk<D, B, VERIFY>(src, g, L, nr, lmin, cnt, ws);
+        else run_chunk<D, B, VERIFY, MF>(src, g, L, nr, lmin, cnt, ws);
         run_min = min(run_min, lmin);
         run_cnt += cnt;
         if (VERIFY) run_ws += ws;
@@ -471,17 +472,54 @@ int launch_build_table(const TableArgs &ta, int D, void *stream) {
 }
 
 template <int D, int B>
-static void enum_launch_b(const GroupArgs &ga, int verify, int blocks, hipStream_t s) {
+static void enum_launch_b(const GroupArgs &ga, int verify, int mfma, int blocks, hipStream_t s) {
     if (verify)
-        hipLaunchKernelGGL((enum_pair_kernel<D, B, true>), dim3(blocks), dim3(256), 0, s, ga);
-    else
-        hipLaunchKernelGGL((enum_pair_kernel<D, B, false>), dim3(blocks), dim3(256), 0, s, ga);
+        hipLaunchKernelGGL((enum_pair_kernel<D, B, true, false>), dim3(blocks), dim3(256), 0, s, ga);
+    else if constexpr (D <= kMfmaMaxD) {
+        if (mfma)
+            hipLaunchKernelGGL((enum_pair_kernel<D, B, false, true>), dim3(blocks), dim3(256), 0, s, ga);
+        else
+            hipLaunchKernelGGL((enum_pair_kernel<D, B, false, false>), dim3(blocks), dim3(256), 0, s, ga);
+    } else {
+        hipLaunchKernelGGL((enum_pair_kernel<D, B, false, false>), dim3(blocks), dim3(256), 0, s, ga);
+    }
 }
 
 template <int D>
-static void enum_launch(const GroupArgs &ga, int items, int verify, int blocks, hipStream_t s) {
-    if (items == 4) enum_launch_b<D, 4>(ga, verify, blocks, s);
-    else enum_launch_b<D, 2>(ga, verify, blocks, s);
+static void enum_launch(const GroupArgs &ga, int items, int verify, int mfma, int blocks, hipStream_t s) {
+    if (items == 4) enum_launch_b<D, 4>(ga, verify, mfma, blocks, s);
+    else enum_launch_b<D, 2>(ga, verify, mfma, blocks, s);
+}
+
+template <int D, int B>
+static int mfma_resident() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, enum_pair_kernel<D, B, false, true>, 256, 0) !=
+        hipSuccess)
+        return 0;
+    return n;
+}
+
+int enum_mfma_resident_blocks(int D, int items) {
+    // the answer depends only on the kernel's resources: asked once per shape
+    static std::atomic<int> cache[kMfmaMaxD + 1][2];
+    if (D < 1 || D > kMfmaMaxD || (items != 2 && items != 4)) return 0;
+    std::atomic<int> &slot = cache[D][items == 4];
+    int n = slot.load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    switch (D * 8 + items) {
+        case 1 * 8 + 2: n = mfma_resident<1, 2>(); break;
+        case 1 * 8 + 4: n = mfma_resident<1, 4>(); break;
+        case 2 * 8 + 2: n = mfma_resident<2, 2>(); break;
+        case 2 * 8 + 4: n = mfma_resident<2, 4>(); break;
+        case 3 * 8 + 2: n = mfma_resident<3, 2>(); break;
+        case 3 * 8 + 4: n = mfma_resident<3, 4>(); break;
+        case 4 * 8 + 2: n = mfma_resident<4, 2>(); break;
+        case 4 * 8 + 4: n = mfma_resident<4, 4>(); break;
+        default: break;
+    }
+    if (n > 0) slot.store(n, std::memory_order_relaxed);
+    return n;
 }
 
 int launch_publish_pair(const GroupArgs &ga, PairMail *mail, void *stream) {
@@ -489,7 +527,7 @@ int launch_publish_pair(const GroupArgs &ga, PairMail *mail, void *stream) {
     return check(hipGetLastError());
 }
 
-int launch_enum_pair(const GroupArgs &ga, int D, int items, int verify, void *stream) {
+int launch_enum_pair(const GroupArgs &ga, int D, int items, int verify, int mfma, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     if (ga.n < 1 || ga.n > (uint32_t)kGroupMax || ga.block_start[0] != 0) return -1;
     for (uint32_t g = 0; g < ga.n; ++g)
@@ -498,7 +536,7 @@ int launch_enum_pair(const GroupArgs &ga, int D, int items, int verify, void *st
             return -1;
     const int blocks = (int)ga.block_start[ga.n];
     switch (D) {
-#define MD_CASE(X) case X: enum_launch<X>(ga, items, verify, blocks, s); break;
+#define MD_CASE(X) case X: enum_launch<X>(ga, items, verify, mfma, blocks, s); break;
         MD_CASE(1) MD_CASE(2) MD_CASE(3) MD_CASE(4) MD_CASE(5) MD_CASE(6) MD_CASE(7) MD_CASE(8)
         MD_CASE(9) MD_CASE(10) MD_CASE(11) MD_CASE(12) MD_CASE(13) MD_CASE(14) MD_CASE(15)
         MD_CASE(16)

@@ -309,6 +309,42 @@ def test_chunk_orders_and_dispensers(order, counters, items, left):
         compare_with_trace(res, gold["trace"], gold["counts"], gold["pair_min"], gold["wsum"], w.k)
 
 
+@pytest.mark.parametrize("mfma,items,order,tile_t", [(1, 4, 0, 0), (1, 2, 1, 0), (1, 4, 0, 33),
+                                                    (1, 2, 0, 1024), (1, 4, 1, 100), (0, 4, 0, 0)])
+def test_matrix_core_and_vector_inner_loops(mfma, items, order, tile_t):
+    """Two-level pairs of 1 to 4 words per codeword with the inner loop on the
+    int8 matrix cores (whole 32-entry blocks of the range every lane subset
+    covers; the rest on the vector ALUs) or on the vector ALUs alone: d, every
+    pair minimum, bound and count equal the oracle's.  Tile lengths of 33 and
+    100 leave a ragged block in every chunk; 5 or more words always take the
+    vector ALUs."""
+    for name in ["rand48x24", "rand150x75", "rand255x40"]:
+        gold = json.load(open(os.path.join(GOLDEN, f"{name}.json")))
+        w = WORKLOADS[name]
+        say(name, "mfma", mfma, "items", items, "order", order, "tile", tile_t)
+        res = md.min_distance(w.matrix(), w.n, w.k, verify=0, mfma=mfma, lane_items=items,
+                              chunk_order=order, tile_t=tile_t)
+        compare_with_trace(res, gold["trace"], gold["counts"], gold["pair_min"], None, w.k)
+        check_witness(w.matrix(), w.n, w.k, res)
+    rng = PCG32(1603, 19 + mfma)
+    for words in (1, 2, 3, 4):
+        done = 0
+        while done < 4:
+            k = rng.uniform_int(6, 40)
+            n = k + rng.uniform_int(32 * (words - 1) + 1, 32 * words)
+            if estimated_work(n, k) > 3e7:
+                continue
+            G = draw_matrix(rng, n, k)
+            try:
+                oracle.partition(G, n, k)
+            except oracle.OracleError:
+                continue
+            say("random", words, "words", n, k, "mfma", mfma)
+            run_and_compare(G, n, k, verify=False, mfma=mfma, lane_items=items, chunk_order=order,
+                            tile_t=tile_t)
+            done += 1
+
+
 @pytest.mark.parametrize("table_mib", [1, 2])
 def test_three_level_split_small_tables(table_mib):
     """Small saved tables force the three-level split (lane subset, outer

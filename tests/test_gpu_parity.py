@@ -413,6 +413,9 @@ def test_cancel_and_deadline():
         r = m.run()                           # the context is reusable afterwards
         assert r["d"] == gold["d"]
         compare_with_trace(r, gold["trace"], gold["counts"], gold["pair_min"], None, w.k)
+    # the deadline on a code whose run takes about ten times the limit
+    # ([255,40], 3e10 codewords of 7 words)
+    w = WORKLOADS["rand255x40"]
     say("deadline")
     with md.MinDist(w.matrix(), w.n, w.k, deadline_ms=1) as m:
         with pytest.raises(md.MindistError) as e:
@@ -422,7 +425,7 @@ def test_cancel_and_deadline():
         # next runs on the context (pairs launched ahead and shared launches
         # reusing its mailboxes) give the full result
         m.set_option("deadline_ms", 0)
-        gold = json.load(open(os.path.join(GOLDEN, "rand150x75.json")))
+        gold = json.load(open(os.path.join(GOLDEN, "rand255x40.json")))
         for _ in range(2):
             r = m.run()
             assert r["d"] == gold["d"]

@@ -356,7 +356,8 @@ typedef struct mindist_batch_opts {
     int32_t tile_min;         /* right-tile length bounds (0 = 2048 / 4096; the maximum is raised
                                  to the minimum if below it) */
     int32_t tile_max;
-    int32_t blocks_per_cu;    /* resident workgroups per CU (0 = 4) */
+    int32_t blocks_per_cu;    /* resident workgroups per CU (0 = 4; capped at what the
+                                 persistent kernel's registers allow: 2) */
     int32_t use_graph;        /* 1 = run as one captured hipGraph (default), 0 = plain launch */
     int32_t table_kib;        /* cap on one saved right-sum table in KiB (0 = 65536) */
     int32_t jobs_per_code;    /* job-arena sizing: average jobs per code (0 = 96) */
@@ -438,8 +439,10 @@ typedef struct mindist_server mindist_server;
 typedef struct mindist_server_opts {
     int32_t max_active;       /* codes running at once: engine 0, worker threads (0 = 8);
                                  engine 1, code slots resident on the device (0 = 256) */
-    int32_t blocks_per_cu;    /* resident workgroups per CU (0 = 4; engine 1 routing codes to
-                                 the single path: 2) */
+    int32_t blocks_per_cu;    /* engine 1: resident workgroups per CU of the persistent kernel
+                                 (0 = as many as its registers allow, 2; 1 while it routes
+                                 codes to the single path, leaving half of each SIMD's
+                                 registers to their kernels) */
     int64_t device_bytes;     /* device memory for the codes in flight: a code is admitted
                                  only when its share fits beside theirs (0 = 8 GiB).  Engine
                                  0: estimated rows, saved right and left tables up to half

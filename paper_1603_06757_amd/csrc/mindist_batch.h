@@ -23,10 +23,11 @@ constexpr int kBatchMaxSets = 32;     // information sets per code
 constexpr int kBatchMaxB = 6;         // right tables b = 0..6 per set
 constexpr int kBatchMaxPairs = 256;   // jobs per code (table job + pairs)
 constexpr int kBatchMaxD = 8;         // 32-bit words carried per row (n <= 256)
-// left subsets per lane: 4 up to 4 words per codeword (each scalar table
-// line then serves 256 codewords of the wave), 2 above (the 128-register
-// budget of the persistent kernel holds 4 x D words of left sums only up to
-// D = 4)
+// left subsets per lane: 4 up to 4 words per codeword (the matrix-core
+// inner loop then multiplies each 32-entry block of right sums by 8 column
+// tiles; on the vector ALUs each scalar table line serves 256 codewords of
+// the wave), 2 above (the vector-ALU loop holds 4 x D words of left sums
+// without spilling only up to D = 4)
 constexpr int kBatchItemsMaxD4 = 4;
 constexpr int kBatchItemsWide = 2;
 MD_HD constexpr int batch_items(int D) { return D <= 4 ? kBatchItemsMaxD4 : kBatchItemsWide; }
@@ -37,7 +38,7 @@ constexpr int kTableChunkMin = 256, kTableChunksWanted = 16;
 // chunk groups of the pair it works on, and the block's slice of the
 // binomial table, C(x, t) for x < 256 and t <= 8, from which lanes unrank
 // their left subsets (subsets of up to 8 rows): 4 waves x 4 KB + 18 KB per
-// block, 4 blocks in 137.5 KB
+// block, 34 KB (the kernel's registers hold 2 blocks per CU)
 constexpr int kRowsLds = 1024;
 constexpr int kLdsBinomX = 256, kLdsBinomT = 9;
 // a saved table of C(k,b) entries is built only if C(k,b) <= C(k,top) /

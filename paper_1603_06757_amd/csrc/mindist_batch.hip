@@ -607,7 +607,7 @@ __device__ __forceinline__ void pair_chunk(const BatchArgs &A, const uint64_t *l
     uint32_t L[BI][D], nr[BI], lmin, ws;
     uint64_t cnt;
     if (v.b2) run_chunk3<D, BI, false>(src, g, L, nr, lmin, cnt, ws);
-    else run_chunk<D, BI, false>(src, g, L, nr, lmin, cnt, ws);
+    else run_chunk<D, BI, false, (D <= kMfmaMaxD)>(src, g, L, nr, lmin, cnt, ws);
     const uint32_t wmin = uni32(wave_min_u32(lmin));
     exec += uni64(wave_sum_u64(cnt));
     if (wmin < wmin_out) wmin_out = wmin;
@@ -812,9 +812,10 @@ __device__ __forceinline__ void idle_backoff(uint32_t &idle) {
 
 }  // namespace
 
-// At most 128 VGPRs (4 waves per SIMD, 4 blocks of 256 per CU): the few
-// values this spills live outside the enumeration loops.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void persistent_batch_kernel(BatchArgs A) {
+// At most 256 VGPRs (2 waves per SIMD, 2 blocks of 256 per CU): the
+// matrix-core operands and products of pairs of up to 4 words take about
+// 200 of them; at 128 the enumeration loops themselves would spill.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void persistent_batch_kernel(BatchArgs A) {
     // one slice per wave for the rows of the set whose tables it builds
     __shared__ uint32_t s_rows[4 * kRowsLds];
     uint32_t *const my_rows = s_rows + (threadIdx.x >> 6) * kRowsLds;

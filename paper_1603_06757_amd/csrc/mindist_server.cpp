@@ -322,9 +322,10 @@ int upload_fresh(mindist_server *S, const uint32_t tile_max) {
 void manager(mindist_server *S) {
     (void)hipSetDevice(S->device);
     const uint32_t tile_min = 2048, tile_max = 4096;   // as the batch defaults
-    // with codes routed to single-path workers, 2 blocks per CU leave room
-    // for their kernels beside the persistent one
-    const int bpc_req = S->o.blocks_per_cu > 0 ? S->o.blocks_per_cu : S->route_min > 0 ? 2 : 4;
+    // with codes routed to single-path workers, 1 block per CU (half of each
+    // SIMD's registers) leaves room for their kernels beside the persistent
+    // one; otherwise as many as fit (2)
+    const int bpc_req = S->o.blocks_per_cu > 0 ? S->o.blocks_per_cu : S->route_min > 0 ? 1 : 4;
     const int resident_bpc = persistent_resident_blocks_per_cu();
     const int blocks = S->cus * (resident_bpc > 0 && bpc_req > resident_bpc ? resident_bpc : bpc_req);
     const double epoch_min = (S->o.epoch_min_ms > 0 ? S->o.epoch_min_ms : 0.5) * 1e-3;

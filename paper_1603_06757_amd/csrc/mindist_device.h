@@ -252,8 +252,9 @@ __device__ __forceinline__ void run_range_mfma(const uint32_t *tab, uint32_t i0,
     for (int q = 0; q < Q; ++q) rmin[q] = 0x7fffffff;
     // this lane's row of every block: entry i0 + 32b + lane%32.  The next
     // block's words are requested before the current block's products and
-    // turned into bytes after them; the minima of tile q are taken while the
-    // products of tile q+1 run.
+    // turned into bytes after them.  Tiles go in pairs, the two products
+    // interleaved word by word (two independent chains); the minima of one
+    // pair are taken while the products of the next run.
     const uint32_t *rp = tab + (size_t)(i0 + (uint32_t)(lane & 31)) * DP;
     uint32_t nxt[D];
     mf_v4i ra[D];
@@ -265,21 +266,32 @@ __device__ __forceinline__ void run_range_mfma(const uint32_t *tab, uint32_t i0,
         const uint32_t *np = rp + (size_t)(b + 1 < nb ? b + 1 : b) * 32 * DP;
 #pragma unroll
         for (int d = 0; d < D; ++d) nxt[d] = np[d];
-        mf_v16i prev = {0};
+        mf_v16i p0 = {0}, p1 = {0};
 #pragma unroll
-        for (int d = 0; d < D; ++d) prev = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[0][d], prev, 0, 0, 0);
+        for (int d = 0; d < D; ++d) {
+            p0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[0][d], p0, 0, 0, 0);
+            p1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[1][d], p1, 0, 0, 0);
+        }
 #pragma unroll
-        for (int q = 1; q <= Q; ++q) {
-            mf_v16i acc = {0};
+        for (int q = 2; q <= Q; q += 2) {
+            mf_v16i a0 = {0}, a1 = {0};
             if (q < Q) {
 #pragma unroll
-                for (int d = 0; d < D; ++d) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[q][d], acc, 0, 0, 0);
+                for (int d = 0; d < D; ++d) {
+                    a0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[q][d], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[q + 1][d], a1, 0, 0, 0);
+                }
             }
-            int32_t v = rmin[q - 1];
+            int32_t v0 = rmin[q - 2], v1 = rmin[q - 1];
 #pragma unroll
-            for (int r = 0; r < 16; r += 2) v = min(min(v, prev[r]), prev[r + 1]);
-            rmin[q - 1] = v;
-            prev = acc;
+            for (int r = 0; r < 16; r += 2) {
+                v0 = min(min(v0, p0[r]), p0[r + 1]);
+                v1 = min(min(v1, p1[r]), p1[r + 1]);
+            }
+            rmin[q - 2] = v0;
+            rmin[q - 1] = v1;
+            p0 = a0;
+            p1 = a1;
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) ra[d] = bits01(nxt[d] >> sh);

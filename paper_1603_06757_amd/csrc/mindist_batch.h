@@ -30,6 +30,10 @@ constexpr int kBatchMaxD = 8;         // 32-bit words carried per row (n <= 256)
 // without spilling only up to D = 4)
 constexpr int kBatchItemsMaxD4 = 4;
 constexpr int kBatchItemsWide = 2;
+// product chains per wave of the matrix-core loop (pairs of up to 4 words):
+// two would keep more of the loop's values in scratch beside the
+// scheduler's state
+constexpr int kBatchMfmaChains = 1;
 MD_HD constexpr int batch_items(int D) { return D <= 4 ? kBatchItemsMaxD4 : kBatchItemsWide; }
 constexpr int kTableChunk = 4096;     // table entries per table-job chunk (at most)
 constexpr int kTableChunkMin = 256, kTableChunksWanted = 16;

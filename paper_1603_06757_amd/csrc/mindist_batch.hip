@@ -607,7 +607,7 @@ __device__ __forceinline__ void pair_chunk(const BatchArgs &A, const uint64_t *l
     uint32_t L[BI][D], nr[BI], lmin, ws;
     uint64_t cnt;
     if (v.b2) run_chunk3<D, BI, false>(src, g, L, nr, lmin, cnt, ws);
-    else run_chunk<D, BI, false, (D <= kMfmaMaxD)>(src, g, L, nr, lmin, cnt, ws);
+    else run_chunk<D, BI, false, (D <= kMfmaMaxD) ? kBatchMfmaChains : 0>(src, g, L, nr, lmin, cnt, ws);
     const uint32_t wmin = uni32(wave_min_u32(lmin));
     exec += uni64(wave_sum_u64(cnt));
     if (wmin < wmin_out) wmin_out = wmin;

@@ -228,8 +228,9 @@ __device__ __forceinline__ mf_v4i bits_pm(uint32_t x) {
 // Right entries [i0, i0 + 32 nb) against the wave's 64 B left subsets (item t
 // of lane u: L[t] of lane u), all of them in range: m[t] = min(m[t], least
 // weight of item t).  Column tile q holds items t = q/2 of lanes
-// 32(q%2) .. 32(q%2)+31.
-template <int D, int B>
+// 32(q%2) .. 32(q%2)+31.  CH: product chains in flight per wave, 1 or 2
+// (tiles in pairs; faster where the registers allow it).
+template <int D, int B, int CH>
 __device__ __forceinline__ void run_range_mfma(const uint32_t *tab, uint32_t i0, uint32_t nb,
                                                const uint32_t (&L)[B][D], uint32_t (&m)[B]) {
     constexpr int DP = dp_of(D);
@@ -252,9 +253,9 @@ __device__ __forceinline__ void run_range_mfma(const uint32_t *tab, uint32_t i0,
     for (int q = 0; q < Q; ++q) rmin[q] = 0x7fffffff;
     // this lane's row of every block: entry i0 + 32b + lane%32.  The next
     // block's words are requested before the current block's products and
-    // turned into bytes after them.  Tiles go in pairs, the two products
-    // interleaved word by word (two independent chains); the minima of one
-    // pair are taken while the products of the next run.
+    // turned into bytes after them.  With CH = 2 tiles go in pairs, the two
+    // products interleaved word by word (two independent chains); the minima
+    // of one pair (or tile) are taken while the products of the next run.
     const uint32_t *rp = tab + (size_t)(i0 + (uint32_t)(lane & 31)) * DP;
     uint32_t nxt[D];
     mf_v4i ra[D];
@@ -266,32 +267,51 @@ __device__ __forceinline__ void run_range_mfma(const uint32_t *tab, uint32_t i0,
         const uint32_t *np = rp + (size_t)(b + 1 < nb ? b + 1 : b) * 32 * DP;
 #pragma unroll
         for (int d = 0; d < D; ++d) nxt[d] = np[d];
-        mf_v16i p0 = {0}, p1 = {0};
+        if constexpr (CH == 2) {
+            mf_v16i p0 = {0}, p1 = {0};
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            p0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[0][d], p0, 0, 0, 0);
-            p1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[1][d], p1, 0, 0, 0);
-        }
+            for (int d = 0; d < D; ++d) {
+                p0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[0][d], p0, 0, 0, 0);
+                p1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[1][d], p1, 0, 0, 0);
+            }
 #pragma unroll
-        for (int q = 2; q <= Q; q += 2) {
-            mf_v16i a0 = {0}, a1 = {0};
-            if (q < Q) {
+            for (int q = 2; q <= Q; q += 2) {
+                mf_v16i a0 = {0}, a1 = {0};
+                if (q < Q) {
 #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    a0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[q][d], a0, 0, 0, 0);
-                    a1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[q + 1][d], a1, 0, 0, 0);
+                    for (int d = 0; d < D; ++d) {
+                        a0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[q][d], a0, 0, 0, 0);
+                        a1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[q + 1][d], a1, 0, 0, 0);
+                    }
                 }
-            }
-            int32_t v0 = rmin[q - 2], v1 = rmin[q - 1];
+                int32_t v0 = rmin[q - 2], v1 = rmin[q - 1];
 #pragma unroll
-            for (int r = 0; r < 16; r += 2) {
-                v0 = min(min(v0, p0[r]), p0[r + 1]);
-                v1 = min(min(v1, p1[r]), p1[r + 1]);
+                for (int r = 0; r < 16; r += 2) {
+                    v0 = min(min(v0, p0[r]), p0[r + 1]);
+                    v1 = min(min(v1, p1[r]), p1[r + 1]);
+                }
+                rmin[q - 2] = v0;
+                rmin[q - 1] = v1;
+                p0 = a0;
+                p1 = a1;
             }
-            rmin[q - 2] = v0;
-            rmin[q - 1] = v1;
-            p0 = a0;
-            p1 = a1;
+        } else {
+            mf_v16i prev = {0};
+#pragma unroll
+            for (int d = 0; d < D; ++d) prev = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[0][d], prev, 0, 0, 0);
+#pragma unroll
+            for (int q = 1; q <= Q; ++q) {
+                mf_v16i acc = {0};
+                if (q < Q) {
+#pragma unroll
+                    for (int d = 0; d < D; ++d) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(ra[d], lb[q][d], acc, 0, 0, 0);
+                }
+                int32_t v = rmin[q - 1];
+#pragma unroll
+                for (int r = 0; r < 16; r += 2) v = min(min(v, prev[r]), prev[r + 1]);
+                rmin[q - 1] = v;
+                prev = acc;
+            }
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) ra[d] = bits01(nxt[d] >> sh);
@@ -342,9 +362,10 @@ struct ChunkGeo {
 // the last valid one) against right entries [i_begin, i_end).  Returns the
 // lane's least weight (without the identity offset), the number of
 // combinations it evaluated and (VERIFY) their weight sum; L and nr stay
-// valid for a witness search.  MF (D <= 4, not with VERIFY): the range every
-// item covers runs on the matrix cores, in whole blocks of 32 entries.
-template <int D, int B, bool VERIFY, bool MF = false>
+// valid for a witness search.  MF (D <= 4, not with VERIFY): 0, or the
+// product chains per wave (1 or 2) with which the range every item covers
+// runs on the matrix cores, in whole blocks of 32 entries.
+template <int D, int B, bool VERIFY, int MF = 0>
 __device__ __forceinline__ void run_chunk(const ItemSrc &s, ChunkGeo &g, uint32_t (&L)[B][D],
                                           uint32_t (&nr)[B], uint32_t &lmin, uint64_t &cnt,
                                           uint32_t &ws) {
@@ -389,11 +410,11 @@ __device__ __forceinline__ void run_chunk(const ItemSrc &s, ChunkGeo &g, uint32_
     }
     ws = 0;
     uint32_t i_mid = g.i_begin;
-    if constexpr (MF) {
+    if constexpr (MF > 0) {
         // whole 32-entry blocks of the range every item covers on the matrix
         // cores, the rest on the VALU
         const uint32_t nb = (fast_end - g.i_begin) / 32;
-        if (nb) run_range_mfma<D, B>(s.table, g.i_begin, nb, L, m);
+        if (nb) run_range_mfma<D, B, MF>(s.table, g.i_begin, nb, L, m);
         i_mid = g.i_begin + 32 * nb;
     }
     run_range<D, B, false, VERIFY>(s.table, i_mid, fast_end, L, nr, vm, m, ws);

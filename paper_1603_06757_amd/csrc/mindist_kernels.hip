@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void enum_pair_kernel(GroupArgs ga) {
         uint32_t L[B][D], nr[B], lmin, ws;
         uint64_t cnt;
         if (p.b2) run_chunk3<D, B, VERIFY>(src, g, L, nr, lmin, cnt, ws);
-        else run_chunk<D, B, VERIFY, MF>(src, g, L, nr, lmin, cnt, ws);
+        else run_chunk<D, B, VERIFY, MF ? 2 : 0>(src, g, L, nr, lmin, cnt, ws);
         run_min = min(run_min, lmin);
         run_cnt += cnt;
         if (VERIFY) run_ws += ws;

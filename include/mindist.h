@@ -147,7 +147,9 @@ extern "C" {
  * every lane subset covers, in whole blocks of 32 right entries, on the
  * int8 matrix cores (wt(l ^ r) = wt(l) + sum_k r_k (1 - 2 l_k), one
  * 32 x 32 x 32 product per word); 0 = XOR and popcount on the vector ALUs
- * throughout.  VERIFY runs always use the vector ALUs. */
+ * throughout.  VERIFY runs always use the vector ALUs.  Single-code path
+ * only: the batch and serving kernel always runs such pairs on the matrix
+ * cores. */
 #define MINDIST_OPT_MFMA             19
 
 typedef struct mindist_ctx mindist_ctx;

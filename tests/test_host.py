@@ -339,3 +339,63 @@ def test_pair_records_convert_to_the_same_dicts():
     assert [type(v) for v in got[0].values()] == [type(v) for v in ref[0].values()]
     assert md._pair_dicts(arr, 7, 19) == ref[7:19]
     assert md._pair_dicts(arr, 5, 5) == []
+
+
+def _bit_bytes4(x, c):
+    # the kernel's expansion: bits 4c..4c+3 of x as bytes 0/1 (one 24-bit
+    # multiply spreads a nibble over four bytes, the mask keeps bit 0 of each)
+    return ((((x >> (4 * c)) & 0xF) * 0x00204081) & 0xFFFFFFFF) & 0x01010101
+
+
+def _bytes16(x, pm):
+    """16 low bits of x as 16 int8 values, as the kernel builds an operand:
+    0/1 (pm False) or +1 for a clear bit / -1 for a set bit (pm True)."""
+    out = []
+    for c in range(4):
+        b = _bit_bytes4(x, c)
+        if pm:
+            b = ((((b << 8) - b) & 0xFFFFFFFF) | 0x01010101)
+        out += [((b >> (8 * p)) & 0xFF) for p in range(4)]
+    return np.array(out, dtype=np.uint8).view(np.int8).astype(np.int64)
+
+
+def test_matrix_core_operand_bytes():
+    """Every nibble expands to its bits, one byte each; the +-1 form is 1 - 2 bit."""
+    for x in range(1 << 16):
+        if x % 97 and x not in (0, 0xFFFF):
+            continue
+        bits = np.array([(x >> p) & 1 for p in range(16)], dtype=np.int64)
+        assert (_bytes16(x, False) == bits).all()
+        assert (_bytes16(x, True) == 1 - 2 * bits).all()
+
+
+def test_matrix_core_block_is_the_weights():
+    """One 32 x 32 block as the matrix-core loop computes it -- lane i + 32h
+    holds bits 16h..16h+15 of each word of row (right sum) or column (left
+    sum) i, D products of 32 bytes summed per (row, column), plus wt(l) --
+    equals popcount(l ^ r) for every pair (wt(l ^ r) = wt(l) + sum_k r_k
+    (1 - 2 l_k)).  The lane layout is the one a one-wave probe of
+    v_mfma_i32_32x32x32_i8 showed on the GPU; here it is only taken as given."""
+    rng = np.random.default_rng(1603)
+    for D in (1, 2, 3, 4):
+        for trial in range(3):
+            R = rng.integers(0, 1 << 32, size=(32, D), dtype=np.uint64)
+            Lf = rng.integers(0, 1 << 32, size=(32, D), dtype=np.uint64)
+            if trial == 1:       # the top word partly used, as in n - k = 75
+                R[:, -1] &= 0x7FF
+                Lf[:, -1] &= 0x7FF
+            acc = np.zeros((32, 32), dtype=np.int64)
+            for d in range(D):
+                A = np.zeros((64, 16), dtype=np.int64)
+                Bm = np.zeros((64, 16), dtype=np.int64)
+                for lane in range(64):
+                    i, h = lane % 32, lane // 32
+                    A[lane] = _bytes16(int(R[i, d]) >> (16 * h), False)
+                    Bm[lane] = _bytes16(int(Lf[i, d]) >> (16 * h), True)
+                # D[i][j] = sum_h sum_p A[i + 32h][p] * B[j + 32h][p]
+                acc += A[:32] @ Bm[:32].T + A[32:] @ Bm[32:].T
+            for i in range(32):
+                for j in range(32):
+                    wl = sum(bin(int(Lf[j, d])).count("1") for d in range(D))
+                    want = sum(bin(int(R[i, d]) ^ int(Lf[j, d])).count("1") for d in range(D))
+                    assert wl + acc[i, j] == want
